@@ -1,0 +1,210 @@
+/*
+ * firesim.h -- C ABI of the MI355X (gfx950) batched fire-spread library.
+ *
+ * The library runs the probabilistic cellular-automaton fire-spread model of
+ * JaxWildfire (arXiv 2512.06102, section 3) over a batch of independent
+ * grids ("envs") on one GPU: the stochastic step (Eqs. 1-4 and the
+ * "Stochastic update" paragraph) and a relaxed mean-field step with its
+ * adjoint (the "Deterministic (raw-probabilities) update", Eqs. 5-10) for
+ * gradient-based calibration.
+ *
+ * Conventions
+ *  - Every pointer marked "device" is memory the caller allocated on the
+ *    handle's GPU; the library never frees caller memory.  "host" pointers
+ *    are read before the call returns.
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Calls enqueue work
+ *    on it and return without synchronising, except sim_init, which
+ *    synchronises once at the end (its host inputs are copied in).
+ *  - Return 0 on success, a negative SIM_E* code on failure; no exception
+ *    crosses the ABI.  sim_last_error() gives the message of the last failure
+ *    (per handle; with h == NULL the calling thread's last sim_init failure).
+ *  - Layout: per-cell arrays are packed env after env (env e starts at
+ *    envs[e].offset), each env row-major with H rows of W cells; row 0 is the
+ *    northern edge, so row index grows southward and column index eastward.
+ *  - Cell states are uint8: SIM_UNBURNABLE (no fuel), SIM_FLAMMABLE (the
+ *    paper's "unburned"), SIM_BURNING, SIM_BURNT.
+ *  - All kernels of one handle run on the device that was current at
+ *    sim_init.  Calls on one handle must not overlap (they share its
+ *    internal buffers and its step counter).
+ */
+#ifndef FIRESIM_H
+#define FIRESIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SIM_OK 0
+#define SIM_EINVAL (-1) /* bad argument: sizes, pointers, ranges         */
+#define SIM_ENOMEM (-2) /* device allocation failed                       */
+#define SIM_EHIP (-3)   /* a HIP runtime call failed (message has the why) */
+#define SIM_ESTATE (-4) /* call not valid in the handle's current state   */
+
+enum { SIM_UNBURNABLE = 0, SIM_FLAMMABLE = 1, SIM_BURNING = 2, SIM_BURNT = 3 };
+
+#define SIM_N_CLASSES 11 /* the WorldCover legend: tree, shrub, grass, crop, built,
+                            bare, snow, water, wetland, mangrove, lichen */
+#define SIM_N_THETA 17   /* p_base, alpha_w1, alpha_w2, alpha_s, alpha_gamma,
+                            p_continue, veg[0..10] */
+
+/* Model parameters, named as in the paper.
+ *  p_base       base propagation factor of phi (Eq. 3)
+ *  alpha_gamma  susceptibility scale: gamma(v) = alpha_gamma (1+veg)(1+den) (Eq. 4)
+ *  alpha_w1/w2  wind factor (Eq. 1); alpha_s slope factor (Eq. 2)
+ *  p_continue   probability that a burning cell keeps burning
+ *  veg[c]       mu_veg of land-cover class c, in [-1, 1]
+ *  cell_size    cell edge in metres (slope = rise / run, run = cell_size or
+ *               cell_size * sqrt(2) on diagonals)
+ *  unburnable_mask  bit c set: class c holds no fuel (starts UNBURNABLE) */
+typedef struct {
+    float p_base, alpha_gamma, alpha_w1, alpha_w2, alpha_s, p_continue;
+    float veg[SIM_N_CLASSES];
+    float cell_size;
+    uint32_t unburnable_mask;
+} sim_params;
+
+/* One env of the batch.  (V, Vx, Vy) is its wind: speed V (m/s) and
+ * Vx = V cos Theta, Vy = V sin Theta, Theta the direction the wind blows
+ * toward, counter-clockwise from east.  Ignored when per-cell wind is given.
+ * env_id selects the env's random stream (two envs with equal env_id, seed
+ * and inputs evolve identically). */
+typedef struct {
+    int64_t offset;
+    int32_t H, W;
+    uint32_t env_id;
+    float V, Vx, Vy;
+} sim_env;
+
+typedef struct sim_handle sim_handle;
+
+/* sim_init -- set up a batch (the static layers of the paper's "State
+ * representation") and write the initial fire state.
+ *  out        receives the new handle (host).
+ *  p          parameters (host); copied.
+ *  n_env, envs  host array of n_env descriptors; 1 <= H, W <= 32767; env
+ *             cell ranges must not overlap and must lie in [0, n_cells).
+ *  n_cells    total packed cells.
+ *  landcover  device uint8[n_cells], class 0..10.
+ *  density    device float[n_cells], mu_den in [-1, 1].
+ *  elevation  device float[n_cells], metres.
+ *  wind_cell  device float[3][n_cells] planes (V | Vx | Vy), or NULL for the
+ *             per-env wind of envs[].
+ *  ignitions  host int32[n_ign][3] (env, row, col); a FLAMMABLE cell there
+ *             starts BURNING, an UNBURNABLE one stays UNBURNABLE.
+ *  seed       Philox key of the random streams.
+ *  states_out device uint8[n_cells]: the initial fire state.
+ * The handle keeps its own copies of everything it needs (fuel term
+ * g = (1+veg)(1+den) in fp32, elevation, class, density, wind); the inputs
+ * may be freed after the call.  The step counter starts at 0. */
+int sim_init(sim_handle** out, const sim_params* p, int32_t n_env, const sim_env* envs,
+             int64_t n_cells, const uint8_t* landcover, const float* density,
+             const float* elevation, const float* wind_cell, const int32_t* ignitions,
+             int32_t n_ign, uint64_t seed, uint8_t* states_out, void* stream);
+
+/* sim_step -- T stochastic steps F_t -> F_{t+1} of every env (section 3,
+ * Eqs. 1-4, "Stochastic update"), starting at the handle's step counter t,
+ * which then advances by T.
+ *  states   device uint8[n_cells], updated in place.
+ *  actions  device int32[T][n_env] or NULL: before step s, env e drops
+ *           suppression on the 5x5 square centred at (a>>16, a&0xFFFF) for
+ *           a = actions[s][e] >= 0 (every FLAMMABLE or BURNING cell of the
+ *           square, clipped to the grid, becomes UNBURNABLE); a < 0 or a
+ *           centre outside the grid means no drop.
+ *  counts   device int32[T][n_env] or NULL: number of BURNING cells of each
+ *           env after each step (overwritten).
+ * The random draw of cell n = i*W + j of env e at absolute step t is
+ * Philox4x32-10 with key (seed lo, seed hi), counter (n>>2, t, env_id, 0),
+ * word n&3, u = (word >> 8) 2^-24; a FLAMMABLE cell ignites iff u <
+ * p_ignite, a BURNING cell burns out iff !(u < p_continue).  Results are
+ * bit-exact to that definition whatever the launch plan. T = 0 is a no-op;
+ * T < 0 is SIM_EINVAL. */
+int sim_step(sim_handle* h, uint8_t* states, const int32_t* actions, int32_t T, int32_t* counts,
+             void* stream);
+
+/* Step counter: get it, or set it to resume a saved run (states saved by
+ * the caller, same handle inputs and seed). */
+int sim_get_step(const sim_handle* h, uint64_t* t);
+int sim_set_step(sim_handle* h, uint64_t t);
+
+/* Launch plan of sim_step (results never depend on it).
+ *  tile_rows    rows per workgroup tile per 4-cell column group (1..8), 0 = default
+ *  temporal     steps fused per tile load (1 = one step per launch), 0 = default
+ *  skip_static  1: tiles of a wave with no burning cell read only the state
+ *               bytes (the fuel and elevation loads are skipped); 0: every
+ *               cell reads its 10 bytes every step
+ *  graph        1: capture the T launches of a call into a HIP graph and
+ *               replay it (re-captured when T, the pointers or the plan
+ *               change); 0: launch directly */
+typedef struct {
+    int32_t tile_rows, temporal, skip_static, graph;
+} sim_plan;
+int sim_set_plan(sim_handle* h, const sim_plan* plan);
+int sim_get_plan(const sim_handle* h, sim_plan* plan);
+
+/* ---------------------------------------------------------------- relaxed */
+/* The relaxed (mean-field) state: per cell U = P(unburned), B = P(burning)
+ * (the paper's p_un and p_burn; p_bd = 1 - U - B is not carried).  One step:
+ *   q_k(v) = 1 - exp(-gamma(v) phi(v - D_k, k))          (per neighbour, Eq. 4)
+ *   P(v)   = 1 - prod_k (1 - q_k(v) B(v - D_k))          (product form)
+ *   N = U P;  U' = U - N;  B' = N + p_continue B        (Eqs. 5-10)
+ * which equals Eq. 4 whenever B is 0/1.
+ * U, B and their adjoints are fp64: the recurrence amplifies small burning
+ * mass exponentially, so an fp32 state drifts onto a different trajectory
+ * within ~100 steps (the per-edge exp terms are fp32). */
+
+/* Initial relaxed state from the handle's initial fire state: U = 1, B = 0
+ * on FLAMMABLE cells, U = 0, B = 1 on BURNING ones, 0 elsewhere.
+ * U, B: device double[n_cells]. */
+int sim_relaxed_init(sim_handle* h, double* U, double* B, void* stream);
+
+/* Workspace bytes the relaxed forward/backward need for T steps with a
+ * checkpoint every ckpt_every steps (ckpt_every >= 1). */
+size_t sim_relaxed_workspace_bytes(const sim_handle* h, int32_t T, int32_t ckpt_every);
+
+/* T relaxed steps in place on (U, B) with parameters p (host; veg, p_base,
+ * alpha_* and p_continue may differ from sim_init's; unburnable_mask and
+ * cell_size must match).  Stores the checkpoints the backward needs in
+ * `workspace` (device, >= sim_relaxed_workspace_bytes). */
+int sim_step_relaxed_fwd(sim_handle* h, const sim_params* p, double* U, double* B, int32_t T,
+                         int32_t ckpt_every, void* workspace, size_t workspace_bytes,
+                         void* stream);
+
+/* Soft-IoU loss of the final relaxed state against a binary target scar.
+ * Per env e: S = 1 - U_T on burnable cells, I = sum S Y, D = sum S + sum Y - I,
+ * loss[e] = 1 - I / D (0 when D = 0).  gU_T (device double[n_cells], or NULL)
+ * receives scale * d loss[e] / d U_T summed over envs, i.e. the seed of the
+ * backward for the objective scale * sum_e loss[e].
+ *  target  device uint8[n_cells], nonzero = burnt in the target scar.
+ *  loss    device float[n_env]. */
+int sim_relaxed_loss(sim_handle* h, const double* U_T, const uint8_t* target, float* loss,
+                     double* gU_T, double scale, void* stream);
+
+/* Gradient of a scalar objective J(U_T, B_T) with respect to the parameter
+ * vector (p_base, alpha_w1, alpha_w2, alpha_s, alpha_gamma, p_continue,
+ * veg[0..10]) through the T relaxed steps of the last sim_step_relaxed_fwd
+ * call on the same workspace (same p, T, ckpt_every): recomputes each
+ * checkpoint segment forward, then runs the adjoint step backward.
+ *  gU_T, gB_T  device double[n_cells]: dJ/dU_T, dJ/dB_T (gB_T may be NULL = 0).
+ *  grad        device double[SIM_N_THETA], overwritten. */
+int sim_step_relaxed_bwd(sim_handle* h, const sim_params* p, const double* gU_T,
+                         const double* gB_T, int32_t T, int32_t ckpt_every, void* workspace,
+                         size_t workspace_bytes, double* grad, void* stream);
+
+/* ------------------------------------------------------------- diagnostics */
+/* The device exp and Philox the step uses, applied elementwise (for parity
+ * tests of the building blocks).  x, y: device float[n]; ctr: device
+ * uint32[n][4], key: device uint32[n][2], out: device uint32[n][4]. */
+int sim_debug_exp(const float* x, float* y, int64_t n, void* stream);
+int sim_debug_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int64_t n,
+                     void* stream);
+
+const char* sim_last_error(const sim_handle* h);
+void sim_destroy(sim_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FIRESIM_H */

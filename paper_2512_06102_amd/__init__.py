@@ -1,0 +1,290 @@
+"""Batched probabilistic fire-spread cellular automaton on AMD MI355X (gfx950).
+
+Thin ctypes binding of the HIP library libfiresim.so (C ABI in
+include/firesim.h).  Python only marshals arguments: PyTorch provides device
+memory and the current stream; every step of the model runs in the library's
+kernels.  Importing works without a GPU; creating a simulator needs the built
+library and a GPU, and fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfiresim.so")
+
+SIM_OK = 0
+UNBURNABLE, FLAMMABLE, BURNING, BURNT = 0, 1, 2, 3
+N_CLASSES = 11
+N_THETA = 17
+THETA_NAMES = ("p_base", "alpha_w1", "alpha_w2", "alpha_s", "alpha_gamma", "p_continue") + \
+    tuple("veg%d" % c for c in range(N_CLASSES))
+
+EXPORTED = ("sim_init", "sim_step", "sim_get_step", "sim_set_step", "sim_set_plan", "sim_get_plan",
+            "sim_relaxed_init", "sim_relaxed_workspace_bytes", "sim_step_relaxed_fwd",
+            "sim_relaxed_loss", "sim_step_relaxed_bwd", "sim_debug_exp", "sim_debug_philox",
+            "sim_last_error", "sim_destroy")
+
+
+class SimParams(ctypes.Structure):
+    _fields_ = [("p_base", ctypes.c_float), ("alpha_gamma", ctypes.c_float),
+                ("alpha_w1", ctypes.c_float), ("alpha_w2", ctypes.c_float),
+                ("alpha_s", ctypes.c_float), ("p_continue", ctypes.c_float),
+                ("veg", ctypes.c_float * N_CLASSES), ("cell_size", ctypes.c_float),
+                ("unburnable_mask", ctypes.c_uint32)]
+
+
+class SimEnv(ctypes.Structure):
+    _fields_ = [("offset", ctypes.c_int64), ("H", ctypes.c_int32), ("W", ctypes.c_int32),
+                ("env_id", ctypes.c_uint32), ("V", ctypes.c_float), ("Vx", ctypes.c_float),
+                ("Vy", ctypes.c_float)]
+
+
+class SimPlan(ctypes.Structure):
+    _fields_ = [("tile_rows", ctypes.c_int32), ("temporal", ctypes.c_int32),
+                ("skip_static", ctypes.c_int32), ("graph", ctypes.c_int32)]
+
+
+class SimError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise SimError("libfiresim.so is not built (run __graft_entry__.build() or "
+                           "python paper_2512_06102_amd/build.py)")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I32, I64, U64, SZ = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
+                                ctypes.c_size_t)
+        L.sim_init.argtypes = [ctypes.POINTER(P), P, I32, P, I64, P, P, P, P, P, I32, U64, P, P]
+        L.sim_step.argtypes = [P, P, P, I32, P, P]
+        L.sim_get_step.argtypes = [P, ctypes.POINTER(U64)]
+        L.sim_set_step.argtypes = [P, U64]
+        L.sim_set_plan.argtypes = [P, P]
+        L.sim_get_plan.argtypes = [P, P]
+        L.sim_relaxed_init.argtypes = [P, P, P, P]
+        L.sim_relaxed_workspace_bytes.argtypes = [P, I32, I32]
+        L.sim_relaxed_workspace_bytes.restype = SZ
+        L.sim_step_relaxed_fwd.argtypes = [P, P, P, P, I32, I32, P, SZ, P]
+        L.sim_relaxed_loss.argtypes = [P, P, P, P, P, ctypes.c_double, P]
+        L.sim_step_relaxed_bwd.argtypes = [P, P, P, P, I32, I32, P, SZ, P, P]
+        L.sim_debug_exp.argtypes = [P, P, I64, P]
+        L.sim_debug_philox.argtypes = [P, P, P, I64, P]
+        L.sim_last_error.argtypes = [P]
+        L.sim_last_error.restype = ctypes.c_char_p
+        L.sim_destroy.argtypes = [P]
+        _lib = L
+    return _lib
+
+
+def _stream(device=None) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _check(rc: int, handle=None):
+    if rc != SIM_OK:
+        msg = lib().sim_last_error(handle)
+        raise SimError("firesim error %d: %s" % (rc, msg.decode() if msg else ""))
+
+
+def make_params(p) -> SimParams:
+    """SimParams from any object with the paper's parameter names."""
+    from_mask = getattr(p, "unburnable_mask", None)
+    s = SimParams()
+    s.p_base, s.alpha_gamma = p.p_base, p.alpha_gamma
+    s.alpha_w1, s.alpha_w2, s.alpha_s = p.alpha_w1, p.alpha_w2, p.alpha_s
+    s.p_continue, s.cell_size = p.p_continue, p.cell_size
+    for c in range(N_CLASSES):
+        s.veg[c] = float(p.veg[c])
+    s.unburnable_mask = int(from_mask) if from_mask is not None else 0
+    return s
+
+
+def params_with_theta(base: SimParams, theta: Sequence[float]) -> SimParams:
+    """Copy of `base` with the 17 calibrated parameters taken from theta."""
+    s = SimParams()
+    ctypes.pointer(s)[0] = base
+    s.p_base, s.alpha_w1, s.alpha_w2, s.alpha_s, s.alpha_gamma, s.p_continue = \
+        (float(x) for x in theta[:6])
+    for c in range(N_CLASSES):
+        s.veg[c] = float(theta[6 + c])
+    return s
+
+
+def debug_exp(x: torch.Tensor) -> torch.Tensor:
+    """The step's device exp applied to a float32 CUDA tensor."""
+    x = x.contiguous()
+    y = torch.empty_like(x)
+    _check(lib().sim_debug_exp(_ptr(x), _ptr(y), x.numel(), ctypes.c_void_p(_stream(x.device))))
+    return y
+
+
+def debug_philox(ctr: torch.Tensor, key: torch.Tensor) -> torch.Tensor:
+    """Philox4x32-10 blocks of int32 CUDA tensors ctr [n,4], key [n,2]."""
+    ctr, key = ctr.contiguous(), key.contiguous()
+    out = torch.empty_like(ctr)
+    _check(lib().sim_debug_philox(_ptr(ctr), _ptr(key), _ptr(out), ctr.shape[0],
+                                  ctypes.c_void_p(_stream(ctr.device))))
+    return out
+
+
+class FireSim:
+    """A batch of envs on one GPU: static layers, fire state, step counter.
+
+    Arguments are CUDA tensors in the packed layout of include/firesim.h:
+    landcover uint8 [n_cells], density / elevation float32 [n_cells],
+    wind_cell float32 [3, n_cells] or None; envs is a list of
+    (offset, H, W, env_id, V, Vx, Vy); ignitions an int32 array [n, 3]."""
+
+    def __init__(self, params, envs, landcover, density, elevation, wind_cell=None,
+                 ignitions=(), seed: int = 0, unburnable_mask: Optional[int] = None):
+        L = lib()
+        self.device = landcover.device
+        self.params = make_params(params)
+        if unburnable_mask is not None:
+            self.params.unburnable_mask = int(unburnable_mask)
+        self.n_env = len(envs)
+        self.n_cells = int(landcover.numel())
+        arr = (SimEnv * self.n_env)()
+        for e, (off, H, W, eid, V, Vx, Vy) in enumerate(envs):
+            arr[e] = SimEnv(int(off), int(H), int(W), int(eid), float(V), float(Vx), float(Vy))
+        self.envs = arr
+        self.env_tuples = [tuple(x) for x in envs]
+        ign = list(ignitions)
+        ign_arr = (ctypes.c_int32 * max(1, 3 * len(ign)))()
+        for q, (e, i, j) in enumerate(ign):
+            ign_arr[3 * q], ign_arr[3 * q + 1], ign_arr[3 * q + 2] = int(e), int(i), int(j)
+        self.states = torch.empty(self.n_cells, dtype=torch.uint8, device=self.device)
+        self._keep = (landcover, density, elevation, wind_cell)
+        h = ctypes.c_void_p()
+        rc = L.sim_init(ctypes.byref(h), ctypes.byref(self.params), self.n_env, arr, self.n_cells,
+                        _ptr(landcover.contiguous()), _ptr(density.contiguous()),
+                        _ptr(elevation.contiguous()),
+                        _ptr(None if wind_cell is None else wind_cell.contiguous()),
+                        ign_arr if ign else None, len(ign), int(seed), _ptr(self.states),
+                        ctypes.c_void_p(_stream(self.device)))
+        _check(rc)
+        self.handle = h
+        self._keep = None
+
+    @classmethod
+    def from_batch(cls, batch, params, seed: int = 0, device="cuda"):
+        """Build from a host batch (numpy arrays: cls, den, elev, wind_cell,
+        offsets, sizes, env_id, wind_env, ignitions)."""
+        dev = torch.device(device)
+        envs = [(int(batch.offset[e]), int(batch.H[e]), int(batch.W[e]), int(batch.env_id[e]),
+                 float(batch.wind_env[e, 0]), float(batch.wind_env[e, 1]),
+                 float(batch.wind_env[e, 2])) for e in range(batch.n_env)]
+        wc = None if batch.wind_cell is None else torch.from_numpy(batch.wind_cell).to(dev)
+        return cls(params, envs, torch.from_numpy(batch.cls).to(dev),
+                   torch.from_numpy(batch.den).to(dev), torch.from_numpy(batch.elev).to(dev),
+                   wc, [tuple(int(x) for x in r) for r in batch.ignitions], seed,
+                   unburnable_mask=batch.unburnable_mask)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.sim_destroy(h)
+            self.handle = None
+
+    def _s(self):
+        return ctypes.c_void_p(_stream(self.device))
+
+    # ---------------------------------------------------------- stochastic
+    def step(self, T: int, actions: Optional[torch.Tensor] = None, counts: bool = False,
+             states: Optional[torch.Tensor] = None):
+        """Advance T stochastic steps in place; returns counts [T, n_env] or None."""
+        st = self.states if states is None else states
+        cnt = torch.empty((T, self.n_env), dtype=torch.int32, device=self.device) if counts else None
+        if actions is not None:
+            actions = actions.to(device=self.device, dtype=torch.int32).contiguous()
+            if tuple(actions.shape) != (T, self.n_env):
+                raise ValueError("actions must be [T, n_env]")
+        _check(lib().sim_step(self.handle, _ptr(st), _ptr(actions), int(T), _ptr(cnt), self._s()),
+               self.handle)
+        return cnt
+
+    @property
+    def t(self) -> int:
+        v = ctypes.c_uint64()
+        _check(lib().sim_get_step(self.handle, ctypes.byref(v)), self.handle)
+        return int(v.value)
+
+    @t.setter
+    def t(self, value: int):
+        _check(lib().sim_set_step(self.handle, int(value)), self.handle)
+
+    def set_plan(self, tile_rows=0, temporal=0, skip_static=0, graph=0):
+        p = SimPlan(tile_rows, temporal, skip_static, graph)
+        _check(lib().sim_set_plan(self.handle, ctypes.byref(p)), self.handle)
+
+    def plan(self) -> dict:
+        p = SimPlan()
+        _check(lib().sim_get_plan(self.handle, ctypes.byref(p)), self.handle)
+        return {"tile_rows": p.tile_rows, "temporal": p.temporal,
+                "skip_static": p.skip_static, "graph": p.graph}
+
+    # ------------------------------------------------------------- relaxed
+    def relaxed_init(self):
+        U = torch.empty(self.n_cells, dtype=torch.float64, device=self.device)
+        B = torch.empty_like(U)
+        _check(lib().sim_relaxed_init(self.handle, _ptr(U), _ptr(B), self._s()), self.handle)
+        return U, B
+
+    def relaxed_workspace(self, T: int, ckpt_every: int) -> torch.Tensor:
+        n = lib().sim_relaxed_workspace_bytes(self.handle, int(T), int(ckpt_every))
+        return torch.empty(max(int(n), 1), dtype=torch.uint8, device=self.device)
+
+    def relaxed_fwd(self, params: SimParams, U, B, T, ckpt_every, ws):
+        _check(lib().sim_step_relaxed_fwd(self.handle, ctypes.byref(params), _ptr(U), _ptr(B),
+                                          int(T), int(ckpt_every), _ptr(ws), ws.numel(), self._s()),
+               self.handle)
+
+    def relaxed_loss(self, U_T, target, scale: float = 1.0, want_grad: bool = True):
+        loss = torch.empty(self.n_env, dtype=torch.float32, device=self.device)
+        g = torch.empty_like(U_T) if want_grad else None
+        _check(lib().sim_relaxed_loss(self.handle, _ptr(U_T), _ptr(target), _ptr(loss), _ptr(g),
+                                      float(scale), self._s()), self.handle)
+        return loss, g
+
+    def relaxed_bwd(self, params: SimParams, gU_T, gB_T, T, ckpt_every, ws) -> torch.Tensor:
+        grad = torch.empty(N_THETA, dtype=torch.float64, device=self.device)
+        _check(lib().sim_step_relaxed_bwd(self.handle, ctypes.byref(params), _ptr(gU_T), _ptr(gB_T),
+                                          int(T), int(ckpt_every), _ptr(ws), ws.numel(), _ptr(grad),
+                                          self._s()), self.handle)
+        return grad
+
+
+class RelaxedCalibrationLoss(torch.autograd.Function):
+    """Mean soft-IoU loss of T relaxed steps as a function of the 17
+    parameters theta (float64 CPU tensor), with the library's adjoint as the
+    backward.  forward(theta, sim, target, T, ckpt_every) -> scalar."""
+
+    @staticmethod
+    def forward(ctx, theta, sim: FireSim, target, T: int, ckpt_every: int = 10):
+        p = params_with_theta(sim.params, theta.detach().cpu().tolist())
+        U, B = sim.relaxed_init()
+        ws = sim.relaxed_workspace(T, ckpt_every)
+        sim.relaxed_fwd(p, U, B, T, ckpt_every, ws)
+        loss, gU = sim.relaxed_loss(U, target, scale=1.0 / sim.n_env)
+        ctx.sim, ctx.p, ctx.T, ctx.k, ctx.ws, ctx.gU = sim, p, T, ckpt_every, ws, gU
+        return loss.double().mean().cpu()
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        g = ctx.sim.relaxed_bwd(ctx.p, ctx.gU, None, ctx.T, ctx.k, ctx.ws)
+        return g.cpu() * grad_out, None, None, None, None

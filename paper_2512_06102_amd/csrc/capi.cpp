@@ -1,0 +1,507 @@
+// capi.cpp -- the C ABI (include/firesim.h): argument checking, the handle's
+// device memory, the tile list, step sequencing and graph replay.  All model
+// arithmetic runs in the kernels (stoch.hip, relaxed.hip).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/firesim.h"
+#include "internal.hpp"
+#include "relaxed.hpp"
+
+using namespace firesim;
+
+namespace {
+
+thread_local std::string g_init_error;
+
+struct GraphCache {
+    hipGraphExec_t exec = nullptr;
+    int32_t T = -1;
+    const void* states = nullptr;
+    const void* actions = nullptr;
+    const void* counts = nullptr;
+    sim_plan plan{};
+    bool valid = false;
+};
+
+}  // namespace
+
+struct sim_handle {
+    int device = 0;
+    sim_params params{};
+    int32_t n_env = 0;
+    int64_t n_cells = 0;
+    std::vector<sim_env> envs;
+    bool aligned = true;
+    bool wind_cell = false;
+    uint64_t seed = 0;
+    uint64_t t = 0;
+    sim_plan plan{4, 1, 0, 0};
+
+    EnvDev* d_envs = nullptr;
+    float* d_g = nullptr;
+    float* d_E = nullptr;
+    uint8_t* d_cls = nullptr;
+    float* d_den = nullptr;
+    float* d_wind = nullptr;
+    uint8_t* d_init_states = nullptr;  // initial fire state (for the relaxed initial state)
+    uint8_t* d_tmp = nullptr;          // ping-pong state buffer
+    uint32_t* d_t = nullptr;           // step counter base read by the step kernels
+    TileDesc* d_tiles = nullptr;
+    int32_t n_tiles = 0;
+    int32_t tiles_rt = 0;              // rows_per_thread the tile list was built for
+    hipStream_t cap_stream = nullptr;
+    GraphCache graph;
+    RelaxedState relaxed;
+    std::string err;
+};
+
+namespace {
+
+int fail(sim_handle* h, int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (h)
+        h->err = buf;
+    else
+        g_init_error = buf;
+    return code;
+}
+
+#define HIP_OR_FAIL(h, expr)                                                              \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail((h), SIM_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));    \
+    } while (0)
+
+void free_all(sim_handle* h)
+{
+    void* ptrs[] = {h->d_envs, h->d_g, h->d_E, h->d_cls, h->d_den, h->d_wind, h->d_init_states,
+                    h->d_tmp, h->d_t, h->d_tiles};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    if (h->graph.exec) (void)hipGraphExecDestroy(h->graph.exec);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+    relaxed_free(h->relaxed);
+}
+
+StepArgs step_args(const sim_handle* h)
+{
+    StepArgs a;
+    const sim_params& p = h->params;
+    a.p_base = p.p_base;
+    a.alpha_gamma = p.alpha_gamma;
+    a.alpha_w1 = p.alpha_w1;
+    a.alpha_w2 = p.alpha_w2;
+    a.alpha_s = p.alpha_s;
+    a.p_continue = p.p_continue;
+    a.inv_run_orth = (float)(1.0 / (double)p.cell_size);
+    a.inv_run_diag = (float)(1.0 / ((double)p.cell_size * std::sqrt(2.0)));
+    a.key0 = (uint32_t)h->seed;
+    a.key1 = (uint32_t)(h->seed >> 32);
+    return a;
+}
+
+int tile_width_for(int W) { return W > 128 ? 256 : (W > 64 ? 128 : 64); }
+
+// Tile list: env-major, then row band, then column band.
+int build_tiles(sim_handle* h, int rt)
+{
+    std::vector<TileDesc> tiles;
+    for (int32_t e = 0; e < h->n_env; ++e) {
+        const int H = h->envs[e].H, W = h->envs[e].W;
+        const int width = tile_width_for(W);
+        const int th = (1024 / width) * rt;
+        for (int r0 = 0; r0 < H; r0 += th)
+            for (int c0 = 0; c0 < W; c0 += width) tiles.push_back(TileDesc{e, r0, c0, width});
+    }
+    if (h->d_tiles) (void)hipFree(h->d_tiles);
+    h->d_tiles = nullptr;
+    if (hipMalloc(&h->d_tiles, tiles.size() * sizeof(TileDesc)) != hipSuccess)
+        return fail(h, SIM_ENOMEM, "tile list allocation failed");
+    HIP_OR_FAIL(h, hipMemcpy(h->d_tiles, tiles.data(), tiles.size() * sizeof(TileDesc),
+                             hipMemcpyHostToDevice));
+    h->n_tiles = (int32_t)tiles.size();
+    h->tiles_rt = rt;
+    return SIM_OK;
+}
+
+StepLaunch step_launch(const sim_handle* h)
+{
+    StepLaunch L;
+    L.tiles = h->d_tiles;
+    L.n_tiles = h->n_tiles;
+    L.envs = h->d_envs;
+    L.n_env = h->n_env;
+    L.fields = StaticFields{h->d_g, h->d_E, h->wind_cell ? h->d_wind : nullptr, h->n_cells};
+    L.args = step_args(h);
+    L.aligned = h->aligned;
+    L.rows_per_thread = h->plan.tile_rows;
+    L.skip_static = h->plan.skip_static != 0;
+    return L;
+}
+
+// Enqueue the T launches of one sim_step call (counts cleared first; if T is
+// odd the result is copied back from the ping-pong buffer).
+hipError_t enqueue_steps(sim_handle* h, hipStream_t s, uint8_t* states, const int32_t* actions,
+                         int32_t T, int32_t* counts)
+{
+    hipError_t e;
+    if (counts) {
+        e = launch_fill_i32(s, counts, (int64_t)T * h->n_env, 0);
+        if (e != hipSuccess) return e;
+    }
+    const StepLaunch L = step_launch(h);
+    uint8_t* cur = states;
+    uint8_t* nxt = h->d_tmp;
+    for (int32_t k = 0; k < T; ++k) {
+        e = launch_stoch_step(s, L, cur, nxt, h->d_t, (uint32_t)k,
+                              actions ? actions + (int64_t)k * h->n_env : nullptr,
+                              counts ? counts + (int64_t)k * h->n_env : nullptr);
+        if (e != hipSuccess) return e;
+        std::swap(cur, nxt);
+    }
+    if (cur != states) return launch_copy_u8(s, states, cur, h->n_cells);
+    return hipSuccess;
+}
+
+bool same_plan(const sim_plan& a, const sim_plan& b)
+{
+    return a.tile_rows == b.tile_rows && a.temporal == b.temporal &&
+           a.skip_static == b.skip_static && a.graph == b.graph;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sim_init(sim_handle** out, const sim_params* p, int32_t n_env, const sim_env* envs,
+             int64_t n_cells, const uint8_t* landcover, const float* density,
+             const float* elevation, const float* wind_cell, const int32_t* ignitions,
+             int32_t n_ign, uint64_t seed, uint8_t* states_out, void* stream)
+{
+    g_init_error.clear();
+    if (!out) return fail(nullptr, SIM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!p || !envs || n_env < 1) return fail(nullptr, SIM_EINVAL, "need params and n_env >= 1 envs");
+    if (!landcover || !density || !elevation || !states_out)
+        return fail(nullptr, SIM_EINVAL, "landcover, density, elevation and states_out are required");
+    if (n_ign < 0 || (n_ign > 0 && !ignitions)) return fail(nullptr, SIM_EINVAL, "bad ignition list");
+    if (!(p->cell_size > 0.0f) || !std::isfinite(p->cell_size))
+        return fail(nullptr, SIM_EINVAL, "cell_size must be positive");
+    if (n_cells < 1) return fail(nullptr, SIM_EINVAL, "n_cells must be >= 1");
+    // envs: sizes and disjoint in-range cell ranges
+    std::vector<std::pair<int64_t, int64_t>> ranges;
+    for (int32_t e = 0; e < n_env; ++e) {
+        const sim_env& v = envs[e];
+        if (v.H < 1 || v.W < 1 || v.H > 32767 || v.W > 32767)
+            return fail(nullptr, SIM_EINVAL, "env %d: H, W must be in [1, 32767]", e);
+        const int64_t cells = (int64_t)v.H * v.W;
+        if (v.offset < 0 || v.offset + cells > n_cells)
+            return fail(nullptr, SIM_EINVAL, "env %d: cells [%lld, %lld) outside [0, %lld)", e,
+                        (long long)v.offset, (long long)(v.offset + cells), (long long)n_cells);
+        ranges.push_back({v.offset, v.offset + cells});
+    }
+    std::sort(ranges.begin(), ranges.end());
+    for (size_t i = 1; i < ranges.size(); ++i)
+        if (ranges[i].first < ranges[i - 1].second)
+            return fail(nullptr, SIM_EINVAL, "env cell ranges overlap");
+    for (int32_t q = 0; q < n_ign; ++q) {
+        const int32_t e = ignitions[3 * q], i = ignitions[3 * q + 1], j = ignitions[3 * q + 2];
+        if (e < 0 || e >= n_env || i < 0 || i >= envs[e].H || j < 0 || j >= envs[e].W)
+            return fail(nullptr, SIM_EINVAL, "ignition %d (%d, %d, %d) outside its env", q, e, i, j);
+    }
+
+    sim_handle* h = new (std::nothrow) sim_handle();
+    if (!h) return fail(nullptr, SIM_ENOMEM, "host allocation failed");
+    hipStream_t s = (hipStream_t)stream;
+    auto bail = [&](int code) {
+        g_init_error = h->err;
+        free_all(h);
+        delete h;
+        return code;
+    };
+    if (hipGetDevice(&h->device) != hipSuccess) {
+        h->err = "hipGetDevice failed (no GPU?)";
+        return bail(SIM_EHIP);
+    }
+    h->params = *p;
+    h->n_env = n_env;
+    h->n_cells = n_cells;
+    h->envs.assign(envs, envs + n_env);
+    h->wind_cell = wind_cell != nullptr;
+    h->seed = seed;
+    // 4-cell vector loads need every row start (and each wind plane) on a 4-cell boundary
+    for (const sim_env& v : h->envs)
+        if (v.W % 4 != 0 || v.offset % 4 != 0) h->aligned = false;
+    if (h->wind_cell && n_cells % 4 != 0) h->aligned = false;
+
+    std::vector<EnvDev> ed(n_env);
+    for (int32_t e = 0; e < n_env; ++e)
+        ed[e] = EnvDev{envs[e].offset, envs[e].H, envs[e].W, envs[e].env_id,
+                       envs[e].V, envs[e].Vx, envs[e].Vy, 0.0f};
+    const size_t n = (size_t)n_cells;
+    int rc;
+#define ALLOC(ptr, bytes)                                                                   \
+    if (hipMalloc(&(ptr), (bytes)) != hipSuccess) {                                         \
+        fail(h, SIM_ENOMEM, "device allocation of %zu bytes failed", (size_t)(bytes));      \
+        return bail(SIM_ENOMEM);                                                            \
+    }
+    ALLOC(h->d_envs, sizeof(EnvDev) * n_env);
+    ALLOC(h->d_g, 4 * n);
+    ALLOC(h->d_E, 4 * n);
+    ALLOC(h->d_cls, n);
+    ALLOC(h->d_den, 4 * n);
+    ALLOC(h->d_init_states, n);
+    ALLOC(h->d_tmp, n);
+    ALLOC(h->d_t, 256);
+    if (h->wind_cell) ALLOC(h->d_wind, 12 * n);
+#undef ALLOC
+    int32_t* d_ign = nullptr;
+    if (hipMemcpy(h->d_envs, ed.data(), sizeof(EnvDev) * n_env, hipMemcpyHostToDevice) != hipSuccess) {
+        fail(h, SIM_EHIP, "env table upload failed");
+        return bail(SIM_EHIP);
+    }
+    if (n_ign > 0) {
+        if (hipMalloc(&d_ign, 12 * (size_t)n_ign) != hipSuccess) {
+            fail(h, SIM_ENOMEM, "ignition list allocation failed");
+            return bail(SIM_ENOMEM);
+        }
+        if (hipMemcpy(d_ign, ignitions, 12 * (size_t)n_ign, hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipFree(d_ign);
+            fail(h, SIM_EHIP, "ignition list upload failed");
+            return bail(SIM_EHIP);
+        }
+    }
+    hipError_t e = launch_init_cells(s, n_cells, landcover, density, elevation, wind_cell,
+                                     p->veg, p->unburnable_mask, h->d_g, h->d_E, h->d_cls,
+                                     h->d_den, h->d_wind, states_out);
+    if (e == hipSuccess) e = launch_ignite(s, d_ign, n_ign, h->d_envs, states_out);
+    if (e == hipSuccess) e = launch_copy_u8(s, h->d_init_states, states_out, n_cells);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (d_ign) (void)hipFree(d_ign);
+    if (e != hipSuccess) {
+        fail(h, SIM_EHIP, "initialisation kernels failed: %s", hipGetErrorString(e));
+        return bail(SIM_EHIP);
+    }
+    if ((rc = build_tiles(h, h->plan.tile_rows)) != SIM_OK) return bail(rc);
+    if (hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        fail(h, SIM_EHIP, "stream creation failed");
+        return bail(SIM_EHIP);
+    }
+    *out = h;
+    return SIM_OK;
+}
+
+int sim_step(sim_handle* h, uint8_t* states, const int32_t* actions, int32_t T, int32_t* counts,
+             void* stream)
+{
+    if (!h) return fail(nullptr, SIM_EINVAL, "handle is NULL");
+    if (T < 0) return fail(h, SIM_EINVAL, "T must be >= 0");
+    if (!states) return fail(h, SIM_EINVAL, "states is NULL");
+    if (T == 0) return SIM_OK;
+    if (h->t + (uint64_t)T > 0xFFFFFFFFull)
+        return fail(h, SIM_ESTATE, "step counter would pass 2^32");
+    hipStream_t s = (hipStream_t)stream;
+    if (h->tiles_rt != h->plan.tile_rows) {
+        const int rc = build_tiles(h, h->plan.tile_rows);
+        if (rc != SIM_OK) return rc;
+        h->graph.valid = false;
+    }
+    HIP_OR_FAIL(h, launch_set_u32(s, h->d_t, (uint32_t)h->t));
+    if (h->plan.graph) {
+        GraphCache& G = h->graph;
+        if (!(G.valid && G.T == T && G.states == states && G.actions == actions &&
+              G.counts == counts && same_plan(G.plan, h->plan))) {
+            if (G.exec) (void)hipGraphExecDestroy(G.exec);
+            G.exec = nullptr;
+            G.valid = false;
+            hipGraph_t graph = nullptr;
+            HIP_OR_FAIL(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+            hipError_t e = enqueue_steps(h, h->cap_stream, states, actions, T, counts);
+            hipError_t e2 = hipStreamEndCapture(h->cap_stream, &graph);
+            if (e != hipSuccess || e2 != hipSuccess) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return fail(h, SIM_EHIP, "graph capture failed: %s",
+                            hipGetErrorString(e != hipSuccess ? e : e2));
+            }
+            e = hipGraphInstantiate(&G.exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) return fail(h, SIM_EHIP, "graph instantiate failed: %s", hipGetErrorString(e));
+            G.T = T;
+            G.states = states;
+            G.actions = actions;
+            G.counts = counts;
+            G.plan = h->plan;
+            G.valid = true;
+        }
+        HIP_OR_FAIL(h, hipGraphLaunch(G.exec, s));
+    } else {
+        HIP_OR_FAIL(h, enqueue_steps(h, s, states, actions, T, counts));
+    }
+    h->t += (uint64_t)T;
+    return SIM_OK;
+}
+
+int sim_get_step(const sim_handle* h, uint64_t* t)
+{
+    if (!h || !t) return SIM_EINVAL;
+    *t = h->t;
+    return SIM_OK;
+}
+
+int sim_set_step(sim_handle* h, uint64_t t)
+{
+    if (!h) return SIM_EINVAL;
+    if (t > 0xFFFFFFFFull) return fail(h, SIM_EINVAL, "step counter must be < 2^32");
+    h->t = t;
+    return SIM_OK;
+}
+
+int sim_set_plan(sim_handle* h, const sim_plan* plan)
+{
+    if (!h || !plan) return SIM_EINVAL;
+    sim_plan p = *plan;
+    if (p.tile_rows == 0) p.tile_rows = 4;
+    if (p.temporal == 0) p.temporal = 1;
+    if (!(p.tile_rows == 1 || p.tile_rows == 2 || p.tile_rows == 4 || p.tile_rows == 8))
+        return fail(h, SIM_EINVAL, "tile_rows must be 1, 2, 4 or 8");
+    if (p.temporal != 1) return fail(h, SIM_EINVAL, "temporal must be 1");
+    if (p.skip_static != 0 && p.skip_static != 1) return fail(h, SIM_EINVAL, "skip_static must be 0 or 1");
+    if (p.graph != 0 && p.graph != 1) return fail(h, SIM_EINVAL, "graph must be 0 or 1");
+    h->plan = p;
+    return SIM_OK;
+}
+
+int sim_get_plan(const sim_handle* h, sim_plan* plan)
+{
+    if (!h || !plan) return SIM_EINVAL;
+    *plan = h->plan;
+    return SIM_OK;
+}
+
+int sim_relaxed_init(sim_handle* h, double* U, double* B, void* stream)
+{
+    if (!h || !U || !B) return fail(h, SIM_EINVAL, "handle, U and B are required");
+    HIP_OR_FAIL(h, launch_relaxed_init(
+                       (hipStream_t)stream, h->d_init_states, h->n_cells, U, B));
+    return SIM_OK;
+}
+
+size_t sim_relaxed_workspace_bytes(const sim_handle* h, int32_t T, int32_t ckpt_every)
+{
+    if (!h || T < 0 || ckpt_every < 1) return 0;
+    return relaxed_workspace_bytes(h->n_cells, T, ckpt_every);
+}
+
+static RelaxedInputs relaxed_inputs(const sim_handle* h)
+{
+    RelaxedInputs in;
+    in.tiles = h->relaxed.d_tiles;
+    in.n_tiles = h->relaxed.n_tiles;
+    in.envs = h->d_envs;
+    in.n_env = h->n_env;
+    in.cls = h->d_cls;
+    in.den = h->d_den;
+    in.E = h->d_E;
+    in.wind = h->wind_cell ? h->d_wind : nullptr;
+    in.n_cells = h->n_cells;
+    return in;
+}
+
+static int check_relaxed_params(sim_handle* h, const sim_params* p)
+{
+    if (!p) return fail(h, SIM_EINVAL, "params are NULL");
+    if (p->cell_size != h->params.cell_size || p->unburnable_mask != h->params.unburnable_mask)
+        return fail(h, SIM_EINVAL, "cell_size and unburnable_mask must match sim_init");
+    return SIM_OK;
+}
+
+int sim_step_relaxed_fwd(sim_handle* h, const sim_params* p, double* U, double* B, int32_t T,
+                         int32_t ckpt_every, void* workspace, size_t workspace_bytes, void* stream)
+{
+    if (!h) return fail(nullptr, SIM_EINVAL, "handle is NULL");
+    int rc = check_relaxed_params(h, p);
+    if (rc) return rc;
+    if (!U || !B || T < 0 || ckpt_every < 1) return fail(h, SIM_EINVAL, "bad U/B/T/ckpt_every");
+    if (T > 0 && (!workspace || workspace_bytes < relaxed_workspace_bytes(h->n_cells, T, ckpt_every)))
+        return fail(h, SIM_EINVAL, "workspace too small (%zu < %zu)", workspace_bytes,
+                    relaxed_workspace_bytes(h->n_cells, T, ckpt_every));
+    if ((rc = relaxed_prepare(h->relaxed, h->envs)) != 0)
+        return fail(h, SIM_ENOMEM, "relaxed tile list allocation failed");
+    hipError_t e = relaxed_forward((hipStream_t)stream, relaxed_inputs(h), *p, U, B, T, ckpt_every,
+                                   workspace);
+    if (e != hipSuccess) return fail(h, SIM_EHIP, "relaxed forward failed: %s", hipGetErrorString(e));
+    return SIM_OK;
+}
+
+int sim_relaxed_loss(sim_handle* h, const double* U_T, const uint8_t* target, float* loss,
+                     double* gU_T, double scale, void* stream)
+{
+    if (!h) return fail(nullptr, SIM_EINVAL, "handle is NULL");
+    if (!U_T || !target || !loss) return fail(h, SIM_EINVAL, "U_T, target and loss are required");
+    if (relaxed_prepare(h->relaxed, h->envs) != 0)
+        return fail(h, SIM_ENOMEM, "relaxed tile list allocation failed");
+    hipError_t e = relaxed_loss((hipStream_t)stream, relaxed_inputs(h), h->d_init_states, U_T,
+                                target, loss, gU_T, scale, h->relaxed);
+    if (e != hipSuccess) return fail(h, SIM_EHIP, "relaxed loss failed: %s", hipGetErrorString(e));
+    return SIM_OK;
+}
+
+int sim_step_relaxed_bwd(sim_handle* h, const sim_params* p, const double* gU_T, const double* gB_T,
+                         int32_t T, int32_t ckpt_every, void* workspace, size_t workspace_bytes,
+                         double* grad, void* stream)
+{
+    if (!h) return fail(nullptr, SIM_EINVAL, "handle is NULL");
+    int rc = check_relaxed_params(h, p);
+    if (rc) return rc;
+    if (!gU_T || !grad || T < 0 || ckpt_every < 1) return fail(h, SIM_EINVAL, "bad gU_T/grad/T/ckpt_every");
+    if (T > 0 && (!workspace || workspace_bytes < relaxed_workspace_bytes(h->n_cells, T, ckpt_every)))
+        return fail(h, SIM_EINVAL, "workspace too small");
+    if ((rc = relaxed_prepare(h->relaxed, h->envs)) != 0)
+        return fail(h, SIM_ENOMEM, "relaxed tile list allocation failed");
+    hipError_t e = relaxed_backward((hipStream_t)stream, relaxed_inputs(h), *p, gU_T, gB_T, T,
+                                    ckpt_every, workspace, grad, h->relaxed);
+    if (e != hipSuccess) return fail(h, SIM_EHIP, "relaxed backward failed: %s", hipGetErrorString(e));
+    return SIM_OK;
+}
+
+int sim_debug_exp(const float* x, float* y, int64_t n, void* stream)
+{
+    if (n < 0 || (n > 0 && (!x || !y))) return SIM_EINVAL;
+    return launch_debug_exp((hipStream_t)stream, x, y, n) == hipSuccess ? SIM_OK : SIM_EHIP;
+}
+
+int sim_debug_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int64_t n, void* stream)
+{
+    if (n < 0 || (n > 0 && (!ctr || !key || !out))) return SIM_EINVAL;
+    return launch_debug_philox((hipStream_t)stream, ctr, key, out, n) == hipSuccess ? SIM_OK : SIM_EHIP;
+}
+
+const char* sim_last_error(const sim_handle* h)
+{
+    return h ? h->err.c_str() : g_init_error.c_str();
+}
+
+void sim_destroy(sim_handle* h)
+{
+    if (!h) return;
+    (void)hipDeviceSynchronize();
+    free_all(h);
+    delete h;
+}
+
+}  // extern "C"

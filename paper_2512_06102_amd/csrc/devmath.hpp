@@ -1,0 +1,92 @@
+// devmath.hpp -- device building blocks of the stochastic step: the
+// counter-based generator, the exponential, and the neighbour geometry.
+//
+// The step's results are defined bit for bit, so every routine here uses only
+// IEEE fp32 add, subtract, multiply, round-to-nearest-even and compares, in a
+// fixed order (the library is built with -ffp-contract=off, so no
+// multiply-add is fused, and with fp32 denormals kept).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace firesim {
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11, section 4.2): ten rounds
+// of two 32x32->64 multiplies mixing the four counter words, the two key
+// words bumped by Weyl constants between rounds.
+__device__ __forceinline__ uint4 philox4x32_10(uint4 x, uint2 key)
+{
+    constexpr uint32_t kMulA = 0xD2511F53u, kMulB = 0xCD9E8D57u;
+    constexpr uint32_t kWeylA = 0x9E3779B9u, kWeylB = 0xBB67AE85u;
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        if (round != 0) {
+            key.x += kWeylA;
+            key.y += kWeylB;
+        }
+        const uint32_t lo_a = kMulA * x.x, hi_a = __umulhi(kMulA, x.x);
+        const uint32_t lo_b = kMulB * x.z, hi_b = __umulhi(kMulB, x.z);
+        x = make_uint4(hi_b ^ x.y ^ key.x, lo_b, hi_a ^ x.w ^ key.y, lo_a);
+    }
+    return x;
+}
+
+// 24-bit uniform in [0, 1 - 2^-24] from one Philox word.
+__device__ __forceinline__ float word_to_uniform(uint32_t w)
+{
+    return (float)(w >> 8) * 5.9604644775390625e-8f;  // 2^-24
+}
+
+// e^x in fp32: x = n ln2 + r with n = rint(x / ln2) (Cody & Waite 1980
+// reduction; ln2 split into a 15-bit head so n * head is exact), e^r from
+// its Taylor series through r^7 evaluated by Horner's rule, then scaled by
+// 2^n through the exponent field.  Defined on [-87, 88]: 0 below, e^88
+// above (results there stay normal, so the scaling is exact).
+__device__ __forceinline__ float exp_c(float x)
+{
+    constexpr float kInvLn2 = (float)1.44269504088896340736;
+    constexpr float kLn2Head = 0.693145751953125f;  // 22713 * 2^-15
+    constexpr float kLn2Tail = (float)(0.69314718055994530942 - 0.693145751953125);
+    constexpr float kT2 = 0.5f, kT3 = (float)(1.0 / 6.0), kT4 = (float)(1.0 / 24.0);
+    constexpr float kT5 = (float)(1.0 / 120.0), kT6 = (float)(1.0 / 720.0);
+    constexpr float kT7 = (float)(1.0 / 5040.0);
+    if (x != x) return x;
+    if (x < -87.0f) return 0.0f;
+    if (x > 88.0f) x = 88.0f;
+    const float n = __builtin_rintf(x * kInvLn2);
+    const float r = (x - n * kLn2Head) - n * kLn2Tail;
+    float poly = kT7;
+    poly = poly * r + kT6;
+    poly = poly * r + kT5;
+    poly = poly * r + kT4;
+    poly = poly * r + kT3;
+    poly = poly * r + kT2;
+    poly = poly * r + 1.0f;
+    poly = poly * r + 1.0f;
+    const float two_n = __int_as_float(((int)n + 127) << 23);
+    return poly * two_n;
+}
+
+// Neighbour direction k points from a source cell to its target; its angle
+// is k*pi/4 counter-clockwise from east and rows grow southward, so
+// (drow, dcol) = E(0,1) NE(-1,1) N(-1,0) NW(-1,-1) W(0,-1) SW(1,-1) S(1,0)
+// SE(1,1).  kCos/kSin hold cos and sin of the angle rounded to fp32.
+__device__ constexpr int kDRow[8] = {0, -1, -1, -1, 0, 1, 1, 1};
+__device__ constexpr int kDCol[8] = {1, 1, 0, -1, -1, -1, 0, 1};
+constexpr float kHalfSqrt2 = 0.70710678118654752440f;
+__device__ constexpr float kCos[8] = {1.0f, kHalfSqrt2, 0.0f, -kHalfSqrt2,
+                                      -1.0f, -kHalfSqrt2, 0.0f, kHalfSqrt2};
+__device__ constexpr float kSin[8] = {0.0f, kHalfSqrt2, 1.0f, kHalfSqrt2,
+                                      0.0f, -kHalfSqrt2, -1.0f, -kHalfSqrt2};
+
+// Exponent of the wind factor (Eq. 1) for direction k at a source with
+// wind (V, Vx, Vy): a_w1 V + a_w2 (V cos(angle_k - Theta) - V), with
+// V cos(angle_k - Theta) = cos_k Vx + sin_k Vy.
+__device__ __forceinline__ float wind_exponent(int k, float a_w1, float a_w2, float V, float Vx,
+                                               float Vy)
+{
+    return a_w1 * V + a_w2 * ((kCos[k] * Vx + kSin[k] * Vy) - V);
+}
+
+}  // namespace firesim

@@ -1,0 +1,78 @@
+// internal.hpp -- types shared by the library's host code and its kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace firesim {
+
+enum : uint8_t { kUnburnable = 0, kFlammable = 1, kBurning = 2, kBurnt = 3 };
+
+// Device copy of one env descriptor.
+struct EnvDev {
+    int64_t offset;
+    int32_t H, W;
+    uint32_t env_id;
+    float V, Vx, Vy;
+    float pad;
+};
+
+// Scalar parameters of the stochastic step, as kernel arguments.
+struct StepArgs {
+    float p_base, alpha_gamma, alpha_w1, alpha_w2, alpha_s, p_continue;
+    float inv_run_orth, inv_run_diag;  // 1/cell_size, 1/(cell_size sqrt 2)
+    uint32_t key0, key1;               // Philox key (seed lo, seed hi)
+};
+
+// Static inputs resident in HBM for the whole life of a handle.
+struct StaticFields {
+    const float* g;      // fuel term (1 + veg[class]) (1 + den), fp32 [n_cells]
+    const float* E;      // elevation, m [n_cells]
+    const float* wind;   // [3][n_cells] (V | Vx | Vy) or nullptr (per-env wind)
+    int64_t n_cells;
+};
+
+// One workgroup tile of the stochastic step: env, first row, first column and
+// tile width in cells (64, 128 or 256).  Its height is (1024 / width) *
+// rows_per_thread.
+struct TileDesc {
+    int32_t env, r0, c0, width;
+};
+
+constexpr int kBlock = 256;
+
+// Launchers (stream-ordered, no synchronisation).
+hipError_t launch_init_cells(hipStream_t s, int64_t n, const uint8_t* cls, const float* den,
+                             const float* elev, const float* wind_in, const float veg[11],
+                             uint32_t unburnable_mask, float* g, float* E, uint8_t* cls_out,
+                             float* den_out, float* wind_out, uint8_t* states);
+hipError_t launch_ignite(hipStream_t s, const int32_t* ign, int32_t n_ign, const EnvDev* envs,
+                         uint8_t* states);
+hipError_t launch_fill_i32(hipStream_t s, int32_t* p, int64_t n, int32_t v);
+hipError_t launch_copy_u8(hipStream_t s, uint8_t* dst, const uint8_t* src, int64_t n);
+
+struct StepLaunch {
+    const TileDesc* tiles;
+    int32_t n_tiles;
+    const EnvDev* envs;
+    int32_t n_env;
+    StaticFields fields;
+    StepArgs args;
+    bool aligned;       // every env has W % 4 == 0
+    int rows_per_thread;
+    bool skip_static;   // skip fuel/elevation loads of waves with no front
+};
+
+// One stochastic step t -> t+1 from src to dst, with t = *t_base + step.
+// t_base lives in device memory so that a captured sequence of launches can be
+// replayed for any starting step.
+hipError_t launch_stoch_step(hipStream_t s, const StepLaunch& L, const uint8_t* src,
+                             uint8_t* dst, const uint32_t* t_base, uint32_t step,
+                             const int32_t* actions_row, int32_t* counts_row);
+hipError_t launch_set_u32(hipStream_t s, uint32_t* p, uint32_t v);
+
+hipError_t launch_debug_exp(hipStream_t s, const float* x, float* y, int64_t n);
+hipError_t launch_debug_philox(hipStream_t s, const uint32_t* ctr, const uint32_t* key,
+                               uint32_t* out, int64_t n);
+
+}  // namespace firesim

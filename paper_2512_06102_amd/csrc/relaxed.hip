@@ -1,0 +1,645 @@
+// relaxed.hip -- the relaxed (mean-field) fire-spread step, its soft-IoU
+// loss and its adjoint, for gradient-based calibration of the model's
+// parameters (JaxWildfire, arXiv 2512.06102, section 3, "Deterministic
+// (raw-probabilities) update", Eqs. 5-10; Eq. 4 for the ignition term).
+//
+// State per cell: U = p_un, B = p_burn.  One step:
+//   q_k(v) = 1 - exp(-gamma(v) phi(u_k, k)),  u_k = v - D_k   (Eqs. 1-4)
+//   P(v)   = 1 - prod_k (1 - q_k(v) B(u_k))
+//   N = U P,  U' = U - N,  B' = N + p_continue B             (Eqs. 5-10)
+//
+// Adjoint of one step (bars are adjoints, primes are step t+1):
+//   Nbar = B'bar - U'bar,   Ubar = U'bar + Nbar P,   Pbar = Nbar U,
+//   Bbar(u) = p_c B'bar(u) + sum_k c_k(u + D_k),  c_k(v) = Pbar(v) q_k(v) E_k(v),
+//   qbar_k(v) = Pbar(v) B(u_k) E_k(v),  E_k = prod_{j != k} (1 - q_j B(u_j))
+// (exclusive products from prefix and suffix products, no division since
+// q B can be 1), then through q = 1 - exp(-y), y = gamma phi (dq/dy =
+// exp(-y)), phi = p_base g(u) exp(x), x = wind exponent + alpha_s S,
+// gamma(v) = alpha_gamma g(v), g = (1 + veg[class]) (1 + den), to the 17
+// parameters.
+//
+// The forward works on 32 x 16 tiles, the adjoint on 32 x 8 tiles (256 lanes).
+// The adjoint's transpose stencil (Bbar(u) gathers from the targets around
+// u, and those need B two cells away) is done in one launch per step: the
+// tile stages B, g and E with a two-cell halo in LDS, phase 1 computes c_k
+// and the source-side fuel adjoint d_k for the tile plus a one-cell ring
+// into LDS, phase 2 gathers them for the tile's own cells.  Parameter
+// gradients are summed per lane, reduced per workgroup, and added to one of
+// 64 fp64 stripes with atomics; a last kernel sums the stripes.
+//
+// Precision: the recurrence amplifies small burning mass exponentially (in
+// the mean-field model every region reachable from a burning cell
+// eventually ignites), so an fp32 state underflows and rounds its way onto a
+// different trajectory within ~100 steps on a 128 x 128 grid.  U, B, the
+// adjoint and the gradient sums are therefore fp64; the per-edge factors
+// exp(x), phi, q = -expm1(-y) and exp(-y) are fp32 from the accurate library
+// routines (small rates keep their relative accuracy).
+#include <algorithm>
+#include <vector>
+
+#include "devmath.hpp"
+#include "relaxed.hpp"
+
+namespace firesim {
+namespace {
+
+struct RelaxedArgs {
+    float p_base, alpha_gamma, alpha_w1, alpha_w2, alpha_s, p_continue;
+    float inv_orth, inv_diag;
+};
+
+RelaxedArgs relaxed_args(const sim_params& p)
+{
+    RelaxedArgs a;
+    a.p_base = p.p_base;
+    a.alpha_gamma = p.alpha_gamma;
+    a.alpha_w1 = p.alpha_w1;
+    a.alpha_w2 = p.alpha_w2;
+    a.alpha_s = p.alpha_s;
+    a.p_continue = p.p_continue;
+    a.inv_orth = (float)(1.0 / (double)p.cell_size);
+    a.inv_diag = (float)(1.0 / ((double)p.cell_size * 1.41421356237309504880));
+    return a;
+}
+
+struct Veg11 {
+    float v[11];
+};
+
+constexpr int TW = kRelaxTW, TH = kRelaxTH;  // forward tile
+constexpr int BW = kRelaxBW, BH = kRelaxBH;  // adjoint tile
+
+__global__ __launch_bounds__(256) void relaxed_init_kernel(const uint8_t* __restrict__ st, int64_t n,
+                                                           double* __restrict__ U, double* __restrict__ B)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const uint8_t s = st[i];
+        U[i] = s == kFlammable ? 1.0 : 0.0;
+        B[i] = s == kBurning ? 1.0 : 0.0;
+    }
+}
+
+__global__ __launch_bounds__(256) void fuel_kernel(const uint8_t* __restrict__ cls,
+                                                   const float* __restrict__ den, int64_t n,
+                                                   Veg11 veg, float* __restrict__ g)
+{
+    __shared__ float sveg[11];
+    if (threadIdx.x < 11) sveg[threadIdx.x] = veg.v[threadIdx.x];
+    __syncthreads();
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        g[i] = (1.0f + sveg[cls[i]]) * (1.0f + den[i]);
+}
+
+__global__ __launch_bounds__(256) void copy_f64_kernel(double* __restrict__ dst,
+                                                       const double* __restrict__ src, int64_t n)
+{
+    const int64_t n2 = n >> 1;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2;
+         i += (int64_t)gridDim.x * blockDim.x)
+        reinterpret_cast<double2*>(dst)[i] = reinterpret_cast<const double2*>(src)[i];
+    for (int64_t i = (n2 << 1) + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+__global__ void fill_f64_kernel(double* p, int64_t n, double v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// Wind exponent of direction k at source cell u (per env from LDS, or per cell).
+template <bool WC>
+__device__ __forceinline__ float source_wind(int k, const float* ew, const float* wind, int64_t n_cells,
+                                             int64_t u, const RelaxedArgs& A)
+{
+    if constexpr (WC)
+        return wind_exponent(k, A.alpha_w1, A.alpha_w2, wind[u], wind[n_cells + u], wind[2 * n_cells + u]);
+    else
+        return ew[k];
+}
+
+// One relaxed forward step on a 32 x 16 tile.
+template <bool WC>
+__global__ __launch_bounds__(256) void relaxed_fwd_kernel(
+    const RelaxedTile* __restrict__ tiles, const EnvDev* __restrict__ envs, const float* __restrict__ g,
+    const float* __restrict__ E, const float* __restrict__ wind, int64_t n_cells, RelaxedArgs A,
+    const double* __restrict__ U, const double* __restrict__ B, double* __restrict__ Uo,
+    double* __restrict__ Bo)
+{
+    constexpr int EW = TW + 2, EH = TH + 2;
+    __shared__ double sB[EH * EW];
+    __shared__ float sg[EH * EW], sE[EH * EW];
+    __shared__ float ew[8];
+    const RelaxedTile td = tiles[blockIdx.x];
+    const EnvDev ed = envs[td.env];
+    const int H = ed.H, W = ed.W, tid = threadIdx.x;
+    for (int idx = tid; idx < EH * EW; idx += 256) {
+        const int gi = td.r0 - 1 + idx / EW, gj = td.c0 - 1 + idx % EW;
+        const bool in = gi >= 0 && gi < H && gj >= 0 && gj < W;
+        const int64_t v = ed.offset + (int64_t)gi * W + gj;
+        sB[idx] = in ? B[v] : 0.0;
+        sg[idx] = in ? g[v] : 0.0f;
+        sE[idx] = in ? E[v] : 0.0f;
+    }
+    if (!WC && tid < 8) ew[tid] = wind_exponent(tid, A.alpha_w1, A.alpha_w2, ed.V, ed.Vx, ed.Vy);
+    __syncthreads();
+    for (int idx = tid; idx < TW * TH; idx += 256) {
+        const int rr = idx / TW, cc = idx % TW;
+        const int gi = td.r0 + rr, gj = td.c0 + cc;
+        if (gi >= H || gj >= W) continue;
+        const int64_t v = ed.offset + (int64_t)gi * W + gj;
+        const int a = rr + 1, b = cc + 1;
+        const double Uv = U[v], Bv = sB[a * EW + b];
+        double prod = 1.0;
+        if (Uv != 0.0) {
+            const float gam = A.alpha_gamma * sg[a * EW + b];
+            const float Ev = sE[a * EW + b];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int s = (a - kDRow[k]) * EW + (b - kDCol[k]);
+                const double Bu = sB[s];
+                if (Bu == 0.0) continue;  // off-grid sources read 0
+                const int64_t u = v - (int64_t)kDRow[k] * W - kDCol[k];
+                const float x = source_wind<WC>(k, ew, wind, n_cells, u, A) +
+                                A.alpha_s * ((Ev - sE[s]) * ((k & 1) ? A.inv_diag : A.inv_orth));
+                const float phi = A.p_base * sg[s] * expf(x);
+                const float q = -expm1f(-(gam * phi));
+                prod = prod * (1.0 - (double)q * Bu);
+            }
+        }
+        const double N = Uv * (1.0 - prod);
+        Uo[v] = Uv - N;
+        Bo[v] = N + (double)A.p_continue * Bv;
+    }
+}
+
+// One adjoint step on a 32 x 8 tile: (U_t, B_t), (Ubar_{t+1}, Bbar_{t+1})
+// -> (Ubar_t, Bbar_t), and the step's contribution to the parameter gradient.
+template <bool WC>
+__global__ __launch_bounds__(256) void relaxed_bwd_kernel(
+    const RelaxedTile* __restrict__ tiles, const EnvDev* __restrict__ envs, const float* __restrict__ g,
+    const float* __restrict__ E, const float* __restrict__ wind, const uint8_t* __restrict__ cls,
+    const float* __restrict__ den, int64_t n_cells, RelaxedArgs A, const double* __restrict__ U,
+    const double* __restrict__ B, const double* __restrict__ gU1, const double* __restrict__ gB1,
+    double* __restrict__ gU0, double* __restrict__ gB0, double* __restrict__ stripes)
+{
+    constexpr int XW = BW + 4, XH = BH + 4;  // two-cell halo: sources of the ring
+    constexpr int EW = BW + 2, EH = BH + 2;  // one-cell ring: targets gathered by the tile
+    constexpr int NE = EW * EH;
+    __shared__ double sB[XH * XW];
+    __shared__ float sg[XH * XW], sE[XH * XW];
+    __shared__ double sC[8 * NE], sD[8 * NE];
+    __shared__ double sgt[BW * BH];
+    __shared__ float ew[8];
+    __shared__ double sred[4][17];
+    const RelaxedTile td = tiles[blockIdx.x];
+    const EnvDev ed = envs[td.env];
+    const int H = ed.H, W = ed.W, tid = threadIdx.x;
+    for (int idx = tid; idx < XH * XW; idx += 256) {
+        const int gi = td.r0 - 2 + idx / XW, gj = td.c0 - 2 + idx % XW;
+        const bool in = gi >= 0 && gi < H && gj >= 0 && gj < W;
+        const int64_t v = ed.offset + (int64_t)gi * W + gj;
+        sB[idx] = in ? B[v] : 0.0;
+        sg[idx] = in ? g[v] : 0.0f;
+        sE[idx] = in ? E[v] : 0.0f;
+    }
+    if (!WC && tid < 8) ew[tid] = wind_exponent(tid, A.alpha_w1, A.alpha_w2, ed.V, ed.Vx, ed.Vy);
+    __syncthreads();
+
+    double acc[17];
+#pragma unroll
+    for (int j = 0; j < 17; ++j) acc[j] = 0.0;
+    const double p_base = A.p_base, a_gamma = A.alpha_gamma;
+
+    // phase 1: every target of the tile and its one-cell ring
+    for (int idx = tid; idx < NE; idx += 256) {
+        const int er = idx / EW, ec = idx % EW;
+        const int gi = td.r0 - 1 + er, gj = td.c0 - 1 + ec;
+        const bool in = gi >= 0 && gi < H && gj >= 0 && gj < W;
+        if (!in) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) sC[k * NE + idx] = sD[k * NE + idx] = 0.0;
+            continue;
+        }
+        const int64_t v = ed.offset + (int64_t)gi * W + gj;
+        const int a = er + 1, b = ec + 1;
+        const double Uv = U[v];
+        const double gU = gU1[v], gB = gB1[v];
+        const double nbar = gB - gU;
+        const double Pbar = nbar * Uv;
+        const float gv = sg[a * XW + b], Ev = sE[a * XW + b];
+        const float gam = A.alpha_gamma * gv;
+        float q[8], em[8], ex[8];
+        double Bs[8], fac[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int s = (a - kDRow[k]) * XW + (b - kDCol[k]);
+            const int ui = gi - kDRow[k], uj = gj - kDCol[k];
+            Bs[k] = sB[s];
+            q[k] = 0.0f;
+            em[k] = 1.0f;
+            ex[k] = 0.0f;
+            if (ui >= 0 && ui < H && uj >= 0 && uj < W && (Pbar != 0.0 || Bs[k] != 0.0)) {
+                const int64_t u = v - (int64_t)kDRow[k] * W - kDCol[k];
+                const float x = source_wind<WC>(k, ew, wind, n_cells, u, A) +
+                                A.alpha_s * ((Ev - sE[s]) * ((k & 1) ? A.inv_diag : A.inv_orth));
+                ex[k] = expf(x);
+                const float y = gam * (A.p_base * sg[s] * ex[k]);
+                q[k] = -expm1f(-y);
+                em[k] = expf(-y);
+            }
+            fac[k] = 1.0 - (double)q[k] * Bs[k];
+        }
+        double pre[9], suf[9];
+        pre[0] = 1.0;
+        suf[8] = 1.0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) pre[k + 1] = pre[k] * fac[k];
+#pragma unroll
+        for (int k = 7; k >= 0; --k) suf[k] = suf[k + 1] * fac[k];
+        const double P = 1.0 - pre[8];
+        const bool interior = er >= 1 && er <= BH && ec >= 1 && ec <= BW;
+        double gt = 0.0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const double excl = pre[k] * suf[k + 1];
+            const double ybar = Pbar * Bs[k] * excl * (double)em[k];  // qbar dq/dy
+            sC[k * NE + idx] = Pbar * (double)q[k] * excl;
+            sD[k * NE + idx] = ybar * (double)gam * p_base * (double)ex[k];  // -> gbar(source)
+            if (interior && ybar != 0.0) {
+                const int s = (a - kDRow[k]) * XW + (b - kDCol[k]);
+                const int64_t u = v - (int64_t)kDRow[k] * W - kDCol[k];
+                const double gu = sg[s];
+                const double phi = p_base * gu * (double)ex[k];
+                float V, Vx, Vy;
+                if constexpr (WC) {
+                    V = wind[u];
+                    Vx = wind[n_cells + u];
+                    Vy = wind[2 * n_cells + u];
+                } else {
+                    V = ed.V;
+                    Vx = ed.Vx;
+                    Vy = ed.Vy;
+                }
+                const double xbar = ybar * (double)gam * phi;
+                acc[0] += ybar * (double)gam * gu * (double)ex[k];
+                acc[1] += xbar * (double)V;
+                acc[2] += xbar * (double)((kCos[k] * Vx + kSin[k] * Vy) - V);
+                acc[3] += xbar * ((double)(Ev - sE[s]) * (double)((k & 1) ? A.inv_diag : A.inv_orth));
+                acc[4] += ybar * phi * (double)gv;
+                gt += ybar * phi * a_gamma;
+            }
+        }
+        if (interior) {
+            gU0[v] = gU + nbar * P;
+            acc[5] += gB * sB[a * XW + b];
+            sgt[(er - 1) * BW + (ec - 1)] = gt;
+        }
+    }
+    __syncthreads();
+
+    // phase 2: gather the transpose stencil for the tile's own cells
+    for (int idx = tid; idx < BW * BH; idx += 256) {
+        const int rr = idx / BW, cc = idx % BW;
+        const int gi = td.r0 + rr, gj = td.c0 + cc;
+        if (gi >= H || gj >= W) continue;
+        const int64_t u = ed.offset + (int64_t)gi * W + gj;
+        const int er = rr + 1, ec = cc + 1;
+        double bsum = 0.0, dsum = 0.0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int e = (er + kDRow[k]) * EW + (ec + kDCol[k]);
+            bsum += sC[k * NE + e];
+            dsum += sD[k * NE + e];
+        }
+        gB0[u] = (double)A.p_continue * gB1[u] + bsum;
+        const double gb = (sgt[idx] + dsum) * (1.0 + (double)den[u]);
+        const int c = cls[u];
+#pragma unroll
+        for (int j = 0; j < 11; ++j) acc[6 + j] += (c == j) ? gb : 0.0;
+    }
+
+    // workgroup reduction of the 17 partial sums, then one fp64 stripe
+#pragma unroll
+    for (int j = 0; j < 17; ++j) {
+        double x = acc[j];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+        acc[j] = x;
+    }
+    if ((tid & 63) == 0) {
+#pragma unroll
+        for (int j = 0; j < 17; ++j) sred[tid >> 6][j] = acc[j];
+    }
+    __syncthreads();
+    if (tid < 17) {
+        const double total = sred[0][tid] + sred[1][tid] + sred[2][tid] + sred[3][tid];
+        if (total != 0.0) unsafeAtomicAdd(stripes + (blockIdx.x % kGradStripes) * 17 + tid, total);
+    }
+}
+
+__global__ void stripes_sum_kernel(const double* __restrict__ stripes, double* __restrict__ grad)
+{
+    const int j = threadIdx.x;
+    if (j >= 17) return;
+    double s = 0.0;
+    for (int r = 0; r < kGradStripes; ++r) s += stripes[r * 17 + j];
+    grad[j] = s;
+}
+
+// Per-env sums of the soft-IoU loss: I = sum S Y, sum S, sum Y.
+__global__ __launch_bounds__(256) void loss_sums_kernel(
+    const RelaxedTile* __restrict__ tiles, const EnvDev* __restrict__ envs,
+    const uint8_t* __restrict__ init_states, const double* __restrict__ U_T,
+    const uint8_t* __restrict__ target, double* __restrict__ acc, int32_t n_env)
+{
+    __shared__ double sred[4][3];
+    const RelaxedTile td = tiles[blockIdx.x];
+    const EnvDev ed = envs[td.env];
+    const int tid = threadIdx.x;
+    double sy = 0.0, ss = 0.0, yy = 0.0;
+    for (int idx = tid; idx < TW * TH; idx += 256) {
+        const int gi = td.r0 + idx / TW, gj = td.c0 + idx % TW;
+        if (gi >= ed.H || gj >= ed.W) continue;
+        const int64_t v = ed.offset + (int64_t)gi * ed.W + gj;
+        const double S = init_states[v] != kUnburnable ? 1.0 - U_T[v] : 0.0;
+        const double Y = target[v] ? 1.0 : 0.0;
+        sy += S * Y;
+        ss += S;
+        yy += Y;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        sy += __shfl_xor(sy, off);
+        ss += __shfl_xor(ss, off);
+        yy += __shfl_xor(yy, off);
+    }
+    if ((tid & 63) == 0) {
+        sred[tid >> 6][0] = sy;
+        sred[tid >> 6][1] = ss;
+        sred[tid >> 6][2] = yy;
+    }
+    __syncthreads();
+    if (tid < 3) {
+        const double t = sred[0][tid] + sred[1][tid] + sred[2][tid] + sred[3][tid];
+        if (t != 0.0) unsafeAtomicAdd(acc + tid * n_env + td.env, t);
+    }
+}
+
+__global__ __launch_bounds__(256) void loss_grad_kernel(
+    const RelaxedTile* __restrict__ tiles, const EnvDev* __restrict__ envs,
+    const uint8_t* __restrict__ init_states, const uint8_t* __restrict__ target,
+    const double* __restrict__ acc, int32_t n_env, double scale, double* __restrict__ gU_T)
+{
+    const RelaxedTile td = tiles[blockIdx.x];
+    const EnvDev ed = envs[td.env];
+    const double I = acc[td.env], Ssum = acc[n_env + td.env], Ysum = acc[2 * n_env + td.env];
+    const double D = Ssum + Ysum - I;
+    for (int idx = threadIdx.x; idx < TW * TH; idx += 256) {
+        const int gi = td.r0 + idx / TW, gj = td.c0 + idx % TW;
+        if (gi >= ed.H || gj >= ed.W) continue;
+        const int64_t v = ed.offset + (int64_t)gi * ed.W + gj;
+        double gv = 0.0;
+        if (D > 0.0 && init_states[v] != kUnburnable) {
+            const double Y = target[v] ? 1.0 : 0.0;
+            gv = scale * (Y * D - I * (1.0 - Y)) / (D * D);  // dL/dU = -dL/dS
+        }
+        gU_T[v] = gv;
+    }
+}
+
+__global__ void loss_final_kernel(const double* __restrict__ acc, int32_t n_env, float* __restrict__ loss)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n_env) return;
+    const double I = acc[e], D = acc[n_env + e] + acc[2 * n_env + e] - acc[e];
+    loss[e] = D > 0.0 ? (float)(1.0 - I / D) : 0.0f;
+}
+
+int blocks_for(int64_t n)
+{
+    int64_t b = (n + 255) / 256;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(b, 65536));
+}
+
+hipError_t copy_f64(hipStream_t s, double* dst, const double* src, int64_t n)
+{
+    hipLaunchKernelGGL(copy_f64_kernel, dim3(blocks_for((n >> 1) + 1)), dim3(256), 0, s, dst, src, n);
+    return hipGetLastError();
+}
+
+hipError_t fill_f64(hipStream_t s, double* p, int64_t n, double v)
+{
+    hipLaunchKernelGGL(fill_f64_kernel, dim3(blocks_for(n)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+// Workspace layout (all offsets 256-byte aligned).
+struct WsLayout {
+    size_t g, ckpt, seg, fwd, adj, stripes, total;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+WsLayout layout(int64_t n, int32_t T, int32_t k)
+{
+    const size_t d = 8 * (size_t)n;
+    const size_t n_ckpt = T > 0 ? (size_t)((T + k - 1) / k) : 1;
+    WsLayout L;
+    size_t o = 0;
+    L.g = o;
+    o = align256(o + 4 * (size_t)n);
+    L.ckpt = o;
+    o = align256(o + n_ckpt * 2 * d);
+    L.seg = o;
+    o = align256(o + (size_t)k * 2 * d);
+    L.fwd = o;
+    o = align256(o + 2 * d);
+    L.adj = o;
+    o = align256(o + 4 * d);
+    L.stripes = o;
+    o = align256(o + sizeof(double) * kGradStripes * 17);
+    L.total = o;
+    return L;
+}
+
+hipError_t fuel(hipStream_t s, const RelaxedInputs& in, const sim_params& p, float* g)
+{
+    Veg11 veg;
+    for (int c = 0; c < 11; ++c) veg.v[c] = p.veg[c];
+    hipLaunchKernelGGL(fuel_kernel, dim3(blocks_for(in.n_cells)), dim3(256), 0, s, in.cls, in.den,
+                       in.n_cells, veg, g);
+    return hipGetLastError();
+}
+
+hipError_t fwd_step(hipStream_t s, const RelaxedInputs& in, const RelaxedArgs& A, const float* g,
+                    const double* U, const double* B, double* Uo, double* Bo)
+{
+    if (in.wind)
+        hipLaunchKernelGGL(relaxed_fwd_kernel<true>, dim3(in.n_tiles), dim3(256), 0, s, in.tiles,
+                           in.envs, g, in.E, in.wind, in.n_cells, A, U, B, Uo, Bo);
+    else
+        hipLaunchKernelGGL(relaxed_fwd_kernel<false>, dim3(in.n_tiles), dim3(256), 0, s, in.tiles,
+                           in.envs, g, in.E, in.wind, in.n_cells, A, U, B, Uo, Bo);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int relaxed_prepare(RelaxedState& R, const std::vector<sim_env>& envs)
+{
+    if (R.d_tiles) return 0;
+    std::vector<RelaxedTile> tiles, btiles;
+    for (int32_t e = 0; e < (int32_t)envs.size(); ++e) {
+        for (int r0 = 0; r0 < envs[e].H; r0 += TH)
+            for (int c0 = 0; c0 < envs[e].W; c0 += TW) tiles.push_back(RelaxedTile{e, r0, c0, 0});
+        for (int r0 = 0; r0 < envs[e].H; r0 += BH)
+            for (int c0 = 0; c0 < envs[e].W; c0 += BW) btiles.push_back(RelaxedTile{e, r0, c0, 0});
+    }
+    if (hipMalloc(&R.d_tiles, tiles.size() * sizeof(RelaxedTile)) != hipSuccess) return -1;
+    if (hipMemcpy(R.d_tiles, tiles.data(), tiles.size() * sizeof(RelaxedTile), hipMemcpyHostToDevice) !=
+        hipSuccess)
+        return -1;
+    if (hipMalloc(&R.d_btiles, btiles.size() * sizeof(RelaxedTile)) != hipSuccess) return -1;
+    if (hipMemcpy(R.d_btiles, btiles.data(), btiles.size() * sizeof(RelaxedTile),
+                  hipMemcpyHostToDevice) != hipSuccess)
+        return -1;
+    R.n_tiles = (int32_t)tiles.size();
+    R.n_btiles = (int32_t)btiles.size();
+    R.n_env = (int32_t)envs.size();
+    if (hipMalloc(&R.d_loss_acc, sizeof(double) * 3 * R.n_env) != hipSuccess) return -1;
+    return 0;
+}
+
+void relaxed_free(RelaxedState& R)
+{
+    if (R.d_tiles) (void)hipFree(R.d_tiles);
+    if (R.d_btiles) (void)hipFree(R.d_btiles);
+    if (R.d_loss_acc) (void)hipFree(R.d_loss_acc);
+    R = RelaxedState{};
+}
+
+size_t relaxed_workspace_bytes(int64_t n_cells, int32_t T, int32_t ckpt_every)
+{
+    return layout(n_cells, T, ckpt_every).total;
+}
+
+hipError_t launch_relaxed_init(hipStream_t s, const uint8_t* init_states, int64_t n, double* U, double* B)
+{
+    hipLaunchKernelGGL(relaxed_init_kernel, dim3(blocks_for(n)), dim3(256), 0, s, init_states, n, U, B);
+    return hipGetLastError();
+}
+
+hipError_t relaxed_forward(hipStream_t s, const RelaxedInputs& in, const sim_params& p, double* U,
+                           double* B, int32_t T, int32_t k, void* workspace)
+{
+    if (T == 0) return hipSuccess;
+    const int64_t n = in.n_cells;
+    const WsLayout L = layout(n, T, k);
+    char* ws = static_cast<char*>(workspace);
+    float* g = reinterpret_cast<float*>(ws + L.g);
+    double* ckpt = reinterpret_cast<double*>(ws + L.ckpt);
+    double* pp = reinterpret_cast<double*>(ws + L.fwd);
+    const RelaxedArgs A = relaxed_args(p);
+    hipError_t e = fuel(s, in, p, g);
+    double* cu = U;
+    double* cb = B;
+    double* nu = pp;
+    double* nb = pp + n;
+    for (int32_t t = 0; t < T && e == hipSuccess; ++t) {
+        if (t % k == 0) {
+            double* slot = ckpt + (size_t)(t / k) * 2 * n;
+            e = copy_f64(s, slot, cu, n);
+            if (e == hipSuccess) e = copy_f64(s, slot + n, cb, n);
+        }
+        if (e == hipSuccess) e = fwd_step(s, in, A, g, cu, cb, nu, nb);
+        std::swap(cu, nu);
+        std::swap(cb, nb);
+    }
+    if (e == hipSuccess && cu != U) {
+        e = copy_f64(s, U, cu, n);
+        if (e == hipSuccess) e = copy_f64(s, B, cb, n);
+    }
+    return e;
+}
+
+hipError_t relaxed_loss(hipStream_t s, const RelaxedInputs& in, const uint8_t* init_states,
+                        const double* U_T, const uint8_t* target, float* loss, double* gU_T,
+                        double scale, RelaxedState& R)
+{
+    hipError_t e = fill_f64(s, R.d_loss_acc, (int64_t)3 * in.n_env, 0.0);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(loss_sums_kernel, dim3(in.n_tiles), dim3(256), 0, s, in.tiles, in.envs,
+                       init_states, U_T, target, R.d_loss_acc, in.n_env);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(loss_final_kernel, dim3((in.n_env + 255) / 256), dim3(256), 0, s, R.d_loss_acc,
+                       in.n_env, loss);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (gU_T) {
+        hipLaunchKernelGGL(loss_grad_kernel, dim3(in.n_tiles), dim3(256), 0, s, in.tiles, in.envs,
+                           init_states, target, R.d_loss_acc, in.n_env, scale, gU_T);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+hipError_t relaxed_backward(hipStream_t s, const RelaxedInputs& in, const sim_params& p,
+                            const double* gU_T, const double* gB_T, int32_t T, int32_t k,
+                            void* workspace, double* grad, RelaxedState& R)
+{
+    const int64_t n = in.n_cells;
+    const WsLayout L = layout(n, T, k);
+    char* ws = static_cast<char*>(workspace);
+    float* g = reinterpret_cast<float*>(ws + L.g);
+    double* ckpt = reinterpret_cast<double*>(ws + L.ckpt);
+    double* seg = reinterpret_cast<double*>(ws + L.seg);
+    double* adj = reinterpret_cast<double*>(ws + L.adj);
+    double* stripes = reinterpret_cast<double*>(ws + L.stripes);
+    const RelaxedArgs A = relaxed_args(p);
+    hipError_t e = fill_f64(s, stripes, (int64_t)kGradStripes * 17, 0.0);
+    if (e == hipSuccess) e = fuel(s, in, p, g);
+    double* cu = adj;  // adjoint at t+1: (Ubar, Bbar)
+    double* cb = adj + n;
+    double* nu = adj + 2 * n;  // adjoint at t
+    double* nb = adj + 3 * n;
+    if (e == hipSuccess) e = copy_f64(s, cu, gU_T, n);
+    if (e == hipSuccess) e = gB_T ? copy_f64(s, cb, gB_T, n) : fill_f64(s, cb, n, 0.0);
+    const int32_t n_seg = T > 0 ? (T + k - 1) / k : 0;
+    for (int32_t sg = n_seg - 1; sg >= 0 && e == hipSuccess; --sg) {
+        const int32_t t0 = sg * k, t1 = std::min(T, t0 + k);
+        const double* base = ckpt + (size_t)sg * 2 * n;
+        // states t0 .. t1-1 of the segment: slot 0 is the checkpoint itself
+        auto state_u = [&](int32_t j) -> const double* { return j == 0 ? base : seg + (size_t)j * 2 * n; };
+        auto state_b = [&](int32_t j) -> const double* {
+            return j == 0 ? base + n : seg + (size_t)j * 2 * n + n;
+        };
+        for (int32_t j = 1; j < t1 - t0 && e == hipSuccess; ++j)
+            e = fwd_step(s, in, A, g, state_u(j - 1), state_b(j - 1), seg + (size_t)j * 2 * n,
+                         seg + (size_t)j * 2 * n + n);
+        for (int32_t t = t1 - 1; t >= t0 && e == hipSuccess; --t) {
+            const int32_t j = t - t0;
+            if (in.wind)
+                hipLaunchKernelGGL(relaxed_bwd_kernel<true>, dim3(R.n_btiles), dim3(256), 0, s, R.d_btiles,
+                                   in.envs, g, in.E, in.wind, in.cls, in.den, in.n_cells, A, state_u(j),
+                                   state_b(j), cu, cb, nu, nb, stripes);
+            else
+                hipLaunchKernelGGL(relaxed_bwd_kernel<false>, dim3(R.n_btiles), dim3(256), 0, s, R.d_btiles,
+                                   in.envs, g, in.E, in.wind, in.cls, in.den, in.n_cells, A, state_u(j),
+                                   state_b(j), cu, cb, nu, nb, stripes);
+            e = hipGetLastError();
+            std::swap(cu, nu);
+            std::swap(cb, nb);
+        }
+    }
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(stripes_sum_kernel, dim3(1), dim3(64), 0, s, stripes, grad);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+}  // namespace firesim

@@ -1,0 +1,60 @@
+// relaxed.hpp -- host interface of the relaxed (mean-field) kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "../../include/firesim.h"
+#include "internal.hpp"
+
+namespace firesim {
+
+// Tiles of the relaxed kernels: forward 32 x 16 cells, adjoint 32 x 8 cells.
+constexpr int kRelaxTW = 32, kRelaxTH = 16;
+constexpr int kRelaxBW = 32, kRelaxBH = 8;
+constexpr int kGradStripes = 64;  // fp64 partial-sum rows of the parameter gradient
+
+struct RelaxedTile {
+    int32_t env, r0, c0, pad;
+};
+
+// Per-handle state of the relaxed path (built on first use).
+struct RelaxedState {
+    RelaxedTile* d_tiles = nullptr;   // forward / loss tiles
+    int32_t n_tiles = 0;
+    RelaxedTile* d_btiles = nullptr;  // adjoint tiles
+    int32_t n_btiles = 0;
+    double* d_loss_acc = nullptr;  // [3][n_env]: sum S Y, sum S, sum Y
+    int32_t n_env = 0;
+};
+
+struct RelaxedInputs {
+    const RelaxedTile* tiles;
+    int32_t n_tiles;
+    const EnvDev* envs;
+    int32_t n_env;
+    const uint8_t* cls;
+    const float* den;
+    const float* E;
+    const float* wind;  // [3][n_cells] or nullptr
+    int64_t n_cells;
+};
+
+int relaxed_prepare(RelaxedState& R, const std::vector<sim_env>& envs);
+void relaxed_free(RelaxedState& R);
+size_t relaxed_workspace_bytes(int64_t n_cells, int32_t T, int32_t ckpt_every);
+
+hipError_t launch_relaxed_init(hipStream_t s, const uint8_t* init_states, int64_t n, double* U,
+                               double* B);
+hipError_t relaxed_forward(hipStream_t s, const RelaxedInputs& in, const sim_params& p, double* U,
+                           double* B, int32_t T, int32_t ckpt_every, void* workspace);
+hipError_t relaxed_loss(hipStream_t s, const RelaxedInputs& in, const uint8_t* init_states,
+                        const double* U_T, const uint8_t* target, float* loss, double* gU_T,
+                        double scale, RelaxedState& R);
+hipError_t relaxed_backward(hipStream_t s, const RelaxedInputs& in, const sim_params& p,
+                            const double* gU_T, const double* gB_T, int32_t T, int32_t ckpt_every,
+                            void* workspace, double* grad, RelaxedState& R);
+
+}  // namespace firesim

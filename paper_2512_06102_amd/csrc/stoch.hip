@@ -1,0 +1,500 @@
+// stoch.hip -- the stochastic fire-spread step and the set-up kernels.
+//
+// Model (JaxWildfire, arXiv 2512.06102, section 3): a FLAMMABLE cell v
+// ignites with p = 1 - exp(-gamma(v) lambda(v)) (Eq. 4), where lambda sums
+// phi(u, D_{u->v}) over its BURNING Moore neighbours u (Eq. 3, with the wind
+// and slope factors of Eqs. 1-2 evaluated at the source u), and gamma(v) =
+// alpha_gamma (1 + mu_veg(v)) (1 + mu_den(v)); a BURNING cell keeps burning
+// with p_continue, else becomes BURNT ("Stochastic update").  All draws of a
+// step use the state before it (synchronous update).
+//
+// Layout and data flow of one step (one launch):
+//  * a workgroup (256 lanes, 4 wave64s) owns a tile of `width` (64/128/256)
+//    columns by (1024/width) * RT rows of one env; each lane owns a 4-cell
+//    column group (one dword of uint8 states) in RT rows;
+//  * the tile's states plus a one-cell halo are staged in LDS (dword rows with
+//    a pad dword on each side so a lane reads its 6-cell neighbourhood row as
+//    three aligned dwords);
+//  * burning / flammable flags are computed four cells at a time with byte
+//    SWAR on the state dwords; lanes with neither a burning cell nor a
+//    flammable cell next to a burning one do no arithmetic at all;
+//  * front lanes draw one Philox block for their four cells and evaluate phi
+//    only for their burning neighbours (fuel and elevation of neighbours come
+//    through the cache; they are the tile's own or its neighbours' lines);
+//  * the new dword is stored, and the BURNING count is reduced per wave, per
+//    workgroup in LDS, and added to the env's counter with one atomic.
+// Workgroup b runs on XCD b % 8; tiles are dealt so that each XCD walks a
+// contiguous run of the tile list (neighbouring tiles share halo lines in
+// that XCD's L2).
+#include "devmath.hpp"
+#include "internal.hpp"
+
+namespace firesim {
+namespace {
+
+// Byte-lane flags (bit 8b set for byte b); state codes are 0..3.
+__device__ __forceinline__ uint32_t burning_flags(uint32_t w) { return (w >> 1) & ~w & 0x01010101u; }
+__device__ __forceinline__ uint32_t flammable_flags(uint32_t w) { return w & ~(w >> 1) & 0x01010101u; }
+// Gather the four byte-lane flags into bits 0..3.
+__device__ __forceinline__ uint32_t pack4(uint32_t f) { return (f | (f >> 7) | (f >> 14) | (f >> 21)) & 0xFu; }
+
+// Burning bits of a 6-cell row window: bit m <-> column (first own column - 1 + m).
+__device__ __forceinline__ uint32_t row_window(uint32_t left, uint32_t own, uint32_t right)
+{
+    return ((burning_flags(left) >> 24) & 1u) | (pack4(burning_flags(own)) << 1) |
+           ((burning_flags(right) & 1u) << 5);
+}
+
+// Burning-neighbour mask of own cell c: bit k set iff the source v - D_k burns.
+__device__ __forceinline__ uint32_t direction_mask(uint32_t up6, uint32_t md6, uint32_t dn6, int c)
+{
+    return ((md6 >> c) & 1u) | (((dn6 >> c) & 1u) << 1) | (((dn6 >> (c + 1)) & 1u) << 2) |
+           (((dn6 >> (c + 2)) & 1u) << 3) | (((md6 >> (c + 2)) & 1u) << 4) |
+           (((up6 >> (c + 2)) & 1u) << 5) | (((up6 >> (c + 1)) & 1u) << 6) |
+           (((up6 >> c) & 1u) << 7);
+}
+
+__device__ __forceinline__ float comp(const float4& v, int c)
+{
+    return c == 0 ? v.x : (c == 1 ? v.y : (c == 2 ? v.z : v.w));
+}
+__device__ __forceinline__ uint32_t compu(const uint4& v, int c)
+{
+    return c == 0 ? v.x : (c == 1 ? v.y : (c == 2 ? v.z : v.w));
+}
+
+// p_ignite of target cell v (packed index) from its burning-neighbour mask.
+template <bool WIND_CELL>
+__device__ __forceinline__ float ignite_prob(uint32_t nbk, int64_t v, int W, float g_v, float E_v,
+                                             const StaticFields& F, const StepArgs& A,
+                                             const float* ew)
+{
+    float lambda = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        if (!((nbk >> k) & 1u)) continue;
+        const int64_t u = v - (int64_t)kDRow[k] * W - kDCol[k];
+        const float g_u = F.g[u];
+        const float E_u = F.E[u];
+        float wexp;
+        if constexpr (WIND_CELL)
+            wexp = wind_exponent(k, A.alpha_w1, A.alpha_w2, F.wind[u], F.wind[F.n_cells + u],
+                                 F.wind[2 * F.n_cells + u]);
+        else
+            wexp = ew[k];
+        const float slope = (E_v - E_u) * ((k & 1) ? A.inv_run_diag : A.inv_run_orth);
+        const float x = wexp + A.alpha_s * slope;
+        lambda = lambda + (A.p_base * g_u) * exp_c(x);
+    }
+    if (!(lambda > 0.0f)) return 0.0f;
+    const float gamma = A.alpha_gamma * g_v;
+    return 1.0f - exp_c(-(gamma * lambda));
+}
+
+__device__ __forceinline__ void keep_loaded(const float4& v)
+{
+    asm volatile("" ::"v"(v.x), "v"(v.y), "v"(v.z), "v"(v.w));
+}
+
+template <int RT>
+constexpr int lds_dwords()
+{
+    // (tile rows + 2) x (lanes per row + 2) for the three tile widths
+    constexpr int a = (16 * RT + 2) * 18, b = (8 * RT + 2) * 34, c = (4 * RT + 2) * 66;
+    return a > b ? (a > c ? a : c) : (b > c ? b : c);
+}
+
+template <bool ALIGNED, bool WIND_CELL, int RT, bool SKIP>
+__global__ __launch_bounds__(kBlock) void stoch_step_kernel(
+    const TileDesc* __restrict__ tiles, int32_t n_tiles, int32_t tiles_per_xcd,
+    const EnvDev* __restrict__ envs, StaticFields F, StepArgs A, const uint8_t* __restrict__ src,
+    uint8_t* __restrict__ dst, const uint32_t* __restrict__ t_base, uint32_t step,
+    const int32_t* __restrict__ actions_row, int32_t* __restrict__ counts_row)
+{
+    __shared__ uint32_t lds[lds_dwords<RT>()];
+    __shared__ float lds_ew[8];
+    __shared__ int32_t lds_cnt[kBlock / 64];
+
+    const int b = blockIdx.x;
+    const int tile = (b & 7) * tiles_per_xcd + (b >> 3);
+    if (tile >= n_tiles) return;
+    const TileDesc td = tiles[tile];
+    const EnvDev ed = envs[td.env];
+    const int H = ed.H, W = ed.W;
+    const int gx_log = td.width == 256 ? 6 : (td.width == 128 ? 5 : 4);
+    const int GX = 1 << gx_log;          // lanes per tile row
+    const int RP = kBlock >> gx_log;     // rows per pass
+    const int TH = RP * RT;              // tile rows
+    const int SD = GX + 2;               // LDS dwords per row
+    const int nrow = TH + 2;
+    const int tid = threadIdx.x;
+    const int tx = tid & (GX - 1), ty = tid >> gx_log;
+    const uint32_t t = *t_base + step;
+    const int64_t base = ed.offset;
+
+    // -- stage the tile's states (one-cell halo; off-grid cells read as 0) --
+    for (int idx = tid; idx < nrow * GX; idx += kBlock) {
+        const int rr = idx >> gx_log, q = idx & (GX - 1);
+        const int gi = td.r0 - 1 + rr, gj = td.c0 + 4 * q;
+        uint32_t v = 0;
+        if (gi >= 0 && gi < H && gj < W) {
+            const uint8_t* p = src + base + (int64_t)gi * W + gj;
+            if constexpr (ALIGNED) {
+                v = *reinterpret_cast<const uint32_t*>(p);
+            } else {
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    if (gj + c < W) v |= (uint32_t)p[c] << (8 * c);
+            }
+        }
+        lds[rr * SD + 1 + q] = v;
+    }
+    for (int idx = tid; idx < 2 * nrow; idx += kBlock) {
+        const int rr = idx >> 1, right = idx & 1;
+        const int gi = td.r0 - 1 + rr, gj = right ? td.c0 + td.width : td.c0 - 1;
+        uint32_t v = 0;
+        if (gi >= 0 && gi < H && gj >= 0 && gj < W) v = src[base + (int64_t)gi * W + gj];
+        if (right)
+            lds[rr * SD + GX + 1] = v;
+        else
+            lds[rr * SD] = v << 24;
+    }
+    if constexpr (!WIND_CELL) {
+        if (tid < 8) lds_ew[tid] = wind_exponent(tid, A.alpha_w1, A.alpha_w2, ed.V, ed.Vx, ed.Vy);
+    }
+
+    // -- own fuel and elevation: every cell reads its 8 bytes (4 + 4, plus
+    //    12 of per-cell wind) each step unless SKIP defers them to front lanes
+    float4 gv[RT], ev[RT];
+    const int gj0 = td.c0 + 4 * tx;
+#pragma unroll
+    for (int m = 0; m < RT; ++m) {
+        gv[m] = make_float4(0.f, 0.f, 0.f, 0.f);
+        ev[m] = gv[m];
+        if constexpr (!SKIP) {
+            const int gi = td.r0 + ty + m * RP;
+            if (gi < H && gj0 < W) {
+                const int64_t c0 = base + (int64_t)gi * W + gj0;
+                if constexpr (ALIGNED) {
+                    gv[m] = *reinterpret_cast<const float4*>(F.g + c0);
+                    ev[m] = *reinterpret_cast<const float4*>(F.E + c0);
+                    if constexpr (WIND_CELL) {
+                        keep_loaded(*reinterpret_cast<const float4*>(F.wind + c0));
+                        keep_loaded(*reinterpret_cast<const float4*>(F.wind + F.n_cells + c0));
+                        keep_loaded(*reinterpret_cast<const float4*>(F.wind + 2 * F.n_cells + c0));
+                    }
+                } else {
+                    float tg[4] = {0.f, 0.f, 0.f, 0.f}, te[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int c = 0; c < 4; ++c)
+                        if (gj0 + c < W) {
+                            tg[c] = F.g[c0 + c];
+                            te[c] = F.E[c0 + c];
+                        }
+                    gv[m] = make_float4(tg[0], tg[1], tg[2], tg[3]);
+                    ev[m] = make_float4(te[0], te[1], te[2], te[3]);
+                }
+                keep_loaded(gv[m]);
+                keep_loaded(ev[m]);
+            }
+        }
+    }
+    __syncthreads();
+
+    // -- suppression drop on the staged tile (halo included), before the step
+    const int32_t act = actions_row ? actions_row[td.env] : -1;
+    if (act >= 0) {
+        const int ar = (act >> 16) & 0x7FFF, ac = act & 0xFFFF;
+        if (ar < H && ac < W) {
+            if (tid < 25) {
+                const int gi = ar - 2 + tid / 5, gj = ac - 2 + tid % 5;
+                const int rr = gi - (td.r0 - 1), cc = gj - td.c0;
+                if (gi >= 0 && gi < H && gj >= 0 && gj < W && rr >= 0 && rr < nrow && cc >= -1 &&
+                    cc <= td.width) {
+                    uint8_t* pb = reinterpret_cast<uint8_t*>(lds) + rr * SD * 4 + 4 + cc;
+                    const uint8_t s0 = *pb;
+                    if (s0 == kFlammable || s0 == kBurning) *pb = kUnburnable;
+                }
+            }
+            __syncthreads();
+        }
+    }
+
+    // -- the step --
+    int cnt = 0;
+    const uint2 key = make_uint2(A.key0, A.key1);
+#pragma unroll
+    for (int m = 0; m < RT; ++m) {
+        const int lr = ty + m * RP;
+        const int gi = td.r0 + lr;
+        if (!(gi < H && gj0 < W)) continue;
+        const uint32_t* up = lds + lr * SD + tx;
+        const uint32_t* md = up + SD;
+        const uint32_t* dn = md + SD;
+        const uint32_t own = md[1];
+        const uint32_t up6 = row_window(up[0], up[1], up[2]);
+        const uint32_t md6 = row_window(md[0], own, md[2]);
+        const uint32_t dn6 = row_window(dn[0], dn[1], dn[2]);
+        const uint32_t ud = up6 | dn6;
+        const uint32_t near = (ud | (ud >> 1) | (ud >> 2) | md6 | (md6 >> 2)) & 0xFu;
+        const uint32_t burn = pack4(burning_flags(own));
+        const uint32_t front = pack4(flammable_flags(own)) & near;
+        uint32_t out = own;
+        if (front | burn) {
+            const int64_t n0 = (int64_t)gi * W + gj0;  // env-local index of own cell 0
+            const int64_t v0 = base + n0;
+            const uint4 w0 = philox4x32_10(make_uint4((uint32_t)(n0 >> 2), t, ed.env_id, 0u), key);
+            uint4 w1 = w0;
+            if constexpr (!ALIGNED) {
+                if (((n0 + 3) >> 2) != (n0 >> 2))
+                    w1 = philox4x32_10(make_uint4((uint32_t)((n0 + 3) >> 2), t, ed.env_id, 0u), key);
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const bool is_burn = (burn >> c) & 1u, is_front = (front >> c) & 1u;
+                if (!(is_burn || is_front)) continue;
+                uint32_t word;
+                if constexpr (ALIGNED) {
+                    word = compu(w0, c);
+                } else {
+                    const int64_t n = n0 + c;
+                    word = (n >> 2) == (n0 >> 2) ? compu(w0, (int)(n & 3)) : compu(w1, (int)(n & 3));
+                }
+                const float u = word_to_uniform(word);
+                uint32_t next;
+                if (is_burn) {
+                    next = (u < A.p_continue) ? kBurning : kBurnt;
+                } else {
+                    float g_v, E_v;
+                    if constexpr (SKIP) {
+                        g_v = F.g[v0 + c];
+                        E_v = F.E[v0 + c];
+                    } else {
+                        g_v = comp(gv[m], c);
+                        E_v = comp(ev[m], c);
+                    }
+                    const float p = ignite_prob<WIND_CELL>(direction_mask(up6, md6, dn6, c), v0 + c,
+                                                           W, g_v, E_v, F, A, lds_ew);
+                    next = (u < p) ? kBurning : kFlammable;
+                }
+                out = (out & ~(0xFFu << (8 * c))) | (next << (8 * c));
+            }
+        }
+        uint8_t* o = dst + base + (int64_t)gi * W + gj0;
+        if constexpr (ALIGNED) {
+            *reinterpret_cast<uint32_t*>(o) = out;
+        } else {
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                if (gj0 + c < W) o[c] = (uint8_t)(out >> (8 * c));
+        }
+        cnt += __popc(pack4(burning_flags(out)));
+    }
+
+    // -- BURNING count of the env after the step --
+    if (counts_row) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
+        if ((tid & 63) == 0) lds_cnt[tid >> 6] = cnt;
+        __syncthreads();
+        if (tid == 0) {
+            const int total = lds_cnt[0] + lds_cnt[1] + lds_cnt[2] + lds_cnt[3];
+            if (total) atomicAdd(counts_row + td.env, total);
+        }
+    }
+}
+
+__global__ void init_cells_kernel(int64_t n, const uint8_t* __restrict__ cls,
+                                  const float* __restrict__ den, const float* __restrict__ elev,
+                                  const float* __restrict__ wind_in, float v0, float v1, float v2,
+                                  float v3, float v4, float v5, float v6, float v7, float v8,
+                                  float v9, float v10, uint32_t mask, float* __restrict__ g,
+                                  float* __restrict__ E, uint8_t* __restrict__ cls_out,
+                                  float* __restrict__ den_out, float* __restrict__ wind_out,
+                                  uint8_t* __restrict__ states)
+{
+    __shared__ float veg[11];
+    if (threadIdx.x == 0) {
+        veg[0] = v0; veg[1] = v1; veg[2] = v2; veg[3] = v3; veg[4] = v4; veg[5] = v5;
+        veg[6] = v6; veg[7] = v7; veg[8] = v8; veg[9] = v9; veg[10] = v10;
+    }
+    __syncthreads();
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t c = cls[i] > 10 ? 10u : cls[i];
+        const float d = den[i];
+        g[i] = (1.0f + veg[c]) * (1.0f + d);
+        E[i] = elev[i];
+        cls_out[i] = (uint8_t)c;
+        den_out[i] = d;
+        states[i] = ((mask >> c) & 1u) ? kUnburnable : kFlammable;
+        if (wind_in) {
+            wind_out[i] = wind_in[i];
+            wind_out[n + i] = wind_in[n + i];
+            wind_out[2 * n + i] = wind_in[2 * n + i];
+        }
+    }
+}
+
+__global__ void ignite_kernel(const int32_t* __restrict__ ign, int32_t n_ign,
+                              const EnvDev* __restrict__ envs, uint8_t* __restrict__ states)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n_ign) return;
+    const EnvDev e = envs[ign[3 * q]];
+    const int64_t idx = e.offset + (int64_t)ign[3 * q + 1] * e.W + ign[3 * q + 2];
+    if (states[idx] == kFlammable) states[idx] = kBurning;
+}
+
+__global__ void fill_i32_kernel(int32_t* p, int64_t n, int32_t v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void copy_u8_kernel(uint8_t* __restrict__ dst, const uint8_t* __restrict__ src, int64_t n)
+{
+    const int64_t n16 = n >> 4;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16;
+         i += (int64_t)gridDim.x * blockDim.x)
+        reinterpret_cast<uint4*>(dst)[i] = reinterpret_cast<const uint4*>(src)[i];
+    for (int64_t i = (n16 << 4) + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+__global__ void set_u32_kernel(uint32_t* p, uint32_t v) { *p = v; }
+
+__global__ void debug_exp_kernel(const float* x, float* y, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = exp_c(x[i]);
+}
+
+__global__ void debug_philox_kernel(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const uint4 r = philox4x32_10(make_uint4(ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3]),
+                                      make_uint2(key[2 * i], key[2 * i + 1]));
+        out[4 * i] = r.x;
+        out[4 * i + 1] = r.y;
+        out[4 * i + 2] = r.z;
+        out[4 * i + 3] = r.w;
+    }
+}
+
+int grid_for(int64_t n, int block)
+{
+    int64_t g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > 65536) g = 65536;
+    return (int)g;
+}
+
+template <bool AL, bool WC, int RT, bool SK>
+hipError_t launch_variant(hipStream_t s, const StepLaunch& L, const uint8_t* src, uint8_t* dst,
+                          const uint32_t* t_base, uint32_t step, const int32_t* act, int32_t* cnt)
+{
+    const int32_t per_xcd = (L.n_tiles + 7) / 8;
+    hipLaunchKernelGGL((stoch_step_kernel<AL, WC, RT, SK>), dim3(8 * per_xcd), dim3(kBlock), 0, s,
+                       L.tiles, L.n_tiles, per_xcd, L.envs, L.fields, L.args, src, dst, t_base,
+                       step, act, cnt);
+    return hipGetLastError();
+}
+
+template <bool AL, bool WC, bool SK>
+hipError_t launch_rt(hipStream_t s, const StepLaunch& L, const uint8_t* src, uint8_t* dst,
+                     const uint32_t* t_base, uint32_t step, const int32_t* act, int32_t* cnt)
+{
+    switch (L.rows_per_thread) {
+    case 1: return launch_variant<AL, WC, 1, SK>(s, L, src, dst, t_base, step, act, cnt);
+    case 2: return launch_variant<AL, WC, 2, SK>(s, L, src, dst, t_base, step, act, cnt);
+    case 8: return launch_variant<AL, WC, 8, SK>(s, L, src, dst, t_base, step, act, cnt);
+    default: return launch_variant<AL, WC, 4, SK>(s, L, src, dst, t_base, step, act, cnt);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_stoch_step(hipStream_t s, const StepLaunch& L, const uint8_t* src, uint8_t* dst,
+                             const uint32_t* t_base, uint32_t step, const int32_t* actions_row,
+                             int32_t* counts_row)
+{
+    const bool wc = L.fields.wind != nullptr;
+    if (L.aligned) {
+        if (wc)
+            return L.skip_static
+                       ? launch_rt<true, true, true>(s, L, src, dst, t_base, step, actions_row, counts_row)
+                       : launch_rt<true, true, false>(s, L, src, dst, t_base, step, actions_row, counts_row);
+        return L.skip_static
+                   ? launch_rt<true, false, true>(s, L, src, dst, t_base, step, actions_row, counts_row)
+                   : launch_rt<true, false, false>(s, L, src, dst, t_base, step, actions_row, counts_row);
+    }
+    if (wc)
+        return L.skip_static
+                   ? launch_rt<false, true, true>(s, L, src, dst, t_base, step, actions_row, counts_row)
+                   : launch_rt<false, true, false>(s, L, src, dst, t_base, step, actions_row, counts_row);
+    return L.skip_static
+               ? launch_rt<false, false, true>(s, L, src, dst, t_base, step, actions_row, counts_row)
+               : launch_rt<false, false, false>(s, L, src, dst, t_base, step, actions_row, counts_row);
+}
+
+hipError_t launch_init_cells(hipStream_t s, int64_t n, const uint8_t* cls, const float* den,
+                             const float* elev, const float* wind_in, const float veg[11],
+                             uint32_t mask, float* g, float* E, uint8_t* cls_out, float* den_out,
+                             float* wind_out, uint8_t* states)
+{
+    hipLaunchKernelGGL(init_cells_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, n, cls, den, elev,
+                       wind_in, veg[0], veg[1], veg[2], veg[3], veg[4], veg[5], veg[6], veg[7],
+                       veg[8], veg[9], veg[10], mask, g, E, cls_out, den_out, wind_out, states);
+    return hipGetLastError();
+}
+
+hipError_t launch_ignite(hipStream_t s, const int32_t* ign, int32_t n_ign, const EnvDev* envs,
+                         uint8_t* states)
+{
+    if (n_ign <= 0) return hipSuccess;
+    hipLaunchKernelGGL(ignite_kernel, dim3((n_ign + 255) / 256), dim3(256), 0, s, ign, n_ign, envs,
+                       states);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(hipStream_t s, int32_t* p, int64_t n, int32_t v)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_u8(hipStream_t s, uint8_t* dst, const uint8_t* src, int64_t n)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(copy_u8_kernel, dim3(grid_for((n >> 4) + 1, 256)), dim3(256), 0, s, dst, src, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_u32(hipStream_t s, uint32_t* p, uint32_t v)
+{
+    hipLaunchKernelGGL(set_u32_kernel, dim3(1), dim3(1), 0, s, p, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_debug_exp(hipStream_t s, const float* x, float* y, int64_t n)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(debug_exp_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, x, y, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_debug_philox(hipStream_t s, const uint32_t* ctr, const uint32_t* key,
+                               uint32_t* out, int64_t n)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(debug_philox_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, ctr, key, out, n);
+    return hipGetLastError();
+}
+
+}  // namespace firesim

@@ -1,0 +1,159 @@
+"""GPU parity of the relaxed forward, soft-IoU loss and adjoint against the
+fp64 oracle.
+
+Tolerances (fp32 kernels against an fp64 reference):
+  forward:   max |U_T - U_T,64| <= 1e-5
+  gradient:  ||g - g64||_inf <= 1e-4 ||g64||_inf, and |g_i - g64_i| <= 1e-4 |g64_i|
+             wherever |g64_i| >= 1e-2 ||g64||_inf; veg entries of unburnable
+             classes exactly 0.
+The oracle runs on the fp32-rounded parameters the kernels receive.
+"""
+import numpy as np
+import pytest
+import torch
+
+import firegen
+import oracle
+from oracle import relaxed64
+
+pytestmark = pytest.mark.gpu
+
+fs = pytest.importorskip("paper_2512_06102_amd")
+
+
+def _params(seed=0, **kw):
+    base = dict(p_base=0.5, alpha_w1=0.05, alpha_w2=0.12, alpha_s=3.0, alpha_gamma=1.1,
+                p_continue=0.55,
+                veg=tuple(float(v) for v in firegen.veg_table(np.random.default_rng(seed))))
+    base.update(kw)
+    return firegen.Params(**base)
+
+
+def _target(batch, params, T, seed):
+    """Binary scar (BURNING or BURNT) of an oracle stochastic run."""
+    ref = oracle.Sim(batch, params, seed=seed)
+    ref.step(T, threads=8)
+    return ((ref.states == firegen.BURNING) | (ref.states == firegen.BURNT)).astype(np.uint8)
+
+
+def _theta32(params):
+    return relaxed64.theta_from_params(params).astype(np.float32).astype(np.float64)
+
+
+def _gpu_loss_grad(batch, params, Y, T, k):
+    sim = fs.FireSim.from_batch(batch, params, seed=0)
+    p = fs.make_params(params)
+    p.unburnable_mask = batch.unburnable_mask
+    U, B = sim.relaxed_init()
+    ws = sim.relaxed_workspace(T, k)
+    sim.relaxed_fwd(p, U, B, T, k, ws)
+    loss, gU = sim.relaxed_loss(U, torch.from_numpy(Y).cuda(), scale=1.0 / batch.n_env)
+    grad = sim.relaxed_bwd(p, gU, None, T, k, ws)
+    torch.cuda.synchronize()
+    return U.cpu().numpy(), B.cpu().numpy(), loss.cpu().numpy(), grad.cpu().numpy()
+
+
+def _check_grad(g, g64):
+    scale = np.max(np.abs(g64))
+    assert scale > 0
+    assert np.max(np.abs(g - g64)) <= 1e-4 * scale, (g, g64)
+    big = np.abs(g64) >= 1e-2 * scale
+    rel = np.abs(g - g64)[big] / np.abs(g64)[big]
+    assert np.all(rel <= 1e-4), (np.array(relaxed64.THETA_NAMES)[big], rel)
+    for c in firegen.UNBURNABLE_CLASSES:
+        assert g[6 + c] == 0.0
+
+
+def _oracle(batch, params, Y, T):
+    Ys = [batch.env_view(Y, e).astype(bool) for e in range(batch.n_env)]
+    return relaxed64.loss_and_grad(batch, _theta32(params), T, Ys, cell_size=params.cell_size)
+
+
+def test_relaxed_init_matches_fire_state():
+    batch = firegen.landscape_batch(2, [(40, 33), (64, 64)])
+    sim = fs.FireSim.from_batch(batch, _params())
+    U, B = sim.relaxed_init()
+    st = sim.states.cpu().numpy()
+    assert np.array_equal(U.cpu().numpy(), (st == firegen.FLAMMABLE).astype(np.float32))
+    assert np.array_equal(B.cpu().numpy(), (st == firegen.BURNING).astype(np.float32))
+
+
+@pytest.mark.parametrize("per_cell_wind", [False, True])
+def test_forward_loss_and_gradient_small(per_cell_wind):
+    batch = firegen.landscape_batch(3, [(40, 56), (33, 17), (64, 64), (5, 70)],
+                                    per_cell_wind=per_cell_wind, elev_max=80.0)
+    params = _params(1)
+    T, k = 24, 5
+    Y = _target(batch, params, T, 4)
+    U, B, loss, grad = _gpu_loss_grad(batch, params, Y, T, k)
+    L64, g64, finals = _oracle(batch, params, Y, T)
+    for e in range(batch.n_env):
+        assert np.max(np.abs(batch.env_view(U, e) - finals[e][0])) <= 1e-5
+        assert np.max(np.abs(batch.env_view(B, e) - finals[e][1])) <= 1e-5
+    assert abs(float(loss.mean()) - L64) <= 1e-5
+    _check_grad(grad, g64)
+
+
+@pytest.mark.parametrize("k", [1, 3, 7, 30])
+def test_checkpoint_interval_does_not_change_gradient(k):
+    batch = firegen.landscape_batch(5, [(48, 48), (32, 80)], elev_max=60.0)
+    params = _params(2)
+    T = 21
+    Y = _target(batch, params, T, 6)
+    _, _, _, g_ref = _gpu_loss_grad(batch, params, Y, T, 21)
+    _, _, _, g = _gpu_loss_grad(batch, params, Y, T, k)
+    assert np.allclose(g, g_ref, rtol=1e-6, atol=1e-9 * np.max(np.abs(g_ref)))
+
+
+def test_autograd_function():
+    batch = firegen.landscape_batch(7, [(36, 36), (24, 60)], elev_max=60.0)
+    params = _params(3)
+    T = 15
+    Y = _target(batch, params, T, 8)
+    sim = fs.FireSim.from_batch(batch, params, seed=0)
+    theta = torch.tensor(_theta32(params), dtype=torch.float64, requires_grad=True)
+    loss = fs.RelaxedCalibrationLoss.apply(theta, sim, torch.from_numpy(Y).cuda(), T, 4)
+    (2.0 * loss).backward()
+    L64, g64, _ = _oracle(batch, params, Y, T)
+    assert abs(loss.item() - L64) <= 1e-5
+    _check_grad(theta.grad.numpy() / 2.0, g64)
+
+
+def test_saturated_relaxed_is_deterministic_ca():
+    """p_base 64, p_continue 0: B is the Chebyshev ring, U zero inside (exact in fp32)."""
+    batch = firegen.uniform_batch(33, 33)
+    params = firegen.Params(p_base=64.0, p_continue=0.0)
+    sim = fs.FireSim.from_batch(batch, params)
+    p = fs.make_params(params)
+    p.unburnable_mask = batch.unburnable_mask
+    U, B = sim.relaxed_init()
+    ws = sim.relaxed_workspace(12, 4)
+    sim.relaxed_fwd(p, U, B, 12, 4, ws)
+    ii, jj = np.meshgrid(np.arange(33), np.arange(33), indexing="ij")
+    d = np.maximum(abs(ii - 16), abs(jj - 16))
+    assert np.array_equal(B.cpu().numpy().reshape(33, 33), (d == 12).astype(np.float32))
+    assert np.array_equal(U.cpu().numpy().reshape(33, 33), (d > 12).astype(np.float32))
+
+
+def test_full_size_relaxed128():
+    """256 envs of 128x128, T = 100, checkpoints every 10 (the benchmark's
+    workload): U_T of sampled envs against the fp64 forward, and the gradient
+    of a 16-env sub-batch against the fp64 adjoint."""
+    batch, params, T, k = firegen.workload_relaxed()
+    Y = _target(batch, params, T, 0)
+    theta_star = params
+    params = params.replace(p_base=params.p_base * 1.2, alpha_w1=params.alpha_w1 * 1.2,
+                            alpha_w2=params.alpha_w2 * 1.2, alpha_s=params.alpha_s * 1.2)
+    U, B, loss, _ = _gpu_loss_grad(batch, params, Y, T, k)
+    sample = [0, 77, 200, 255]
+    for e in sample:
+        env = relaxed64.from_batch(batch, e, params.cell_size)
+        U0, B0, _ = relaxed64.initial_state(batch, e)
+        Us, Bs, _ = relaxed64.forward(env, _theta32(params), U0, B0, T)
+        assert np.max(np.abs(batch.env_view(U, e) - Us[-1])) <= 1e-5, e
+    sub = batch.subset(range(16))
+    Ysub = np.concatenate([batch.env_view(Y, e).ravel() for e in range(16)])
+    _, _, _, g = _gpu_loss_grad(sub, params, Ysub, T, k)
+    _, g64, _ = _oracle(sub, params, Ysub, T)
+    _check_grad(g, g64)
+    assert theta_star.p_base == 0.58
