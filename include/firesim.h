@@ -130,16 +130,18 @@ int sim_get_step(const sim_handle* h, uint64_t* t);
 int sim_set_step(sim_handle* h, uint64_t t);
 
 /* Launch plan of sim_step (results never depend on it).
- *  tile_rows    rows per workgroup tile per 4-cell column group (1..8), 0 = default
+ *  tile_rows    rows of 4-cell groups each lane owns in its tile (1, 2, 4 or 8),
+ *               0 = default (4)
+ *  tile_width   widest tile in cells (64, 128 or 256; narrower envs use the
+ *               largest width not above W rounded up), 0 = default (256)
  *  temporal     steps fused per tile load (1 = one step per launch), 0 = default
- *  skip_static  1: tiles of a wave with no burning cell read only the state
- *               bytes (the fuel and elevation loads are skipped); 0: every
- *               cell reads its 10 bytes every step
+ *  skip_static  1: only cells with a burning neighbour read fuel and
+ *               elevation; 0: every cell reads its 10 bytes every step
  *  graph        1: capture the T launches of a call into a HIP graph and
  *               replay it (re-captured when T, the pointers or the plan
  *               change); 0: launch directly */
 typedef struct {
-    int32_t tile_rows, temporal, skip_static, graph;
+    int32_t tile_rows, tile_width, temporal, skip_static, graph;
 } sim_plan;
 int sim_set_plan(sim_handle* h, const sim_plan* plan);
 int sim_get_plan(const sim_handle* h, sim_plan* plan);

@@ -45,8 +45,9 @@ class SimEnv(ctypes.Structure):
 
 
 class SimPlan(ctypes.Structure):
-    _fields_ = [("tile_rows", ctypes.c_int32), ("temporal", ctypes.c_int32),
-                ("skip_static", ctypes.c_int32), ("graph", ctypes.c_int32)]
+    _fields_ = [("tile_rows", ctypes.c_int32), ("tile_width", ctypes.c_int32),
+                ("temporal", ctypes.c_int32), ("skip_static", ctypes.c_int32),
+                ("graph", ctypes.c_int32)]
 
 
 class SimError(RuntimeError):
@@ -228,14 +229,14 @@ class FireSim:
     def t(self, value: int):
         _check(lib().sim_set_step(self.handle, int(value)), self.handle)
 
-    def set_plan(self, tile_rows=0, temporal=0, skip_static=0, graph=0):
-        p = SimPlan(tile_rows, temporal, skip_static, graph)
+    def set_plan(self, tile_rows=0, tile_width=0, temporal=0, skip_static=0, graph=0):
+        p = SimPlan(tile_rows, tile_width, temporal, skip_static, graph)
         _check(lib().sim_set_plan(self.handle, ctypes.byref(p)), self.handle)
 
     def plan(self) -> dict:
         p = SimPlan()
         _check(lib().sim_get_plan(self.handle, ctypes.byref(p)), self.handle)
-        return {"tile_rows": p.tile_rows, "temporal": p.temporal,
+        return {"tile_rows": p.tile_rows, "tile_width": p.tile_width, "temporal": p.temporal,
                 "skip_static": p.skip_static, "graph": p.graph}
 
     # ------------------------------------------------------------- relaxed

@@ -44,7 +44,7 @@ struct sim_handle {
     bool wind_cell = false;
     uint64_t seed = 0;
     uint64_t t = 0;
-    sim_plan plan{4, 1, 0, 0};
+    sim_plan plan{4, 256, 1, 0, 0};
 
     EnvDev* d_envs = nullptr;
     float* d_g = nullptr;
@@ -57,7 +57,8 @@ struct sim_handle {
     uint32_t* d_t = nullptr;           // step counter base read by the step kernels
     TileDesc* d_tiles = nullptr;
     int32_t n_tiles = 0;
-    int32_t tiles_rt = 0;              // rows_per_thread the tile list was built for
+    int32_t tiles_rt = 0;              // tile_rows the tile list was built for
+    int32_t tiles_tw = 0;              // tile_width the tile list was built for
     hipStream_t cap_stream = nullptr;
     GraphCache graph;
     RelaxedState relaxed;
@@ -115,15 +116,20 @@ StepArgs step_args(const sim_handle* h)
     return a;
 }
 
-int tile_width_for(int W) { return W > 128 ? 256 : (W > 64 ? 128 : 64); }
+// Widest tile width (64, 128, 256) not above max_width that W needs.
+int tile_width_for(int W, int max_width)
+{
+    const int w = W > 128 ? 256 : (W > 64 ? 128 : 64);
+    return w < max_width ? w : max_width;
+}
 
 // Tile list: env-major, then row band, then column band.
-int build_tiles(sim_handle* h, int rt)
+int build_tiles(sim_handle* h, int rt, int max_width)
 {
     std::vector<TileDesc> tiles;
     for (int32_t e = 0; e < h->n_env; ++e) {
         const int H = h->envs[e].H, W = h->envs[e].W;
-        const int width = tile_width_for(W);
+        const int width = tile_width_for(W, max_width);
         const int th = (1024 / width) * rt;
         for (int r0 = 0; r0 < H; r0 += th)
             for (int c0 = 0; c0 < W; c0 += width) tiles.push_back(TileDesc{e, r0, c0, width});
@@ -136,6 +142,7 @@ int build_tiles(sim_handle* h, int rt)
                              hipMemcpyHostToDevice));
     h->n_tiles = (int32_t)tiles.size();
     h->tiles_rt = rt;
+    h->tiles_tw = max_width;
     return SIM_OK;
 }
 
@@ -180,7 +187,7 @@ hipError_t enqueue_steps(sim_handle* h, hipStream_t s, uint8_t* states, const in
 
 bool same_plan(const sim_plan& a, const sim_plan& b)
 {
-    return a.tile_rows == b.tile_rows && a.temporal == b.temporal &&
+    return a.tile_rows == b.tile_rows && a.tile_width == b.tile_width && a.temporal == b.temporal &&
            a.skip_static == b.skip_static && a.graph == b.graph;
 }
 
@@ -297,7 +304,7 @@ int sim_init(sim_handle** out, const sim_params* p, int32_t n_env, const sim_env
         fail(h, SIM_EHIP, "initialisation kernels failed: %s", hipGetErrorString(e));
         return bail(SIM_EHIP);
     }
-    if ((rc = build_tiles(h, h->plan.tile_rows)) != SIM_OK) return bail(rc);
+    if ((rc = build_tiles(h, h->plan.tile_rows, h->plan.tile_width)) != SIM_OK) return bail(rc);
     if (hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess) {
         fail(h, SIM_EHIP, "stream creation failed");
         return bail(SIM_EHIP);
@@ -316,8 +323,8 @@ int sim_step(sim_handle* h, uint8_t* states, const int32_t* actions, int32_t T, 
     if (h->t + (uint64_t)T > 0xFFFFFFFFull)
         return fail(h, SIM_ESTATE, "step counter would pass 2^32");
     hipStream_t s = (hipStream_t)stream;
-    if (h->tiles_rt != h->plan.tile_rows) {
-        const int rc = build_tiles(h, h->plan.tile_rows);
+    if (h->tiles_rt != h->plan.tile_rows || h->tiles_tw != h->plan.tile_width) {
+        const int rc = build_tiles(h, h->plan.tile_rows, h->plan.tile_width);
         if (rc != SIM_OK) return rc;
         h->graph.valid = false;
     }
@@ -376,9 +383,12 @@ int sim_set_plan(sim_handle* h, const sim_plan* plan)
     if (!h || !plan) return SIM_EINVAL;
     sim_plan p = *plan;
     if (p.tile_rows == 0) p.tile_rows = 4;
+    if (p.tile_width == 0) p.tile_width = 256;
     if (p.temporal == 0) p.temporal = 1;
     if (!(p.tile_rows == 1 || p.tile_rows == 2 || p.tile_rows == 4 || p.tile_rows == 8))
         return fail(h, SIM_EINVAL, "tile_rows must be 1, 2, 4 or 8");
+    if (!(p.tile_width == 64 || p.tile_width == 128 || p.tile_width == 256))
+        return fail(h, SIM_EINVAL, "tile_width must be 64, 128 or 256");
     if (p.temporal != 1) return fail(h, SIM_EINVAL, "temporal must be 1");
     if (p.skip_static != 0 && p.skip_static != 1) return fail(h, SIM_EINVAL, "skip_static must be 0 or 1");
     if (p.graph != 0 && p.graph != 1) return fail(h, SIM_EINVAL, "graph must be 0 or 1");

@@ -8,21 +8,28 @@
 // with p_continue, else becomes BURNT ("Stochastic update").  All draws of a
 // step use the state before it (synchronous update).
 //
-// Layout and data flow of one step (one launch):
-//  * a workgroup (256 lanes, 4 wave64s) owns a tile of `width` (64/128/256)
-//    columns by (1024/width) * RT rows of one env; each lane owns a 4-cell
-//    column group (one dword of uint8 states) in RT rows;
-//  * the tile's states plus a one-cell halo are staged in LDS (dword rows with
-//    a pad dword on each side so a lane reads its 6-cell neighbourhood row as
-//    three aligned dwords);
-//  * burning / flammable flags are computed four cells at a time with byte
-//    SWAR on the state dwords; lanes with neither a burning cell nor a
-//    flammable cell next to a burning one do no arithmetic at all;
-//  * front lanes draw one Philox block for their four cells and evaluate phi
-//    only for their burning neighbours (fuel and elevation of neighbours come
-//    through the cache; they are the tile's own or its neighbours' lines);
-//  * the new dword is stored, and the BURNING count is reduced per wave, per
-//    workgroup in LDS, and added to the env's counter with one atomic.
+// One step is one launch.  A workgroup (256 lanes, 4 wave64s) owns a tile of
+// one env, `width` (64/128/256) columns by (1024/width) * RT rows; each lane
+// owns a 4-cell column group (one dword of uint8 states) in RT rows.
+//  1. The tile's states plus a one-cell halo are staged in LDS (dword rows
+//     with a pad dword on each side, so a lane reads its 6-cell neighbourhood
+//     row as three aligned dwords).  In the dense plan every lane also loads
+//     the fuel term and elevation of its cells (the step's 10 bytes per cell).
+//  2. A suppression drop, if any, is applied to the staged tile.
+//  3. Burning / flammable flags come four cells at a time from byte SWAR.
+//     Front cells (flammable with a burning neighbour) and 4-cell groups that
+//     need a draw (a front or burning cell) are counted, the counts are
+//     scanned across the workgroup, and both are listed in LDS.
+//  4. All 256 lanes then work through the lists: one Philox block per listed
+//     group, then lambda and p for each listed front cell (its neighbours'
+//     fuel and elevation loaded together, then the ordered sum of phi).  Fires
+//     occupy a few percent of the cells, so packing their arithmetic onto
+//     every lane instead of leaving it on the lanes that own the cells keeps
+//     the step at memory speed.  If a list would overflow its LDS area the
+//     workgroup falls back to each lane handling its own cells.
+//  5. Owners assemble the new dwords from the lists' results and store them;
+//     the BURNING count is reduced per wave, per workgroup, and added to the
+//     env's counter with one atomic.
 // Workgroup b runs on XCD b % 8; tiles are dealt so that each XCD walks a
 // contiguous run of the tile list (neighbouring tiles share halo lines in
 // that XCD's L2).
@@ -31,6 +38,9 @@
 
 namespace firesim {
 namespace {
+
+constexpr int kCellCap = 1024;   // listed front cells per workgroup
+constexpr int kGroupCap = 512;   // listed 4-cell groups per workgroup
 
 // Byte-lane flags (bit 8b set for byte b); state codes are 0..3.
 __device__ __forceinline__ uint32_t burning_flags(uint32_t w) { return (w >> 1) & ~w & 0x01010101u; }
@@ -54,41 +64,73 @@ __device__ __forceinline__ uint32_t direction_mask(uint32_t up6, uint32_t md6, u
            (((up6 >> c) & 1u) << 7);
 }
 
-__device__ __forceinline__ float comp(const float4& v, int c)
-{
-    return c == 0 ? v.x : (c == 1 ? v.y : (c == 2 ? v.z : v.w));
-}
 __device__ __forceinline__ uint32_t compu(const uint4& v, int c)
 {
     return c == 0 ? v.x : (c == 1 ? v.y : (c == 2 ? v.z : v.w));
 }
 
 // p_ignite of target cell v (packed index) from its burning-neighbour mask.
+// The sources' fuel, elevation (and wind) are loaded together first so their
+// latency is paid once; lambda is then summed in ascending direction order.
 template <bool WIND_CELL>
-__device__ __forceinline__ float ignite_prob(uint32_t nbk, int64_t v, int W, float g_v, float E_v,
-                                             const StaticFields& F, const StepArgs& A,
-                                             const float* ew)
+__device__ __forceinline__ float ignite_prob(uint32_t nbk, int64_t v, int W, const StaticFields& F,
+                                             const StepArgs& A, const float* ew)
 {
+    float g_u[8], E_u[8], V_u[8], Vx_u[8], Vy_u[8];
+    const float g_v = F.g[v], E_v = F.E[v];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        g_u[k] = E_u[k] = V_u[k] = Vx_u[k] = Vy_u[k] = 0.0f;
+        if ((nbk >> k) & 1u) {
+            const int64_t u = v - (int64_t)kDRow[k] * W - kDCol[k];
+            g_u[k] = F.g[u];
+            E_u[k] = F.E[u];
+            if constexpr (WIND_CELL) {
+                V_u[k] = F.wind[u];
+                Vx_u[k] = F.wind[F.n_cells + u];
+                Vy_u[k] = F.wind[2 * F.n_cells + u];
+            }
+        }
+    }
     float lambda = 0.0f;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
         if (!((nbk >> k) & 1u)) continue;
-        const int64_t u = v - (int64_t)kDRow[k] * W - kDCol[k];
-        const float g_u = F.g[u];
-        const float E_u = F.E[u];
         float wexp;
         if constexpr (WIND_CELL)
-            wexp = wind_exponent(k, A.alpha_w1, A.alpha_w2, F.wind[u], F.wind[F.n_cells + u],
-                                 F.wind[2 * F.n_cells + u]);
+            wexp = wind_exponent(k, A.alpha_w1, A.alpha_w2, V_u[k], Vx_u[k], Vy_u[k]);
         else
             wexp = ew[k];
-        const float slope = (E_v - E_u) * ((k & 1) ? A.inv_run_diag : A.inv_run_orth);
+        const float slope = (E_v - E_u[k]) * ((k & 1) ? A.inv_run_diag : A.inv_run_orth);
         const float x = wexp + A.alpha_s * slope;
-        lambda = lambda + (A.p_base * g_u) * exp_c(x);
+        lambda = lambda + (A.p_base * g_u[k]) * exp_c(x);
     }
     if (!(lambda > 0.0f)) return 0.0f;
     const float gamma = A.alpha_gamma * g_v;
     return 1.0f - exp_c(-(gamma * lambda));
+}
+
+// The four Philox words of a 4-cell group whose first cell has env-local
+// index n0 (a group may straddle two counters when W % 4 != 0).
+template <bool ALIGNED>
+__device__ __forceinline__ uint4 group_words(int64_t n0, uint32_t t, uint32_t env_id, uint2 key)
+{
+    const uint4 w0 = philox4x32_10(make_uint4((uint32_t)(n0 >> 2), t, env_id, 0u), key);
+    if constexpr (ALIGNED) {
+        return w0;
+    } else {
+        const int64_t q0 = n0 >> 2;
+        uint4 w1 = w0;
+        if (((n0 + 3) >> 2) != q0)
+            w1 = philox4x32_10(make_uint4((uint32_t)(q0 + 1), t, env_id, 0u), key);
+        uint32_t w[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int64_t n = n0 + c;
+            w[c] = (n >> 2) == q0 ? compu(w0, (int)(n & 3)) : compu(w1, (int)(n & 3));
+        }
+        return make_uint4(w[0], w[1], w[2], w[3]);
+    }
 }
 
 __device__ __forceinline__ void keep_loaded(const float4& v)
@@ -104,6 +146,30 @@ constexpr int lds_dwords()
     return a > b ? (a > c ? a : c) : (b > c ? b : c);
 }
 
+// Workgroup-wide exclusive scan of one 32-bit value per lane; returns the
+// lane's offset and writes the workgroup total.
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x, uint32_t* lds4, uint32_t& total)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t incl = x;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(incl, off);
+        if (lane >= off) incl += y;
+    }
+    if (lane == 63) lds4[wave] = incl;
+    __syncthreads();
+    uint32_t before = 0;
+    total = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) {
+        const uint32_t s = lds4[w];
+        before += w < wave ? s : 0u;
+        total += s;
+    }
+    return before + incl - x;
+}
+
 template <bool ALIGNED, bool WIND_CELL, int RT, bool SKIP>
 __global__ __launch_bounds__(kBlock) void stoch_step_kernel(
     const TileDesc* __restrict__ tiles, int32_t n_tiles, int32_t tiles_per_xcd,
@@ -113,6 +179,11 @@ __global__ __launch_bounds__(kBlock) void stoch_step_kernel(
 {
     __shared__ uint32_t lds[lds_dwords<RT>()];
     __shared__ float lds_ew[8];
+    __shared__ uint32_t lds_scan[kBlock / 64];
+    __shared__ uint32_t lds_cell[kCellCap];   // tid | m << 8 | c << 11 | nbk << 13 | group << 21
+    __shared__ uint16_t lds_group[kGroupCap]; // tid | m << 8
+    __shared__ float lds_u[kGroupCap * 4];    // uniforms of each listed group's cells
+    __shared__ uint8_t lds_dec[kCellCap];     // ignition decision of each listed cell
     __shared__ int32_t lds_cnt[kBlock / 64];
 
     const int b = blockIdx.x;
@@ -131,8 +202,9 @@ __global__ __launch_bounds__(kBlock) void stoch_step_kernel(
     const int tx = tid & (GX - 1), ty = tid >> gx_log;
     const uint32_t t = *t_base + step;
     const int64_t base = ed.offset;
+    const uint2 key = make_uint2(A.key0, A.key1);
 
-    // -- stage the tile's states (one-cell halo; off-grid cells read as 0) --
+    // -- 1. stage the tile's states (one-cell halo; off-grid cells read as 0) --
     for (int idx = tid; idx < nrow * GX; idx += kBlock) {
         const int rr = idx >> gx_log, q = idx & (GX - 1);
         const int gi = td.r0 - 1 + rr, gj = td.c0 + 4 * q;
@@ -162,11 +234,9 @@ __global__ __launch_bounds__(kBlock) void stoch_step_kernel(
     if constexpr (!WIND_CELL) {
         if (tid < 8) lds_ew[tid] = wind_exponent(tid, A.alpha_w1, A.alpha_w2, ed.V, ed.Vx, ed.Vy);
     }
-
-    // -- own fuel and elevation: every cell reads its 8 bytes (4 + 4, plus
-    //    12 of per-cell wind) each step unless SKIP defers them to front lanes
-    float4 gv[RT], ev[RT];
+    // dense plan: every cell reads its fuel and elevation (and per-cell wind) each step
     const int gj0 = td.c0 + 4 * tx;
+    float4 gv[RT], ev[RT];
 #pragma unroll
     for (int m = 0; m < RT; ++m) {
         gv[m] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -194,14 +264,19 @@ __global__ __launch_bounds__(kBlock) void stoch_step_kernel(
                     gv[m] = make_float4(tg[0], tg[1], tg[2], tg[3]);
                     ev[m] = make_float4(te[0], te[1], te[2], te[3]);
                 }
-                keep_loaded(gv[m]);
-                keep_loaded(ev[m]);
             }
         }
     }
     __syncthreads();
+    if constexpr (!SKIP) {
+#pragma unroll
+        for (int m = 0; m < RT; ++m) {
+            keep_loaded(gv[m]);
+            keep_loaded(ev[m]);
+        }
+    }
 
-    // -- suppression drop on the staged tile (halo included), before the step
+    // -- 2. suppression drop on the staged tile (halo included), before the step
     const int32_t act = actions_row ? actions_row[td.env] : -1;
     if (act >= 0) {
         const int ar = (act >> 16) & 0x7FFF, ac = act & 0xFFFF;
@@ -220,13 +295,16 @@ __global__ __launch_bounds__(kBlock) void stoch_step_kernel(
         }
     }
 
-    // -- the step --
-    int cnt = 0;
-    const uint2 key = make_uint2(A.key0, A.key1);
+    // -- 3. flags of own cells: burning (bits 0-3), front (bits 4-7), and the
+    //       burning-neighbour masks of the four cells (8 bits each)
+    uint32_t flags[RT], nbks[RT];
+    uint32_t my_cells = 0, my_groups = 0;
 #pragma unroll
     for (int m = 0; m < RT; ++m) {
         const int lr = ty + m * RP;
         const int gi = td.r0 + lr;
+        flags[m] = 0;
+        nbks[m] = 0;
         if (!(gi < H && gj0 < W)) continue;
         const uint32_t* up = lds + lr * SD + tx;
         const uint32_t* md = up + SD;
@@ -239,45 +317,111 @@ __global__ __launch_bounds__(kBlock) void stoch_step_kernel(
         const uint32_t near = (ud | (ud >> 1) | (ud >> 2) | md6 | (md6 >> 2)) & 0xFu;
         const uint32_t burn = pack4(burning_flags(own));
         const uint32_t front = pack4(flammable_flags(own)) & near;
-        uint32_t out = own;
-        if (front | burn) {
-            const int64_t n0 = (int64_t)gi * W + gj0;  // env-local index of own cell 0
-            const int64_t v0 = base + n0;
-            const uint4 w0 = philox4x32_10(make_uint4((uint32_t)(n0 >> 2), t, ed.env_id, 0u), key);
-            uint4 w1 = w0;
-            if constexpr (!ALIGNED) {
-                if (((n0 + 3) >> 2) != (n0 >> 2))
-                    w1 = philox4x32_10(make_uint4((uint32_t)((n0 + 3) >> 2), t, ed.env_id, 0u), key);
-            }
+        uint32_t nb = 0;
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const bool is_burn = (burn >> c) & 1u, is_front = (front >> c) & 1u;
-                if (!(is_burn || is_front)) continue;
-                uint32_t word;
-                if constexpr (ALIGNED) {
-                    word = compu(w0, c);
-                } else {
-                    const int64_t n = n0 + c;
-                    word = (n >> 2) == (n0 >> 2) ? compu(w0, (int)(n & 3)) : compu(w1, (int)(n & 3));
+        for (int c = 0; c < 4; ++c)
+            if ((front >> c) & 1u) nb |= direction_mask(up6, md6, dn6, c) << (8 * c);
+        flags[m] = burn | (front << 4);
+        nbks[m] = nb;
+        my_cells += __popc(front);
+        my_groups += (burn | front) != 0u;
+    }
+
+    // -- 4. list front cells and draw groups across the workgroup
+    uint32_t totals;
+    const uint32_t off = block_exclusive_scan(my_cells | (my_groups << 16), lds_scan, totals);
+    const uint32_t n_cells = totals & 0xFFFFu, n_groups = totals >> 16;
+    const bool listed = n_cells <= (uint32_t)kCellCap && n_groups <= (uint32_t)kGroupCap;
+    uint32_t slot[RT];  // per row: group index | first cell index << 16
+#pragma unroll
+    for (int m = 0; m < RT; ++m) slot[m] = 0;
+    if (listed && totals != 0u) {
+        uint32_t ci = off & 0xFFFFu, gidx = off >> 16;
+#pragma unroll
+        for (int m = 0; m < RT; ++m) {
+            slot[m] = 0;
+            const uint32_t burn = flags[m] & 0xFu, front = flags[m] >> 4;
+            if (!(burn | front)) continue;
+            slot[m] = gidx | (ci << 16);
+            lds_group[gidx] = (uint16_t)(tid | (m << 8));
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                if ((front >> c) & 1u)
+                    lds_cell[ci++] = (uint32_t)tid | ((uint32_t)m << 8) | ((uint32_t)c << 11) |
+                                     (((nbks[m] >> (8 * c)) & 0xFFu) << 13) | (gidx << 21);
+            ++gidx;
+        }
+        __syncthreads();
+        // one Philox block per listed group
+        for (uint32_t gq = tid; gq < n_groups; gq += kBlock) {
+            const uint32_t e = lds_group[gq];
+            const int otid = e & 0xFF, m = e >> 8;
+            const int gi = td.r0 + (otid >> gx_log) + m * RP;
+            const int gj = td.c0 + 4 * (otid & (GX - 1));
+            const uint4 w = group_words<ALIGNED>((int64_t)gi * W + gj, t, ed.env_id, key);
+            lds_u[gq * 4 + 0] = word_to_uniform(w.x);
+            lds_u[gq * 4 + 1] = word_to_uniform(w.y);
+            lds_u[gq * 4 + 2] = word_to_uniform(w.z);
+            lds_u[gq * 4 + 3] = word_to_uniform(w.w);
+        }
+        __syncthreads();
+        // lambda and p of each listed front cell
+        for (uint32_t cq = tid; cq < n_cells; cq += kBlock) {
+            const uint32_t e = lds_cell[cq];
+            const int otid = e & 0xFF, m = (e >> 8) & 7, c = (e >> 11) & 3;
+            const uint32_t nbk = (e >> 13) & 0xFF, gq = e >> 21;
+            const int gi = td.r0 + (otid >> gx_log) + m * RP;
+            const int gj = td.c0 + 4 * (otid & (GX - 1)) + c;
+            const float p = ignite_prob<WIND_CELL>(nbk, base + (int64_t)gi * W + gj, W, F, A, lds_ew);
+            lds_dec[cq] = lds_u[gq * 4 + c] < p ? 1 : 0;
+        }
+        __syncthreads();
+    }
+
+    // -- 5. new states, store, count
+    int cnt = 0;
+#pragma unroll
+    for (int m = 0; m < RT; ++m) {
+        const int lr = ty + m * RP;
+        const int gi = td.r0 + lr;
+        if (!(gi < H && gj0 < W)) continue;
+        const uint32_t own = lds[(lr + 1) * SD + tx + 1];
+        const uint32_t burn = flags[m] & 0xFu, front = flags[m] >> 4;
+        uint32_t out = own;
+        if (burn | front) {
+            if (listed) {
+                const uint32_t gq = slot[m] & 0xFFFFu;
+                uint32_t ci = slot[m] >> 16;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    uint32_t next;
+                    if ((burn >> c) & 1u)
+                        next = lds_u[gq * 4 + c] < A.p_continue ? kBurning : kBurnt;
+                    else if ((front >> c) & 1u)
+                        next = lds_dec[ci++] ? kBurning : kFlammable;
+                    else
+                        continue;
+                    out = (out & ~(0xFFu << (8 * c))) | (next << (8 * c));
                 }
-                const float u = word_to_uniform(word);
-                uint32_t next;
-                if (is_burn) {
-                    next = (u < A.p_continue) ? kBurning : kBurnt;
-                } else {
-                    float g_v, E_v;
-                    if constexpr (SKIP) {
-                        g_v = F.g[v0 + c];
-                        E_v = F.E[v0 + c];
-                    } else {
-                        g_v = comp(gv[m], c);
-                        E_v = comp(ev[m], c);
-                    }
-                    const float p = ignite_prob<WIND_CELL>(direction_mask(up6, md6, dn6, c), v0 + c,
-                                                           W, g_v, E_v, F, A, lds_ew);
-                    next = (u < p) ? kBurning : kFlammable;
+            } else {
+                // list overflow: this lane draws and evaluates its own cells
+                const int64_t n0 = (int64_t)gi * W + gj0;
+                const uint4 w = group_words<ALIGNED>(n0, t, ed.env_id, key);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const float u = word_to_uniform(compu(w, c));
+                    uint32_t next;
+                    if ((burn >> c) & 1u)
+                        next = u < A.p_continue ? kBurning : kBurnt;
+                    else if ((front >> c) & 1u)
+                        next = u < ignite_prob<WIND_CELL>((nbks[m] >> (8 * c)) & 0xFFu,
+                                                          base + n0 + c, W, F, A, lds_ew)
+                                   ? kBurning
+                                   : kFlammable;
+                    else
+                        continue;
+                    out = (out & ~(0xFFu << (8 * c))) | (next << (8 * c));
                 }
-                out = (out & ~(0xFFu << (8 * c))) | (next << (8 * c));
             }
         }
         uint8_t* o = dst + base + (int64_t)gi * W + gj0;
@@ -294,7 +438,7 @@ __global__ __launch_bounds__(kBlock) void stoch_step_kernel(
     // -- BURNING count of the env after the step --
     if (counts_row) {
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
+        for (int off2 = 32; off2 > 0; off2 >>= 1) cnt += __shfl_xor(cnt, off2);
         if ((tid & 63) == 0) lds_cnt[tid >> 6] = cnt;
         __syncthreads();
         if (tid == 0) {

@@ -116,15 +116,41 @@ ALIGNED_SIZES = [(64, 64), (128, 256), (256, 256), (512, 128), (96, 192), (256, 
 
 @pytest.mark.parametrize("tile_rows", [1, 2, 4, 8])
 @pytest.mark.parametrize("skip_static", [0, 1])
-def test_aligned_batch_every_plan(tile_rows, skip_static):
-    """Same bits whatever the tile height and load mode."""
+@pytest.mark.parametrize("tile_width", [64, 256])
+def test_aligned_batch_every_plan(tile_rows, skip_static, tile_width):
+    """Same bits whatever the tile shape and load mode."""
     batch = firegen.landscape_batch(31, ALIGNED_SIZES)
     params = firegen.Params(p_base=0.8, veg=_veg(4))
     acts = firegen.random_actions(6, batch, 30, p_none=0.5)
     sim, ref, got, want = _run_both(batch, params, 30, seed=9, actions=acts,
-                                    plan={"tile_rows": tile_rows, "skip_static": skip_static})
+                                    plan={"tile_rows": tile_rows, "skip_static": skip_static,
+                                          "tile_width": tile_width})
     assert np.array_equal(sim.states.cpu().numpy(), ref.states)
     assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("tile_rows", [2, 8])
+def test_dense_fronts_overflow_the_lists(tile_rows):
+    """A checkerboard of burning cells makes half of every tile a front cell,
+    more than a workgroup lists; those workgroups fall back to per-lane work
+    and must give the same bits."""
+    batch = firegen.landscape_batch(35, [(256, 256), (128, 128), (64, 200)])
+    params = firegen.Params(p_base=0.3, veg=_veg(9))
+    sim = fs.FireSim.from_batch(batch, params, seed=13)
+    sim.set_plan(tile_rows=tile_rows)
+    ref = oracle.Sim(batch, params, seed=13)
+    st = ref.states.copy()
+    for e in range(batch.n_env):
+        v = batch.env_view(st, e)
+        ii, jj = np.meshgrid(np.arange(v.shape[0]), np.arange(v.shape[1]), indexing="ij")
+        v[((ii + jj) % 2 == 0) & (v == firegen.FLAMMABLE)] = firegen.BURNING
+    ref.states[:] = st
+    sim.states.copy_(torch.from_numpy(st))
+    c = sim.step(4, counts=True).cpu().numpy()
+    rc = ref.step(4, counts=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(sim.states.cpu().numpy(), ref.states)
+    assert np.array_equal(c, rc)
 
 
 def test_graph_replay_and_resume_split():
@@ -216,3 +242,36 @@ def test_rejects_bad_arguments():
     with pytest.raises(fs.SimError):
         sim.set_plan(tile_rows=3)
     assert sim.step(0) is None
+
+
+def test_uneven_batch_with_drops_sampled_envs():
+    """Envs with sides drawn from {64, 128, 256, 512}, one 5x5 drop per env per
+    step, 300 steps, counts: sampled envs of every size equal the oracle."""
+    batch, params, T, seed, acts = firegen.workload_uneven(n_env=384)
+    sim = fs.FireSim.from_batch(batch, params, seed=seed)
+    cnt = sim.step(T, actions=torch.from_numpy(acts), counts=True).cpu().numpy()
+    torch.cuda.synchronize()
+    got = sim.states.cpu().numpy()
+    sample = []
+    for side in (64, 128, 256, 512):
+        sample += [int(e) for e in np.flatnonzero(batch.H == side)[:2]]
+    sub = batch.subset(sample)
+    ref = oracle.Sim(sub, params, seed=seed)
+    rc = ref.step(T, actions=np.ascontiguousarray(acts[:, sample]), counts=True, threads=8)
+    for k, e in enumerate(sample):
+        assert np.array_equal(batch.env_view(got, e), sub.env_view(ref.states, k)), e
+        assert np.array_equal(cnt[:, e], rc[:, k]), e
+
+
+def test_large_grids_per_cell_wind_sampled():
+    """2048 x 2048 envs with per-cell wind and 0-2000 m terrain: two envs
+    against the oracle over 150 steps (dense and skip plans)."""
+    batch, params, _, seed = firegen.workload_large(n_env=2)
+    ref = oracle.Sim(batch, params, seed=seed)
+    ref.step(150, threads=2)
+    for skip in (0, 1):
+        sim = fs.FireSim.from_batch(batch, params, seed=seed)
+        sim.set_plan(skip_static=skip)
+        sim.step(150)
+        torch.cuda.synchronize()
+        assert np.array_equal(sim.states.cpu().numpy(), ref.states), skip
