@@ -130,7 +130,7 @@ int build_tiles(sim_handle* h, int rt, int max_width)
     for (int32_t e = 0; e < h->n_env; ++e) {
         const int H = h->envs[e].H, W = h->envs[e].W;
         const int width = tile_width_for(W, max_width);
-        const int th = (1024 / width) * rt;
+        const int th = (256 / width) * rt;  // one wave64 per tile: 256 / width lane rows of rt rows
         for (int r0 = 0; r0 < H; r0 += th)
             for (int c0 = 0; c0 < W; c0 += width) tiles.push_back(TileDesc{e, r0, c0, width});
     }

@@ -8,39 +8,44 @@
 // with p_continue, else becomes BURNT ("Stochastic update").  All draws of a
 // step use the state before it (synchronous update).
 //
-// One step is one launch.  A workgroup (256 lanes, 4 wave64s) owns a tile of
-// one env, `width` (64/128/256) columns by (1024/width) * RT rows; each lane
-// owns a 4-cell column group (one dword of uint8 states) in RT rows.
-//  1. The tile's states plus a one-cell halo are staged in LDS (dword rows
-//     with a pad dword on each side, so a lane reads its 6-cell neighbourhood
-//     row as three aligned dwords).  In the dense plan every lane also loads
-//     the fuel term and elevation of its cells (the step's 10 bytes per cell).
-//  2. A suppression drop, if any, is applied to the staged tile.
+// One step is one launch of 64-lane workgroups (one wave64 each).  A
+// workgroup owns a tile of one env: `width` (64/128/256) columns by
+// (256/width) * RT rows.  Lane (tx, ty) owns the 4-cell column group at
+// column c0 + 4 tx (one dword of uint8 states) in the RT consecutive rows
+// r0 + ty RT + m.
+//  1. Each lane loads its RT state dwords and the dwords directly above and
+//     below them (those repeats hit L2: the neighbouring lanes load the same
+//     lines), and in the dense plan the fuel term and elevation of its cells
+//     (the step's 10 bytes per cell).  The left / right neighbour bytes come
+//     from the adjacent lanes of the row segment by a lane shuffle; only the
+//     segment's end lanes load the halo byte beyond the tile.  Nothing is
+//     staged in LDS and no barrier waits on the loads.
+//  2. A suppression drop, if any, is applied to the loaded dwords.
 //  3. Burning / flammable flags come four cells at a time from byte SWAR.
 //     Front cells (flammable with a burning neighbour) and 4-cell groups that
-//     need a draw (a front or burning cell) are counted, the counts are
-//     scanned across the workgroup, and both are listed in LDS.
-//  4. All 256 lanes then work through the lists: one Philox block per listed
-//     group, then lambda and p for each listed front cell (its neighbours'
+//     need a draw (a front or burning cell) are counted, scanned across the
+//     wave and listed in LDS.
+//  4. The wave then works through the lists: one Philox block per listed
+//     group, then lambda and p of each listed front cell (its neighbours'
 //     fuel and elevation loaded together, then the ordered sum of phi).  Fires
-//     occupy a few percent of the cells, so packing their arithmetic onto
-//     every lane instead of leaving it on the lanes that own the cells keeps
-//     the step at memory speed.  If a list would overflow its LDS area the
-//     workgroup falls back to each lane handling its own cells.
-//  5. Owners assemble the new dwords from the lists' results and store them;
-//     the BURNING count is reduced per wave, per workgroup, and added to the
-//     env's counter with one atomic.
+//     cover a few percent of the cells, so packing their arithmetic onto every
+//     lane, instead of leaving it to the lanes that own the cells, keeps the
+//     step at memory speed.  A wave whose lists would overflow falls back to
+//     each lane handling its own cells.
+//  5. Owners assemble the new dwords and store them; the BURNING count is
+//     reduced across the wave and added to the env's counter with one atomic.
 // Workgroup b runs on XCD b % 8; tiles are dealt so that each XCD walks a
-// contiguous run of the tile list (neighbouring tiles share halo lines in
-// that XCD's L2).
+// contiguous run of the tile list (neighbouring tiles share lines in that
+// XCD's L2).
 #include "devmath.hpp"
 #include "internal.hpp"
 
 namespace firesim {
 namespace {
 
-constexpr int kCellCap = 1024;   // listed front cells per workgroup
-constexpr int kGroupCap = 512;   // listed 4-cell groups per workgroup
+constexpr int kWave = 64;
+constexpr int kCellCap = 256;    // listed front cells per wave
+constexpr int kGroupCap = 128;   // listed 4-cell groups per wave
 
 // Byte-lane flags (bit 8b set for byte b); state codes are 0..3.
 __device__ __forceinline__ uint32_t burning_flags(uint32_t w) { return (w >> 1) & ~w & 0x01010101u; }
@@ -138,53 +143,65 @@ __device__ __forceinline__ void keep_loaded(const float4& v)
     asm volatile("" ::"v"(v.x), "v"(v.y), "v"(v.z), "v"(v.w));
 }
 
-template <int RT>
-constexpr int lds_dwords()
+// Wave-wide exclusive scan of one 32-bit value per lane; returns the lane's
+// offset and the wave total.
+__device__ __forceinline__ uint32_t wave_exclusive_scan(uint32_t x, uint32_t& total)
 {
-    // (tile rows + 2) x (lanes per row + 2) for the three tile widths
-    constexpr int a = (16 * RT + 2) * 18, b = (8 * RT + 2) * 34, c = (4 * RT + 2) * 66;
-    return a > b ? (a > c ? a : c) : (b > c ? b : c);
-}
-
-// Workgroup-wide exclusive scan of one 32-bit value per lane; returns the
-// lane's offset and writes the workgroup total.
-__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x, uint32_t* lds4, uint32_t& total)
-{
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x;
     uint32_t incl = x;
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
+    for (int off = 1; off < kWave; off <<= 1) {
         const uint32_t y = __shfl_up(incl, off);
         if (lane >= off) incl += y;
     }
-    if (lane == 63) lds4[wave] = incl;
-    __syncthreads();
-    uint32_t before = 0;
-    total = 0;
+    total = __shfl(incl, kWave - 1);
+    return incl - x;
+}
+
+// State dword of the 4-cell group at (gi, gj); 0 (not burning) off the grid.
+template <bool ALIGNED>
+__device__ __forceinline__ uint32_t load_group(const uint8_t* __restrict__ env_src, int gi, int gj, int H,
+                                               int W)
+{
+    if (gi < 0 || gi >= H || gj >= W) return 0u;
+    const uint8_t* p = env_src + (int64_t)gi * W + gj;
+    if constexpr (ALIGNED) {
+        return *reinterpret_cast<const uint32_t*>(p);
+    } else {
+        uint32_t v = 0;
 #pragma unroll
-    for (int w = 0; w < kBlock / 64; ++w) {
-        const uint32_t s = lds4[w];
-        before += w < wave ? s : 0u;
-        total += s;
+        for (int c = 0; c < 4; ++c)
+            if (gj + c < W) v |= (uint32_t)p[c] << (8 * c);
+        return v;
     }
-    return before + incl - x;
+}
+
+// A drop clears FLAMMABLE (1) and BURNING (2) bytes of dword w (columns
+// gj..gj+3, row gi) that lie in the 5 x 5 square centred at (ar, ac).
+__device__ __forceinline__ uint32_t apply_drop(uint32_t w, int gi, int gj, int ar, int ac)
+{
+    if (gi < ar - 2 || gi > ar + 2) return w;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int j = gj + c;
+        const uint32_t s = (w >> (8 * c)) & 0xFFu;
+        if (j >= ac - 2 && j <= ac + 2 && (s == kFlammable || s == kBurning)) w &= ~(0xFFu << (8 * c));
+    }
+    return w;
 }
 
 template <bool ALIGNED, bool WIND_CELL, int RT, bool SKIP>
-__global__ __launch_bounds__(kBlock) void stoch_step_kernel(
+__global__ __launch_bounds__(kWave) void stoch_step_kernel(
     const TileDesc* __restrict__ tiles, int32_t n_tiles, int32_t tiles_per_xcd,
     const EnvDev* __restrict__ envs, StaticFields F, StepArgs A, const uint8_t* __restrict__ src,
     uint8_t* __restrict__ dst, const uint32_t* __restrict__ t_base, uint32_t step,
     const int32_t* __restrict__ actions_row, int32_t* __restrict__ counts_row)
 {
-    __shared__ uint32_t lds[lds_dwords<RT>()];
-    __shared__ float lds_ew[8];
-    __shared__ uint32_t lds_scan[kBlock / 64];
-    __shared__ uint32_t lds_cell[kCellCap];   // tid | m << 8 | c << 11 | nbk << 13 | group << 21
-    __shared__ uint16_t lds_group[kGroupCap]; // tid | m << 8
+    __shared__ uint32_t lds_cell[kCellCap];   // lane | m << 6 | c << 9 | nbk << 11 | group << 19
+    __shared__ uint16_t lds_group[kGroupCap]; // lane | m << 6
     __shared__ float lds_u[kGroupCap * 4];    // uniforms of each listed group's cells
     __shared__ uint8_t lds_dec[kCellCap];     // ignition decision of each listed cell
-    __shared__ int32_t lds_cnt[kBlock / 64];
+    __shared__ float lds_ew[8];
 
     const int b = blockIdx.x;
     const int tile = (b & 7) * tiles_per_xcd + (b >> 3);
@@ -193,56 +210,36 @@ __global__ __launch_bounds__(kBlock) void stoch_step_kernel(
     const EnvDev ed = envs[td.env];
     const int H = ed.H, W = ed.W;
     const int gx_log = td.width == 256 ? 6 : (td.width == 128 ? 5 : 4);
-    const int GX = 1 << gx_log;          // lanes per tile row
-    const int RP = kBlock >> gx_log;     // rows per pass
-    const int TH = RP * RT;              // tile rows
-    const int SD = GX + 2;               // LDS dwords per row
-    const int nrow = TH + 2;
-    const int tid = threadIdx.x;
-    const int tx = tid & (GX - 1), ty = tid >> gx_log;
+    const int GX = 1 << gx_log;  // lanes per row segment
+    const int lane = threadIdx.x;
+    const int tx = lane & (GX - 1), ty = lane >> gx_log;
+    const int row0 = td.r0 + ty * RT;  // first own row
+    const int gj0 = td.c0 + 4 * tx;    // first own column
     const uint32_t t = *t_base + step;
     const int64_t base = ed.offset;
+    const uint8_t* env_src = src + base;
     const uint2 key = make_uint2(A.key0, A.key1);
 
-    // -- 1. stage the tile's states (one-cell halo; off-grid cells read as 0) --
-    for (int idx = tid; idx < nrow * GX; idx += kBlock) {
-        const int rr = idx >> gx_log, q = idx & (GX - 1);
-        const int gi = td.r0 - 1 + rr, gj = td.c0 + 4 * q;
-        uint32_t v = 0;
-        if (gi >= 0 && gi < H && gj < W) {
-            const uint8_t* p = src + base + (int64_t)gi * W + gj;
-            if constexpr (ALIGNED) {
-                v = *reinterpret_cast<const uint32_t*>(p);
-            } else {
+    // -- 1. loads: RT own dwords plus the one above and below; halo bytes at
+    //       the segment ends; fuel and elevation of own cells (dense plan)
+    uint32_t s[RT + 2], hl[RT + 2], hr[RT + 2];
 #pragma unroll
-                for (int c = 0; c < 4; ++c)
-                    if (gj + c < W) v |= (uint32_t)p[c] << (8 * c);
-            }
-        }
-        lds[rr * SD + 1 + q] = v;
+    for (int j = 0; j < RT + 2; ++j) s[j] = load_group<ALIGNED>(env_src, row0 - 1 + j, gj0, H, W);
+    const int cl = td.c0 - 1, cr = td.c0 + td.width;
+#pragma unroll
+    for (int j = 0; j < RT + 2; ++j) {
+        const int gi = row0 - 1 + j;
+        const bool row_in = gi >= 0 && gi < H;
+        hl[j] = (tx == 0 && row_in && cl >= 0) ? (uint32_t)env_src[(int64_t)gi * W + cl] : 0u;
+        hr[j] = (tx == GX - 1 && row_in && cr < W) ? (uint32_t)env_src[(int64_t)gi * W + cr] : 0u;
     }
-    for (int idx = tid; idx < 2 * nrow; idx += kBlock) {
-        const int rr = idx >> 1, right = idx & 1;
-        const int gi = td.r0 - 1 + rr, gj = right ? td.c0 + td.width : td.c0 - 1;
-        uint32_t v = 0;
-        if (gi >= 0 && gi < H && gj >= 0 && gj < W) v = src[base + (int64_t)gi * W + gj];
-        if (right)
-            lds[rr * SD + GX + 1] = v;
-        else
-            lds[rr * SD] = v << 24;
-    }
-    if constexpr (!WIND_CELL) {
-        if (tid < 8) lds_ew[tid] = wind_exponent(tid, A.alpha_w1, A.alpha_w2, ed.V, ed.Vx, ed.Vy);
-    }
-    // dense plan: every cell reads its fuel and elevation (and per-cell wind) each step
-    const int gj0 = td.c0 + 4 * tx;
     float4 gv[RT], ev[RT];
 #pragma unroll
     for (int m = 0; m < RT; ++m) {
         gv[m] = make_float4(0.f, 0.f, 0.f, 0.f);
         ev[m] = gv[m];
         if constexpr (!SKIP) {
-            const int gi = td.r0 + ty + m * RP;
+            const int gi = row0 + m;
             if (gi < H && gj0 < W) {
                 const int64_t c0 = base + (int64_t)gi * W + gj0;
                 if constexpr (ALIGNED) {
@@ -267,56 +264,59 @@ __global__ __launch_bounds__(kBlock) void stoch_step_kernel(
             }
         }
     }
-    __syncthreads();
     if constexpr (!SKIP) {
+        // the loaded values are not needed by this lane (front cells reload
+        // through the cache), only their arrival
 #pragma unroll
         for (int m = 0; m < RT; ++m) {
             keep_loaded(gv[m]);
             keep_loaded(ev[m]);
         }
     }
+    if constexpr (!WIND_CELL) {
+        if (lane < 8) lds_ew[lane] = wind_exponent(lane, A.alpha_w1, A.alpha_w2, ed.V, ed.Vx, ed.Vy);
+    }
 
-    // -- 2. suppression drop on the staged tile (halo included), before the step
+    // -- 2. suppression drop on the loaded dwords and halo bytes, before the step
     const int32_t act = actions_row ? actions_row[td.env] : -1;
     if (act >= 0) {
         const int ar = (act >> 16) & 0x7FFF, ac = act & 0xFFFF;
         if (ar < H && ac < W) {
-            if (tid < 25) {
-                const int gi = ar - 2 + tid / 5, gj = ac - 2 + tid % 5;
-                const int rr = gi - (td.r0 - 1), cc = gj - td.c0;
-                if (gi >= 0 && gi < H && gj >= 0 && gj < W && rr >= 0 && rr < nrow && cc >= -1 &&
-                    cc <= td.width) {
-                    uint8_t* pb = reinterpret_cast<uint8_t*>(lds) + rr * SD * 4 + 4 + cc;
-                    const uint8_t s0 = *pb;
-                    if (s0 == kFlammable || s0 == kBurning) *pb = kUnburnable;
+#pragma unroll
+            for (int j = 0; j < RT + 2; ++j) {
+                const int gi = row0 - 1 + j;
+                s[j] = apply_drop(s[j], gi, gj0, ar, ac);
+                if (gi >= ar - 2 && gi <= ar + 2) {
+                    if (cl >= ac - 2 && cl <= ac + 2 && (hl[j] == kFlammable || hl[j] == kBurning)) hl[j] = 0;
+                    if (cr >= ac - 2 && cr <= ac + 2 && (hr[j] == kFlammable || hr[j] == kBurning)) hr[j] = 0;
                 }
             }
-            __syncthreads();
         }
     }
 
-    // -- 3. flags of own cells: burning (bits 0-3), front (bits 4-7), and the
-    //       burning-neighbour masks of the four cells (8 bits each)
+    // -- 3. neighbour dwords across the row segment, then flags of own cells:
+    //       burning (bits 0-3), front (bits 4-7) and the burning-neighbour
+    //       masks of the four cells (8 bits each)
+    uint32_t win[RT + 2];  // burning bits of the 6-cell window of each loaded row
+#pragma unroll
+    for (int j = 0; j < RT + 2; ++j) {
+        uint32_t left = __shfl_up(s[j], 1, GX), right = __shfl_down(s[j], 1, GX);
+        if (tx == 0) left = hl[j] << 24;
+        if (tx == GX - 1) right = hr[j];
+        win[j] = row_window(left, s[j], right);
+    }
     uint32_t flags[RT], nbks[RT];
     uint32_t my_cells = 0, my_groups = 0;
 #pragma unroll
     for (int m = 0; m < RT; ++m) {
-        const int lr = ty + m * RP;
-        const int gi = td.r0 + lr;
         flags[m] = 0;
         nbks[m] = 0;
-        if (!(gi < H && gj0 < W)) continue;
-        const uint32_t* up = lds + lr * SD + tx;
-        const uint32_t* md = up + SD;
-        const uint32_t* dn = md + SD;
-        const uint32_t own = md[1];
-        const uint32_t up6 = row_window(up[0], up[1], up[2]);
-        const uint32_t md6 = row_window(md[0], own, md[2]);
-        const uint32_t dn6 = row_window(dn[0], dn[1], dn[2]);
+        if (!(row0 + m < H && gj0 < W)) continue;
+        const uint32_t up6 = win[m], md6 = win[m + 1], dn6 = win[m + 2];
         const uint32_t ud = up6 | dn6;
         const uint32_t near = (ud | (ud >> 1) | (ud >> 2) | md6 | (md6 >> 2)) & 0xFu;
-        const uint32_t burn = pack4(burning_flags(own));
-        const uint32_t front = pack4(flammable_flags(own)) & near;
+        const uint32_t burn = pack4(burning_flags(s[m + 1]));
+        const uint32_t front = pack4(flammable_flags(s[m + 1])) & near;
         uint32_t nb = 0;
 #pragma unroll
         for (int c = 0; c < 4; ++c)
@@ -326,10 +326,11 @@ __global__ __launch_bounds__(kBlock) void stoch_step_kernel(
         my_cells += __popc(front);
         my_groups += (burn | front) != 0u;
     }
+    __syncthreads();  // lds_ew visible (one wave: no waiting on other waves)
 
-    // -- 4. list front cells and draw groups across the workgroup
-    uint32_t totals;
-    const uint32_t off = block_exclusive_scan(my_cells | (my_groups << 16), lds_scan, totals);
+    // -- 4. list front cells and draw groups across the wave
+    uint32_t totals = 0, off = 0;
+    if (__any(my_groups != 0u)) off = wave_exclusive_scan(my_cells | (my_groups << 16), totals);
     const uint32_t n_cells = totals & 0xFFFFu, n_groups = totals >> 16;
     const bool listed = n_cells <= (uint32_t)kCellCap && n_groups <= (uint32_t)kGroupCap;
     uint32_t slot[RT];  // per row: group index | first cell index << 16
@@ -339,25 +340,24 @@ __global__ __launch_bounds__(kBlock) void stoch_step_kernel(
         uint32_t ci = off & 0xFFFFu, gidx = off >> 16;
 #pragma unroll
         for (int m = 0; m < RT; ++m) {
-            slot[m] = 0;
             const uint32_t burn = flags[m] & 0xFu, front = flags[m] >> 4;
             if (!(burn | front)) continue;
             slot[m] = gidx | (ci << 16);
-            lds_group[gidx] = (uint16_t)(tid | (m << 8));
+            lds_group[gidx] = (uint16_t)(lane | (m << 6));
 #pragma unroll
             for (int c = 0; c < 4; ++c)
                 if ((front >> c) & 1u)
-                    lds_cell[ci++] = (uint32_t)tid | ((uint32_t)m << 8) | ((uint32_t)c << 11) |
-                                     (((nbks[m] >> (8 * c)) & 0xFFu) << 13) | (gidx << 21);
+                    lds_cell[ci++] = (uint32_t)lane | ((uint32_t)m << 6) | ((uint32_t)c << 9) |
+                                     (((nbks[m] >> (8 * c)) & 0xFFu) << 11) | (gidx << 19);
             ++gidx;
         }
         __syncthreads();
         // one Philox block per listed group
-        for (uint32_t gq = tid; gq < n_groups; gq += kBlock) {
+        for (uint32_t gq = lane; gq < n_groups; gq += kWave) {
             const uint32_t e = lds_group[gq];
-            const int otid = e & 0xFF, m = e >> 8;
-            const int gi = td.r0 + (otid >> gx_log) + m * RP;
-            const int gj = td.c0 + 4 * (otid & (GX - 1));
+            const int olane = e & 63, m = e >> 6;
+            const int gi = td.r0 + (olane >> gx_log) * RT + m;
+            const int gj = td.c0 + 4 * (olane & (GX - 1));
             const uint4 w = group_words<ALIGNED>((int64_t)gi * W + gj, t, ed.env_id, key);
             lds_u[gq * 4 + 0] = word_to_uniform(w.x);
             lds_u[gq * 4 + 1] = word_to_uniform(w.y);
@@ -366,12 +366,12 @@ __global__ __launch_bounds__(kBlock) void stoch_step_kernel(
         }
         __syncthreads();
         // lambda and p of each listed front cell
-        for (uint32_t cq = tid; cq < n_cells; cq += kBlock) {
+        for (uint32_t cq = lane; cq < n_cells; cq += kWave) {
             const uint32_t e = lds_cell[cq];
-            const int otid = e & 0xFF, m = (e >> 8) & 7, c = (e >> 11) & 3;
-            const uint32_t nbk = (e >> 13) & 0xFF, gq = e >> 21;
-            const int gi = td.r0 + (otid >> gx_log) + m * RP;
-            const int gj = td.c0 + 4 * (otid & (GX - 1)) + c;
+            const int olane = e & 63, m = (e >> 6) & 7, c = (e >> 9) & 3;
+            const uint32_t nbk = (e >> 11) & 0xFF, gq = e >> 19;
+            const int gi = td.r0 + (olane >> gx_log) * RT + m;
+            const int gj = td.c0 + 4 * (olane & (GX - 1)) + c;
             const float p = ignite_prob<WIND_CELL>(nbk, base + (int64_t)gi * W + gj, W, F, A, lds_ew);
             lds_dec[cq] = lds_u[gq * 4 + c] < p ? 1 : 0;
         }
@@ -382,10 +382,9 @@ __global__ __launch_bounds__(kBlock) void stoch_step_kernel(
     int cnt = 0;
 #pragma unroll
     for (int m = 0; m < RT; ++m) {
-        const int lr = ty + m * RP;
-        const int gi = td.r0 + lr;
+        const int gi = row0 + m;
         if (!(gi < H && gj0 < W)) continue;
-        const uint32_t own = lds[(lr + 1) * SD + tx + 1];
+        const uint32_t own = s[m + 1];
         const uint32_t burn = flags[m] & 0xFu, front = flags[m] >> 4;
         uint32_t out = own;
         if (burn | front) {
@@ -438,13 +437,8 @@ __global__ __launch_bounds__(kBlock) void stoch_step_kernel(
     // -- BURNING count of the env after the step --
     if (counts_row) {
 #pragma unroll
-        for (int off2 = 32; off2 > 0; off2 >>= 1) cnt += __shfl_xor(cnt, off2);
-        if ((tid & 63) == 0) lds_cnt[tid >> 6] = cnt;
-        __syncthreads();
-        if (tid == 0) {
-            const int total = lds_cnt[0] + lds_cnt[1] + lds_cnt[2] + lds_cnt[3];
-            if (total) atomicAdd(counts_row + td.env, total);
-        }
+        for (int o2 = 32; o2 > 0; o2 >>= 1) cnt += __shfl_xor(cnt, o2);
+        if (lane == 0 && cnt) atomicAdd(counts_row + td.env, cnt);
     }
 }
 
@@ -543,7 +537,7 @@ hipError_t launch_variant(hipStream_t s, const StepLaunch& L, const uint8_t* src
                           const uint32_t* t_base, uint32_t step, const int32_t* act, int32_t* cnt)
 {
     const int32_t per_xcd = (L.n_tiles + 7) / 8;
-    hipLaunchKernelGGL((stoch_step_kernel<AL, WC, RT, SK>), dim3(8 * per_xcd), dim3(kBlock), 0, s,
+    hipLaunchKernelGGL((stoch_step_kernel<AL, WC, RT, SK>), dim3(8 * per_xcd), dim3(kWave), 0, s,
                        L.tiles, L.n_tiles, per_xcd, L.envs, L.fields, L.args, src, dst, t_base,
                        step, act, cnt);
     return hipGetLastError();
