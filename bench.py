@@ -76,7 +76,7 @@ def bench_stochastic(args, torch, fs, firegen):
     log("[bench] workload generated: %d envs, %d cells" % (batch.n_env, batch.n_cells))
     sim = fs.FireSim.from_batch(batch, params, seed=seed)
     plan = {"tile_rows": args.tile_rows, "tile_width": args.tile_width,
-            "skip_static": args.skip_static, "graph": args.graph}
+            "skip_static": args.skip_static, "sparse": args.sparse, "graph": args.graph}
     sim.set_plan(**plan)
     init = sim.states.clone()
     stream = torch.cuda.current_stream()
@@ -111,8 +111,8 @@ def bench_stochastic(args, torch, fs, firegen):
     cells = float(batch.n_cells)
     value = cells * T / (ms / 1e3)
     achieved = STOCH_BYTES_PER_CELL * cells / (launch_ms / 1e3) / 1e9
-    plan_key = "tile_rows=%d,tile_width=%d,skip_static=%d" % (
-        sim.plan()["tile_rows"], sim.plan()["tile_width"], args.skip_static)
+    plan_key = "tile_rows=%d,tile_width=%d,skip_static=%d,sparse=%d" % (
+        sim.plan()["tile_rows"], sim.plan()["tile_width"], args.skip_static, args.sparse)
     traffic = stored_traffic(plan_key)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -170,6 +170,7 @@ def main():
     ap.add_argument("--tile-rows", type=int, default=4)
     ap.add_argument("--tile-width", type=int, default=256)
     ap.add_argument("--skip-static", type=int, default=0)
+    ap.add_argument("--sparse", type=int, default=0)
     ap.add_argument("--graph", type=int, default=1)
     ap.add_argument("--relaxed-reps", type=int, default=3)
     ap.add_argument("--no-relaxed", action="store_true")

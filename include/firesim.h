@@ -137,14 +137,35 @@ int sim_set_step(sim_handle* h, uint64_t t);
  *  temporal     steps fused per tile load (1 = one step per launch), 0 = default
  *  skip_static  1: only cells with a burning neighbour read fuel and
  *               elevation; 0: every cell reads its 10 bytes every step
+ *  sparse       1: after the first step of a call, a tile with no burning
+ *               cell in it or in its 8 neighbouring tiles, and no drop on it,
+ *               is not computed (its cells cannot change); 0: every tile runs
  *  graph        1: capture the T launches of a call into a HIP graph and
  *               replay it (re-captured when T, the pointers or the plan
  *               change); 0: launch directly */
 typedef struct {
-    int32_t tile_rows, tile_width, temporal, skip_static, graph;
+    int32_t tile_rows, tile_width, temporal, skip_static, sparse, graph;
 } sim_plan;
 int sim_set_plan(sim_handle* h, const sim_plan* plan);
 int sim_get_plan(const sim_handle* h, sim_plan* plan);
+
+/* Autotuner: times every candidate plan (tile_rows 1/2/4/8 x tile_width
+ * 64/256, with skip_static 0 and, if allow_skip, 1; sparse = allow_sparse)
+ * for T_probe steps of this batch starting from `states` (device, read only)
+ * at the handle's step counter, and makes the fastest the handle's plan
+ * (graph flag kept).
+ * Neither `states` nor the step counter change; the handle allocates and
+ * frees one scratch state buffer.  Synchronises `stream`.
+ *  results      host array of max_results entries or NULL: the plans tried,
+ *               fastest first, with their measured milliseconds per step
+ *  n_results    receives the number of entries written (may be NULL) */
+typedef struct {
+    sim_plan plan;
+    float ms_per_step;
+} sim_tune_result;
+int sim_autotune(sim_handle* h, const uint8_t* states, int32_t T_probe, int32_t allow_skip,
+                 int32_t allow_sparse, sim_tune_result* results, int32_t max_results,
+                 int32_t* n_results, void* stream);
 
 /* ---------------------------------------------------------------- relaxed */
 /* The relaxed (mean-field) state: per cell U = P(unburned), B = P(burning)
@@ -169,9 +190,15 @@ size_t sim_relaxed_workspace_bytes(const sim_handle* h, int32_t T, int32_t ckpt_
 /* T relaxed steps in place on (U, B) with parameters p (host; veg, p_base,
  * alpha_* and p_continue may differ from sim_init's; unburnable_mask and
  * cell_size must match).  Stores the checkpoints the backward needs in
- * `workspace` (device, >= sim_relaxed_workspace_bytes). */
+ * `workspace` (device, >= sim_relaxed_workspace_bytes).
+ *  form  SIM_FORM_PRODUCT: P = 1 - prod_k (1 - q_k B(u_k)) as above;
+ *        SIM_FORM_EXP: P = 1 - exp(-gamma(v) sum_k B(u_k) phi(u_k, k)), Eq. 4
+ *        with the burning indicator replaced by B (the paper's soft reading).
+ *        Both equal Eq. 4 on 0/1 states. */
+#define SIM_FORM_PRODUCT 0
+#define SIM_FORM_EXP 1
 int sim_step_relaxed_fwd(sim_handle* h, const sim_params* p, double* U, double* B, int32_t T,
-                         int32_t ckpt_every, void* workspace, size_t workspace_bytes,
+                         int32_t ckpt_every, int32_t form, void* workspace, size_t workspace_bytes,
                          void* stream);
 
 /* Soft-IoU loss of the final relaxed state against a binary target scar.
@@ -184,15 +211,27 @@ int sim_step_relaxed_fwd(sim_handle* h, const sim_params* p, double* U, double* 
 int sim_relaxed_loss(sim_handle* h, const double* U_T, const uint8_t* target, float* loss,
                      double* gU_T, double scale, void* stream);
 
+/* The paper's calibration loss (section 4): per env e, binary cross-entropy
+ * of S = clip(1 - U_T on burnable cells, 0 elsewhere; eps, 1 - eps) against
+ * the target scar Y, averaged over the env's cells, plus mse_weight times the
+ * mean squared error between the pool x pool block averages of S and Y
+ * (blocks at the far edges cover what is left).  loss[e] is written; gU_T
+ * (or NULL) receives scale * d loss[e] / d U_T as for sim_relaxed_loss
+ * (zero where S is clipped).  1 <= pool <= 64, 0 < eps < 0.5. */
+int sim_relaxed_loss_bce(sim_handle* h, const double* U_T, const uint8_t* target, int32_t pool,
+                         double mse_weight, double eps, float* loss, double* gU_T, double scale,
+                         void* stream);
+
 /* Gradient of a scalar objective J(U_T, B_T) with respect to the parameter
  * vector (p_base, alpha_w1, alpha_w2, alpha_s, alpha_gamma, p_continue,
  * veg[0..10]) through the T relaxed steps of the last sim_step_relaxed_fwd
- * call on the same workspace (same p, T, ckpt_every): recomputes each
+ * call on the same workspace (same p, T, ckpt_every, form): recomputes each
  * checkpoint segment forward, then runs the adjoint step backward.
  *  gU_T, gB_T  device double[n_cells]: dJ/dU_T, dJ/dB_T (gB_T may be NULL = 0).
  *  grad        device double[SIM_N_THETA], overwritten. */
 int sim_step_relaxed_bwd(sim_handle* h, const sim_params* p, const double* gU_T,
-                         const double* gB_T, int32_t T, int32_t ckpt_every, void* workspace,
+                         const double* gB_T, int32_t T, int32_t ckpt_every, int32_t form,
+                         void* workspace,
                          size_t workspace_bytes, double* grad, void* stream);
 
 /* ------------------------------------------------------------- diagnostics */

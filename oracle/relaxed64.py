@@ -1,4 +1,4 @@
-"""Relaxed (mean-field) fire spread, its soft-IoU loss and its adjoint, in float64.
+"""Relaxed (mean-field) fire spread, its calibration losses and its adjoint, in float64.
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
@@ -10,22 +10,28 @@ carries per cell the probabilities (p_un, p_burn, p_bd) and updates
     p_bd'   = p_bd + p_burn (1 - p_continue).
 
 Here U = p_un, B = p_burn; p_bd = 1 - U - B never feeds back, so it is not
-carried.  The ignition term takes b(u) = B(u) in the product form
+carried.  Two readings of p_ignite with b(u) = B(u):
 
-    p_ignite(v) = 1 - prod_k (1 - q_k(v) B(u_k)),
-    q_k(v)      = 1 - exp(-gamma(v) phi(u_k, k)),   u_k = v - D_k,
+  form "product":  p_ignite(v) = 1 - prod_k (1 - q_k(v) B(u_k)),
+                   q_k(v) = 1 - exp(-gamma(v) phi(u_k, k)),  u_k = v - D_k;
+  form "exp":      p_ignite(v) = 1 - exp(-gamma(v) sum_k B(u_k) phi(u_k, k))
+                   (Eq. 4 with the burning indicator replaced by B).
 
-which is Eq. 4 exactly whenever B is 0/1 (prod_k exp(-gamma phi_k b_k) =
-exp(-gamma lambda)).  phi follows Eqs. 1-3 with the wind and slope exponent
-written as in the paper: kappa_wind = exp(a_w1 V) exp(a_w2 V (cos(ang_k -
-Theta) - 1)), kappa_slope = exp(a_s S).
+Both equal Eq. 4 when B is 0/1.  phi follows Eqs. 1-3 with the wind and slope
+factors written as in the paper: kappa_wind = exp(a_w1 V) exp(a_w2 V
+(cos(ang_k - Theta) - 1)), kappa_slope = exp(a_s S).
 
-The loss is one minus the soft intersection-over-union of the soft scar
-S = 1 - U_T (burnable cells) with a binary target scar Y, averaged over envs.
+Losses of the final state, S = 1 - U_T on burnable cells (0 elsewhere) against
+a binary target scar Y, averaged over envs:
+  "iou":  1 - sum S Y / (sum S + sum Y - sum S Y);
+  "bce":  binary cross-entropy of clip(S, eps, 1 - eps) against Y (mean over
+          cells) plus w times the mean squared error between k x k average
+          pools of S and Y (the paper's calibration loss, section 4).
 
-The adjoint is reverse-mode differentiation of exactly these formulas.  q does
-not change over time, so its adjoint is summed over all steps first and then
-taken through q -> (phi, gamma) -> parameters once.
+The adjoint is reverse-mode differentiation of exactly these formulas.  The
+per-edge phi and the per-cell gamma do not change over time, so their
+adjoints are summed over all steps first and then taken to the parameters
+once.
 
 Parameter vector (THETA_NAMES): p_base, alpha_w1, alpha_w2, alpha_s,
 alpha_gamma, p_continue, veg[0..10].
@@ -42,6 +48,7 @@ DIRS = ((0, 1), (-1, 1), (-1, 0), (-1, -1), (0, -1), (1, -1), (1, 0), (1, 1))
 THETA_NAMES = ("p_base", "alpha_w1", "alpha_w2", "alpha_s", "alpha_gamma", "p_continue") + \
     tuple("veg%d" % c for c in range(11))
 N_THETA = len(THETA_NAMES)
+FORMS = ("product", "exp")
 
 
 def theta_from_params(p) -> np.ndarray:
@@ -138,17 +145,24 @@ def edge_terms(env: Env64, theta: np.ndarray) -> dict:
     return out
 
 
-def ignite_prob(q: list, B: np.ndarray) -> np.ndarray:
-    """p_ignite = 1 - prod_k (1 - q_k B(u_k))."""
-    prod = np.ones_like(B)
-    for k in range(8):
-        prod = prod * (1.0 - q[k] * shift_from_source(B, k))
-    return 1.0 - prod
+def ignite_prob(terms: dict, B: np.ndarray, form: str = "product") -> np.ndarray:
+    """p_ignite of every cell from the soft burning mass B."""
+    if form == "product":
+        prod = np.ones_like(B)
+        for k in range(8):
+            prod = prod * (1.0 - terms["q"][k] * shift_from_source(B, k))
+        return 1.0 - prod
+    if form == "exp":
+        lam = np.zeros_like(B)
+        for k in range(8):
+            lam = lam + terms["phi"][k] * shift_from_source(B, k)
+        return -np.expm1(-terms["gamma"] * lam)
+    raise ValueError(form)
 
 
-def step(U, B, q, p_continue):
-    """One relaxed step (Eqs. 5-10 with the product-form ignition)."""
-    P = ignite_prob(q, B)
+def step(U, B, terms, p_continue, form="product"):
+    """One relaxed step (Eqs. 5-10)."""
+    P = ignite_prob(terms, B, form)
     newly = U * P
     return U - newly, newly + p_continue * B
 
@@ -168,12 +182,12 @@ def initial_state(batch, e) -> tuple:
     return U, B, burnable
 
 
-def forward(env: Env64, theta, U0, B0, T) -> tuple:
+def forward(env: Env64, theta, U0, B0, T, form="product") -> tuple:
     """Return the lists U[0..T], B[0..T] and the edge terms."""
     terms = edge_terms(env, theta)
     Us, Bs = [U0.astype(np.float64)], [B0.astype(np.float64)]
     for _ in range(T):
-        U, B = step(Us[-1], Bs[-1], terms["q"], theta[5])
+        U, B = step(Us[-1], Bs[-1], terms, theta[5], form)
         Us.append(U)
         Bs.append(B)
     return Us, Bs, terms
@@ -193,56 +207,106 @@ def soft_iou_loss(U_T, Y, burnable) -> tuple:
     return L, np.where(burnable, -dL_dS, 0.0)
 
 
-def adjoint(env: Env64, theta, Us, Bs, terms, gU_T, gB_T=None) -> np.ndarray:
+def _pool(A, k):
+    """Mean over the k x k blocks of A (blocks at the far edges may be smaller)."""
+    H, W = A.shape
+    nb_r, nb_c = -(-H // k), -(-W // k)
+    out = np.zeros((nb_r, nb_c))
+    cnt = np.zeros((nb_r, nb_c))
+    ii, jj = np.meshgrid(np.arange(H) // k, np.arange(W) // k, indexing="ij")
+    np.add.at(out, (ii, jj), A)
+    np.add.at(cnt, (ii, jj), 1.0)
+    return out / cnt, cnt, (ii, jj)
+
+
+def bce_pool_loss(U_T, Y, burnable, pool=8, mse_weight=1.0, eps=1e-6) -> tuple:
+    """BCE of clip(S, eps, 1-eps) against Y over all cells plus mse_weight x
+    MSE of the pool x pool block means of S and Y.  Returns (L, dL/dU_T)."""
+    S = np.where(burnable, 1.0 - U_T, 0.0)
+    Yf = Y.astype(np.float64)
+    n = S.size
+    Sc = np.clip(S, eps, 1.0 - eps)
+    bce = -np.sum(Yf * np.log(Sc) + (1.0 - Yf) * np.log(1.0 - Sc)) / n
+    inside = (S > eps) & (S < 1.0 - eps)
+    dbce_dS = np.where(inside, (-(Yf / Sc) + (1.0 - Yf) / (1.0 - Sc)) / n, 0.0)
+    pS, cnt, idx = _pool(S, pool)
+    pY, _, _ = _pool(Yf, pool)
+    m = pS.size
+    mse = np.sum((pS - pY) ** 2) / m
+    dmse_dpS = 2.0 * (pS - pY) / m
+    dmse_dS = (dmse_dpS / cnt)[idx]
+    dL_dS = dbce_dS + mse_weight * dmse_dS
+    return bce + mse_weight * mse, np.where(burnable, -dL_dS, 0.0)
+
+
+def loss_fn(kind, U_T, Y, burnable, **kw):
+    if kind == "iou":
+        return soft_iou_loss(U_T, Y, burnable)
+    if kind == "bce":
+        return bce_pool_loss(U_T, Y, burnable, **kw)
+    raise ValueError(kind)
+
+
+def adjoint(env: Env64, theta, Us, Bs, terms, gU_T, gB_T=None, form="product") -> np.ndarray:
     """Reverse-mode gradient of a scalar loss with dL/dU_T = gU_T (and dL/dB_T
     = gB_T, default 0) with respect to THETA."""
     T = len(Us) - 1
     p_c = theta[5]
-    q = terms["q"]
+    q, phi_k = terms["q"], terms["phi"]
+    gamma = terms["gamma"]
     gU = gU_T.astype(np.float64).copy()
     gB = np.zeros_like(gU) if gB_T is None else gB_T.astype(np.float64).copy()
-    Qbar = [np.zeros_like(gU) for _ in range(8)]
+    phibar = [np.zeros_like(gU) for _ in range(8)]   # summed over time
+    gamma_bar = np.zeros_like(gU)
     grad = np.zeros(N_THETA)
     for t in range(T - 1, -1, -1):
         U, B = Us[t], Bs[t]
         Bsrc = [shift_from_source(B, k) for k in range(8)]
-        fac = [1.0 - q[k] * Bsrc[k] for k in range(8)]
-        # exclusive products prod_{j != k} fac_j by prefix and suffix products
-        pre = [np.ones_like(U)]
-        for k in range(8):
-            pre.append(pre[-1] * fac[k])
-        suf = [np.ones_like(U)] * 9
-        for k in range(7, -1, -1):
-            suf[k] = suf[k + 1] * fac[k]
-        P = 1.0 - pre[8]
-        nbar = gB - gU                   # adjoint of newly = U P
-        gU_new = gU + nbar * P
-        Pbar = nbar * U
-        grad[5] += float(np.sum(gB * B))  # B' = newly + p_c B
         gB_new = p_c * gB
-        for k in range(8):
-            excl = pre[k] * suf[k + 1]
-            gB_new = gB_new + scatter_to_source(Pbar * q[k] * excl, k)
-            Qbar[k] += Pbar * Bsrc[k] * excl
-        gU, gB = gU_new, gB_new
-    # through q_k = 1 - exp(-gamma phi_k)
+        if form == "product":
+            fac = [1.0 - q[k] * Bsrc[k] for k in range(8)]
+            # exclusive products prod_{j != k} fac_j by prefix and suffix products
+            pre = [np.ones_like(U)]
+            for k in range(8):
+                pre.append(pre[-1] * fac[k])
+            suf = [np.ones_like(U)] * 9
+            for k in range(7, -1, -1):
+                suf[k] = suf[k + 1] * fac[k]
+            P = 1.0 - pre[8]
+            nbar = gB - gU                   # adjoint of newly = U P
+            Pbar = nbar * U
+            for k in range(8):
+                excl = pre[k] * suf[k + 1]
+                gB_new = gB_new + scatter_to_source(Pbar * q[k] * excl, k)
+                ybar = Pbar * Bsrc[k] * excl * (1.0 - q[k])   # qbar dq/dy, y = gamma phi
+                phibar[k] += ybar * gamma
+                gamma_bar += ybar * phi_k[k]
+        else:
+            lam = np.zeros_like(U)
+            for k in range(8):
+                lam = lam + phi_k[k] * Bsrc[k]
+            P = -np.expm1(-gamma * lam)
+            nbar = gB - gU
+            Pbar = nbar * U
+            lbar = Pbar * gamma * (1.0 - P)               # dP/dlambda = gamma exp(-gamma lambda)
+            gamma_bar += Pbar * lam * (1.0 - P)
+            for k in range(8):
+                gB_new = gB_new + scatter_to_source(lbar * phi_k[k], k)
+                phibar[k] += lbar * Bsrc[k]
+        grad[5] += float(np.sum(gB * B))  # B' = newly + p_c B
+        gU, gB = gU + nbar * P, gB_new
+    # through phi_k = p_base g(u) kappa_k and gamma = alpha_gamma g(v)
     p_base, a_gamma = theta[0], theta[4]
     g = terms["g"]
-    gamma = terms["gamma"]
     gbar = np.zeros_like(g)       # adjoint of the fuel term g per cell
-    gamma_bar = np.zeros_like(g)
     for k in range(8):
-        ybar = Qbar[k] * (1.0 - q[k])          # dq/dy = exp(-y) = 1 - q
-        phi = terms["phi"][k]
-        phibar = ybar * gamma
-        gamma_bar += ybar * phi
         kappa = np.where(env.valid[k], terms["kappa"][k], 0.0)
-        grad[0] += float(np.sum(phibar * terms["g_src"][k] * kappa))
-        xbar = phibar * phi                       # phi = p_base g_u exp(x)
+        grad[0] += float(np.sum(phibar[k] * terms["g_src"][k] * kappa))
+        xbar = phibar[k] * phi_k[k]                  # phi = p_base g_u exp(x)
         grad[1] += float(np.sum(xbar * terms["V_src"][k]))
         grad[2] += float(np.sum(xbar * terms["cosdev"][k]))
         grad[3] += float(np.sum(xbar * np.where(env.valid[k], terms["S"][k], 0.0)))
-        gbar += scatter_to_source(phibar * p_base * kappa, k)
+        gbar += scatter_to_source(phibar[k] * p_base * kappa, k)
     grad[4] += float(np.sum(gamma_bar * g))
     gbar += gamma_bar * a_gamma
     contrib = gbar * (1.0 + env.den)             # g = (1 + veg[c]) (1 + den)
@@ -250,12 +314,12 @@ def adjoint(env: Env64, theta, Us, Bs, terms, gU_T, gB_T=None) -> np.ndarray:
     return grad
 
 
-def loss_and_grad(batch, theta, T, Y_list, env_ids=None, cell_size=30.0) -> tuple:
-    """Mean soft-IoU loss over the given envs after T relaxed steps, its
-    gradient, and the final U_T per env."""
+def loss_and_grad(batch, theta, T, Y_list, env_ids=None, cell_size=30.0, form="product",
+                  loss="iou", **loss_kw) -> tuple:
+    """Mean loss over the given envs after T relaxed steps, its gradient,
+    and the final (U_T, B_T) per env."""
     theta = np.asarray(theta, np.float64)
-    env_ids = range(batch.n_env) if env_ids is None else env_ids
-    env_ids = list(env_ids)
+    env_ids = list(range(batch.n_env) if env_ids is None else env_ids)
     n = len(env_ids)
     L = 0.0
     grad = np.zeros(N_THETA)
@@ -263,15 +327,16 @@ def loss_and_grad(batch, theta, T, Y_list, env_ids=None, cell_size=30.0) -> tupl
     for idx, e in enumerate(env_ids):
         env = from_batch(batch, e, cell_size)
         U0, B0, burnable = initial_state(batch, e)
-        Us, Bs, terms = forward(env, theta, U0, B0, T)
-        Le, gU = soft_iou_loss(Us[-1], Y_list[idx], burnable)
+        Us, Bs, terms = forward(env, theta, U0, B0, T, form)
+        Le, gU = loss_fn(loss, Us[-1], Y_list[idx], burnable, **loss_kw)
         L += Le / n
-        grad += adjoint(env, theta, Us, Bs, terms, gU / n)
+        grad += adjoint(env, theta, Us, Bs, terms, gU / n, form=form)
         finals.append((Us[-1], Bs[-1]))
     return L, grad, finals
 
 
-def loss_only(batch, theta, T, Y_list, env_ids=None, cell_size=30.0) -> float:
+def loss_only(batch, theta, T, Y_list, env_ids=None, cell_size=30.0, form="product", loss="iou",
+              **loss_kw) -> float:
     theta = np.asarray(theta, np.float64)
     env_ids = list(range(batch.n_env) if env_ids is None else env_ids)
     n = len(env_ids)
@@ -279,6 +344,6 @@ def loss_only(batch, theta, T, Y_list, env_ids=None, cell_size=30.0) -> float:
     for idx, e in enumerate(env_ids):
         env = from_batch(batch, e, cell_size)
         U0, B0, burnable = initial_state(batch, e)
-        Us, Bs, _ = forward(env, theta, U0, B0, T)
-        L += soft_iou_loss(Us[-1], Y_list[idx], burnable)[0] / n
+        Us, Bs, _ = forward(env, theta, U0, B0, T, form)
+        L += loss_fn(loss, Us[-1], Y_list[idx], burnable, **loss_kw)[0] / n
     return L

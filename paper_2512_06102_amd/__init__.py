@@ -25,8 +25,9 @@ THETA_NAMES = ("p_base", "alpha_w1", "alpha_w2", "alpha_s", "alpha_gamma", "p_co
     tuple("veg%d" % c for c in range(N_CLASSES))
 
 EXPORTED = ("sim_init", "sim_step", "sim_get_step", "sim_set_step", "sim_set_plan", "sim_get_plan",
+            "sim_autotune",
             "sim_relaxed_init", "sim_relaxed_workspace_bytes", "sim_step_relaxed_fwd",
-            "sim_relaxed_loss", "sim_step_relaxed_bwd", "sim_debug_exp", "sim_debug_philox",
+            "sim_relaxed_loss", "sim_relaxed_loss_bce", "sim_step_relaxed_bwd", "sim_debug_exp", "sim_debug_philox",
             "sim_last_error", "sim_destroy")
 
 
@@ -47,7 +48,11 @@ class SimEnv(ctypes.Structure):
 class SimPlan(ctypes.Structure):
     _fields_ = [("tile_rows", ctypes.c_int32), ("tile_width", ctypes.c_int32),
                 ("temporal", ctypes.c_int32), ("skip_static", ctypes.c_int32),
-                ("graph", ctypes.c_int32)]
+                ("sparse", ctypes.c_int32), ("graph", ctypes.c_int32)]
+
+
+class SimTuneResult(ctypes.Structure):
+    _fields_ = [("plan", SimPlan), ("ms_per_step", ctypes.c_float)]
 
 
 class SimError(RuntimeError):
@@ -73,12 +78,15 @@ def lib() -> ctypes.CDLL:
         L.sim_set_step.argtypes = [P, U64]
         L.sim_set_plan.argtypes = [P, P]
         L.sim_get_plan.argtypes = [P, P]
+        L.sim_autotune.argtypes = [P, P, I32, I32, I32, P, I32, ctypes.POINTER(I32), P]
         L.sim_relaxed_init.argtypes = [P, P, P, P]
         L.sim_relaxed_workspace_bytes.argtypes = [P, I32, I32]
         L.sim_relaxed_workspace_bytes.restype = SZ
-        L.sim_step_relaxed_fwd.argtypes = [P, P, P, P, I32, I32, P, SZ, P]
-        L.sim_relaxed_loss.argtypes = [P, P, P, P, P, ctypes.c_double, P]
-        L.sim_step_relaxed_bwd.argtypes = [P, P, P, P, I32, I32, P, SZ, P, P]
+        D = ctypes.c_double
+        L.sim_step_relaxed_fwd.argtypes = [P, P, P, P, I32, I32, I32, P, SZ, P]
+        L.sim_relaxed_loss.argtypes = [P, P, P, P, P, D, P]
+        L.sim_relaxed_loss_bce.argtypes = [P, P, P, I32, D, D, P, P, D, P]
+        L.sim_step_relaxed_bwd.argtypes = [P, P, P, P, I32, I32, I32, P, SZ, P, P]
         L.sim_debug_exp.argtypes = [P, P, I64, P]
         L.sim_debug_philox.argtypes = [P, P, P, I64, P]
         L.sim_last_error.argtypes = [P]
@@ -90,6 +98,12 @@ def lib() -> ctypes.CDLL:
 
 def _stream(device=None) -> int:
     return torch.cuda.current_stream(device).cuda_stream
+
+
+def _form(form: str) -> int:
+    if form not in ("product", "exp"):
+        raise ValueError("form must be 'product' or 'exp', got %r" % (form,))
+    return 0 if form == "product" else 1
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -229,15 +243,31 @@ class FireSim:
     def t(self, value: int):
         _check(lib().sim_set_step(self.handle, int(value)), self.handle)
 
-    def set_plan(self, tile_rows=0, tile_width=0, temporal=0, skip_static=0, graph=0):
-        p = SimPlan(tile_rows, tile_width, temporal, skip_static, graph)
+    def set_plan(self, tile_rows=0, tile_width=0, temporal=0, skip_static=0, sparse=0, graph=0):
+        p = SimPlan(tile_rows, tile_width, temporal, skip_static, sparse, graph)
         _check(lib().sim_set_plan(self.handle, ctypes.byref(p)), self.handle)
 
     def plan(self) -> dict:
         p = SimPlan()
         _check(lib().sim_get_plan(self.handle, ctypes.byref(p)), self.handle)
         return {"tile_rows": p.tile_rows, "tile_width": p.tile_width, "temporal": p.temporal,
+                "sparse": p.sparse,
                 "skip_static": p.skip_static, "graph": p.graph}
+
+    def autotune(self, T_probe: int = 10, allow_skip: bool = True, allow_sparse: bool = False) -> list:
+        """Time every candidate plan on this batch (states and step counter
+        unchanged) and adopt the fastest; returns [(plan dict, ms/step)]."""
+        res = (SimTuneResult * 32)()
+        n = ctypes.c_int32(0)
+        _check(lib().sim_autotune(self.handle, _ptr(self.states), int(T_probe), int(allow_skip),
+                                  int(allow_sparse), res, 32, ctypes.byref(n), self._s()), self.handle)
+        out = []
+        for i in range(n.value):
+            p = res[i].plan
+            out.append(({"tile_rows": p.tile_rows, "tile_width": p.tile_width,
+                         "skip_static": p.skip_static, "sparse": p.sparse},
+                        float(res[i].ms_per_step)))
+        return out
 
     # ------------------------------------------------------------- relaxed
     def relaxed_init(self):
@@ -250,10 +280,10 @@ class FireSim:
         n = lib().sim_relaxed_workspace_bytes(self.handle, int(T), int(ckpt_every))
         return torch.empty(max(int(n), 1), dtype=torch.uint8, device=self.device)
 
-    def relaxed_fwd(self, params: SimParams, U, B, T, ckpt_every, ws):
+    def relaxed_fwd(self, params: SimParams, U, B, T, ckpt_every, ws, form: str = "product"):
         _check(lib().sim_step_relaxed_fwd(self.handle, ctypes.byref(params), _ptr(U), _ptr(B),
-                                          int(T), int(ckpt_every), _ptr(ws), ws.numel(), self._s()),
-               self.handle)
+                                          int(T), int(ckpt_every), _form(form), _ptr(ws), ws.numel(),
+                                          self._s()), self.handle)
 
     def relaxed_loss(self, U_T, target, scale: float = 1.0, want_grad: bool = True):
         loss = torch.empty(self.n_env, dtype=torch.float32, device=self.device)
@@ -262,30 +292,90 @@ class FireSim:
                                       float(scale), self._s()), self.handle)
         return loss, g
 
-    def relaxed_bwd(self, params: SimParams, gU_T, gB_T, T, ckpt_every, ws) -> torch.Tensor:
+    def relaxed_loss_bce(self, U_T, target, pool: int = 8, mse_weight: float = 1.0, eps: float = 1e-6,
+                         scale: float = 1.0, want_grad: bool = True):
+        """Per-env BCE of the clipped soft scar plus mse_weight x MSE of its
+        pool x pool block means, and scale x dL/dU_T."""
+        loss = torch.empty(self.n_env, dtype=torch.float32, device=self.device)
+        g = torch.empty_like(U_T) if want_grad else None
+        _check(lib().sim_relaxed_loss_bce(self.handle, _ptr(U_T), _ptr(target), int(pool),
+                                          float(mse_weight), float(eps), _ptr(loss), _ptr(g),
+                                          float(scale), self._s()), self.handle)
+        return loss, g
+
+    def relaxed_loss_any(self, kind: str, U_T, target, scale: float = 1.0, **kw):
+        if kind == "iou":
+            return self.relaxed_loss(U_T, target, scale=scale)
+        if kind == "bce":
+            return self.relaxed_loss_bce(U_T, target, scale=scale, **kw)
+        raise ValueError("loss must be 'iou' or 'bce', got %r" % (kind,))
+
+    def relaxed_bwd(self, params: SimParams, gU_T, gB_T, T, ckpt_every, ws,
+                    form: str = "product") -> torch.Tensor:
         grad = torch.empty(N_THETA, dtype=torch.float64, device=self.device)
         _check(lib().sim_step_relaxed_bwd(self.handle, ctypes.byref(params), _ptr(gU_T), _ptr(gB_T),
-                                          int(T), int(ckpt_every), _ptr(ws), ws.numel(), _ptr(grad),
-                                          self._s()), self.handle)
+                                          int(T), int(ckpt_every), _form(form), _ptr(ws), ws.numel(),
+                                          _ptr(grad), self._s()), self.handle)
         return grad
 
 
 class RelaxedCalibrationLoss(torch.autograd.Function):
-    """Mean soft-IoU loss of T relaxed steps as a function of the 17
+    """Mean per-env loss of T relaxed steps as a function of the 17
     parameters theta (float64 CPU tensor), with the library's adjoint as the
-    backward.  forward(theta, sim, target, T, ckpt_every) -> scalar."""
+    backward.  forward(theta, sim, target, T, ckpt_every, form, loss, loss_kw)
+    -> scalar; form is "product" or "exp", loss "iou" (soft IoU) or "bce"
+    (BCE + pooled MSE, loss_kw: pool, mse_weight, eps)."""
 
     @staticmethod
-    def forward(ctx, theta, sim: FireSim, target, T: int, ckpt_every: int = 10):
+    def forward(ctx, theta, sim: FireSim, target, T: int, ckpt_every: int = 10, form: str = "product",
+                loss: str = "iou", loss_kw: Optional[dict] = None):
         p = params_with_theta(sim.params, theta.detach().cpu().tolist())
         U, B = sim.relaxed_init()
         ws = sim.relaxed_workspace(T, ckpt_every)
-        sim.relaxed_fwd(p, U, B, T, ckpt_every, ws)
-        loss, gU = sim.relaxed_loss(U, target, scale=1.0 / sim.n_env)
-        ctx.sim, ctx.p, ctx.T, ctx.k, ctx.ws, ctx.gU = sim, p, T, ckpt_every, ws, gU
-        return loss.double().mean().cpu()
+        sim.relaxed_fwd(p, U, B, T, ckpt_every, ws, form)
+        L, gU = sim.relaxed_loss_any(loss, U, target, scale=1.0 / sim.n_env, **(loss_kw or {}))
+        ctx.sim, ctx.p, ctx.T, ctx.k, ctx.ws, ctx.gU, ctx.form = sim, p, T, ckpt_every, ws, gU, form
+        return L.double().mean().cpu()
 
     @staticmethod
     def backward(ctx, grad_out):
-        g = ctx.sim.relaxed_bwd(ctx.p, ctx.gU, None, ctx.T, ctx.k, ctx.ws)
-        return g.cpu() * grad_out, None, None, None, None
+        g = ctx.sim.relaxed_bwd(ctx.p, ctx.gU, None, ctx.T, ctx.k, ctx.ws, ctx.form)
+        return g.cpu() * grad_out, None, None, None, None, None, None, None
+
+
+def calibrate(sim: FireSim, target, T: int, theta0, steps: int = 50, lr: float = 0.02,
+              ckpt_every: int = 10, form: str = "product", loss: str = "iou",
+              loss_kw: Optional[dict] = None, fixed: Sequence[int] = (),
+              lower=None, upper=None, callback=None):
+    """Gradient-based parameter calibration: Adam on the 17 parameters against
+    the observed scars `target`, each iteration one relaxed forward + adjoint
+    in the library.  Parameters listed in `fixed` are not updated; after each
+    update theta is clamped to [lower, upper] (default: p_continue and the
+    probabilities in [0, 1], the rest unbounded, p_base >= 0).  Returns
+    (theta, losses)."""
+    theta = torch.tensor([float(v) for v in theta0], dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([theta], lr=lr)
+    lo = torch.full((N_THETA,), -float("inf"), dtype=torch.float64)
+    hi = torch.full((N_THETA,), float("inf"), dtype=torch.float64)
+    lo[0], lo[4], lo[5], hi[5] = 0.0, 0.0, 0.0, 1.0
+    lo[6:] = -0.99
+    if lower is not None:
+        lo = torch.as_tensor(lower, dtype=torch.float64)
+    if upper is not None:
+        hi = torch.as_tensor(upper, dtype=torch.float64)
+    mask = torch.ones(N_THETA, dtype=torch.float64)
+    for i in fixed:
+        mask[i] = 0.0
+    losses = []
+    for it in range(steps):
+        opt.zero_grad()
+        L = RelaxedCalibrationLoss.apply(theta, sim, target, T, ckpt_every, form, loss, loss_kw)
+        L.backward()
+        theta.grad.mul_(mask)
+        opt.step()
+        with torch.no_grad():
+            theta.copy_(torch.maximum(torch.minimum(theta, hi), lo))
+        losses.append(float(L))
+        if callback is not None:
+            callback(it, float(L), theta.detach().clone())
+    return theta.detach(), losses

@@ -44,7 +44,7 @@ struct sim_handle {
     bool wind_cell = false;
     uint64_t seed = 0;
     uint64_t t = 0;
-    sim_plan plan{4, 256, 1, 0, 0};
+    sim_plan plan{4, 256, 1, 0, 0, 0};
 
     EnvDev* d_envs = nullptr;
     float* d_g = nullptr;
@@ -56,6 +56,9 @@ struct sim_handle {
     uint8_t* d_tmp = nullptr;          // ping-pong state buffer
     uint32_t* d_t = nullptr;           // step counter base read by the step kernels
     TileDesc* d_tiles = nullptr;
+    int32_t* d_tile_nbr = nullptr;     // [n_tiles][8] neighbouring tiles (-1 off the env)
+    int32_t* d_tile_burn = nullptr;    // [2][n_tiles] burning cells per tile (sparse plan)
+    int32_t* d_tile_eq = nullptr;      // [n_tiles] both state buffers agree on the tile
     int32_t n_tiles = 0;
     int32_t tiles_rt = 0;              // tile_rows the tile list was built for
     int32_t tiles_tw = 0;              // tile_width the tile list was built for
@@ -91,7 +94,7 @@ int fail(sim_handle* h, int code, const char* fmt, ...)
 void free_all(sim_handle* h)
 {
     void* ptrs[] = {h->d_envs, h->d_g, h->d_E, h->d_cls, h->d_den, h->d_wind, h->d_init_states,
-                    h->d_tmp, h->d_t, h->d_tiles};
+                    h->d_tmp, h->d_t, h->d_tiles, h->d_tile_nbr, h->d_tile_burn, h->d_tile_eq};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (h->graph.exec) (void)hipGraphExecDestroy(h->graph.exec);
@@ -123,23 +126,42 @@ int tile_width_for(int W, int max_width)
     return w < max_width ? w : max_width;
 }
 
-// Tile list: env-major, then row band, then column band.
+// Tile list: env-major, then row band, then column band; with each tile's 8
+// neighbouring tiles (same env) for the sparse plan.
 int build_tiles(sim_handle* h, int rt, int max_width)
 {
     std::vector<TileDesc> tiles;
+    std::vector<int32_t> nbr;
     for (int32_t e = 0; e < h->n_env; ++e) {
         const int H = h->envs[e].H, W = h->envs[e].W;
         const int width = tile_width_for(W, max_width);
         const int th = (256 / width) * rt;  // one wave64 per tile: 256 / width lane rows of rt rows
-        for (int r0 = 0; r0 < H; r0 += th)
-            for (int c0 = 0; c0 < W; c0 += width) tiles.push_back(TileDesc{e, r0, c0, width});
+        const int nr = (H + th - 1) / th, nc = (W + width - 1) / width;
+        const int32_t first = (int32_t)tiles.size();
+        for (int i = 0; i < nr; ++i)
+            for (int j = 0; j < nc; ++j) {
+                tiles.push_back(TileDesc{e, i * th, j * width, width});
+                for (int di = -1; di <= 1; ++di)
+                    for (int dj = -1; dj <= 1; ++dj) {
+                        if (di == 0 && dj == 0) continue;
+                        const int a = i + di, b = j + dj;
+                        nbr.push_back(a >= 0 && a < nr && b >= 0 && b < nc ? first + a * nc + b : -1);
+                    }
+            }
     }
-    if (h->d_tiles) (void)hipFree(h->d_tiles);
-    h->d_tiles = nullptr;
-    if (hipMalloc(&h->d_tiles, tiles.size() * sizeof(TileDesc)) != hipSuccess)
+    for (void** p : {(void**)&h->d_tiles, (void**)&h->d_tile_nbr, (void**)&h->d_tile_burn,
+                     (void**)&h->d_tile_eq}) {
+        if (*p) (void)hipFree(*p);
+        *p = nullptr;
+    }
+    const size_t nt = tiles.size();
+    if (hipMalloc(&h->d_tiles, nt * sizeof(TileDesc)) != hipSuccess ||
+        hipMalloc(&h->d_tile_nbr, nt * 8 * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&h->d_tile_burn, nt * 2 * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&h->d_tile_eq, nt * sizeof(int32_t)) != hipSuccess)
         return fail(h, SIM_ENOMEM, "tile list allocation failed");
-    HIP_OR_FAIL(h, hipMemcpy(h->d_tiles, tiles.data(), tiles.size() * sizeof(TileDesc),
-                             hipMemcpyHostToDevice));
+    HIP_OR_FAIL(h, hipMemcpy(h->d_tiles, tiles.data(), nt * sizeof(TileDesc), hipMemcpyHostToDevice));
+    HIP_OR_FAIL(h, hipMemcpy(h->d_tile_nbr, nbr.data(), nt * 8 * sizeof(int32_t), hipMemcpyHostToDevice));
     h->n_tiles = (int32_t)tiles.size();
     h->tiles_rt = rt;
     h->tiles_tw = max_width;
@@ -172,12 +194,21 @@ hipError_t enqueue_steps(sim_handle* h, hipStream_t s, uint8_t* states, const in
         if (e != hipSuccess) return e;
     }
     const StepLaunch L = step_launch(h);
+    const bool sparse = h->plan.sparse != 0;
+    if (sparse) {  // nothing is known yet about how the two buffers compare
+        e = launch_fill_i32(s, h->d_tile_eq, h->n_tiles, 0);
+        if (e != hipSuccess) return e;
+    }
     uint8_t* cur = states;
     uint8_t* nxt = h->d_tmp;
     for (int32_t k = 0; k < T; ++k) {
+        SparseArgs sp{nullptr, nullptr, nullptr, nullptr, 0};
+        if (sparse)
+            sp = SparseArgs{h->d_tile_burn + (k & 1) * h->n_tiles, h->d_tile_burn + ((k + 1) & 1) * h->n_tiles,
+                            h->d_tile_eq, h->d_tile_nbr, k == 0 ? 1 : 0};
         e = launch_stoch_step(s, L, cur, nxt, h->d_t, (uint32_t)k,
                               actions ? actions + (int64_t)k * h->n_env : nullptr,
-                              counts ? counts + (int64_t)k * h->n_env : nullptr);
+                              counts ? counts + (int64_t)k * h->n_env : nullptr, sp);
         if (e != hipSuccess) return e;
         std::swap(cur, nxt);
     }
@@ -188,7 +219,23 @@ hipError_t enqueue_steps(sim_handle* h, hipStream_t s, uint8_t* states, const in
 bool same_plan(const sim_plan& a, const sim_plan& b)
 {
     return a.tile_rows == b.tile_rows && a.tile_width == b.tile_width && a.temporal == b.temporal &&
-           a.skip_static == b.skip_static && a.graph == b.graph;
+           a.skip_static == b.skip_static && a.sparse == b.sparse && a.graph == b.graph;
+}
+
+int validate_plan(sim_handle* h, sim_plan& p)
+{
+    if (p.tile_rows == 0) p.tile_rows = 4;
+    if (p.tile_width == 0) p.tile_width = 256;
+    if (p.temporal == 0) p.temporal = 1;
+    if (!(p.tile_rows == 1 || p.tile_rows == 2 || p.tile_rows == 4 || p.tile_rows == 8))
+        return fail(h, SIM_EINVAL, "tile_rows must be 1, 2, 4 or 8");
+    if (!(p.tile_width == 64 || p.tile_width == 128 || p.tile_width == 256))
+        return fail(h, SIM_EINVAL, "tile_width must be 64, 128 or 256");
+    if (p.temporal != 1) return fail(h, SIM_EINVAL, "temporal must be 1");
+    if (p.skip_static != 0 && p.skip_static != 1) return fail(h, SIM_EINVAL, "skip_static must be 0 or 1");
+    if (p.sparse != 0 && p.sparse != 1) return fail(h, SIM_EINVAL, "sparse must be 0 or 1");
+    if (p.graph != 0 && p.graph != 1) return fail(h, SIM_EINVAL, "graph must be 0 or 1");
+    return SIM_OK;
 }
 
 }  // namespace
@@ -382,16 +429,8 @@ int sim_set_plan(sim_handle* h, const sim_plan* plan)
 {
     if (!h || !plan) return SIM_EINVAL;
     sim_plan p = *plan;
-    if (p.tile_rows == 0) p.tile_rows = 4;
-    if (p.tile_width == 0) p.tile_width = 256;
-    if (p.temporal == 0) p.temporal = 1;
-    if (!(p.tile_rows == 1 || p.tile_rows == 2 || p.tile_rows == 4 || p.tile_rows == 8))
-        return fail(h, SIM_EINVAL, "tile_rows must be 1, 2, 4 or 8");
-    if (!(p.tile_width == 64 || p.tile_width == 128 || p.tile_width == 256))
-        return fail(h, SIM_EINVAL, "tile_width must be 64, 128 or 256");
-    if (p.temporal != 1) return fail(h, SIM_EINVAL, "temporal must be 1");
-    if (p.skip_static != 0 && p.skip_static != 1) return fail(h, SIM_EINVAL, "skip_static must be 0 or 1");
-    if (p.graph != 0 && p.graph != 1) return fail(h, SIM_EINVAL, "graph must be 0 or 1");
+    const int rc = validate_plan(h, p);
+    if (rc != SIM_OK) return rc;
     h->plan = p;
     return SIM_OK;
 }
@@ -401,6 +440,66 @@ int sim_get_plan(const sim_handle* h, sim_plan* plan)
     if (!h || !plan) return SIM_EINVAL;
     *plan = h->plan;
     return SIM_OK;
+}
+
+int sim_autotune(sim_handle* h, const uint8_t* states, int32_t T_probe, int32_t allow_skip,
+                 int32_t allow_sparse, sim_tune_result* results, int32_t max_results,
+                 int32_t* n_results, void* stream)
+{
+    if (!h) return fail(nullptr, SIM_EINVAL, "handle is NULL");
+    if (!states || T_probe < 1 || max_results < 0 || (max_results > 0 && !results))
+        return fail(h, SIM_EINVAL, "need states, T_probe >= 1 and a results array");
+    hipStream_t s = (hipStream_t)stream;
+    const sim_plan saved = h->plan;
+    uint8_t* work = nullptr;
+    if (hipMalloc(&work, (size_t)h->n_cells) != hipSuccess)
+        return fail(h, SIM_ENOMEM, "autotune scratch allocation failed");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    std::vector<sim_tune_result> tried;
+    int rc = SIM_OK;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        rc = fail(h, SIM_EHIP, "event creation failed");
+    }
+    for (int skip = 0; rc == SIM_OK && skip <= (allow_skip ? 1 : 0); ++skip)
+        for (int width : {64, 256})
+            for (int rows : {1, 2, 4, 8}) {
+                if (rc != SIM_OK) break;
+                h->plan = sim_plan{rows, width, 1, skip, allow_sparse ? 1 : 0, 0};
+                if ((rc = build_tiles(h, rows, width)) != SIM_OK) break;
+                hipError_t e = hipSuccess;
+                float best = 0.0f;
+                for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {  // first pass warms up
+                    e = launch_copy_u8(s, work, states, h->n_cells);
+                    if (e == hipSuccess) e = launch_set_u32(s, h->d_t, (uint32_t)h->t);
+                    if (e == hipSuccess) e = hipEventRecord(e0, s);
+                    if (e == hipSuccess) e = enqueue_steps(h, s, work, nullptr, T_probe, nullptr);
+                    if (e == hipSuccess) e = hipEventRecord(e1, s);
+                    if (e == hipSuccess) e = hipEventSynchronize(e1);
+                    if (e == hipSuccess) e = hipEventElapsedTime(&best, e0, e1);
+                }
+                if (e != hipSuccess) {
+                    rc = fail(h, SIM_EHIP, "autotune run failed: %s", hipGetErrorString(e));
+                    break;
+                }
+                tried.push_back(sim_tune_result{h->plan, best / (float)T_probe});
+            }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(work);
+    std::sort(tried.begin(), tried.end(),
+              [](const sim_tune_result& a, const sim_tune_result& b) { return a.ms_per_step < b.ms_per_step; });
+    h->plan = saved;
+    if (rc == SIM_OK && !tried.empty()) {
+        h->plan = tried[0].plan;
+        h->plan.graph = saved.graph;
+    }
+    h->graph.valid = false;
+    const int built = build_tiles(h, h->plan.tile_rows, h->plan.tile_width);
+    if (rc == SIM_OK) rc = built;
+    const int n = std::min<int>((int)tried.size(), max_results);
+    for (int i = 0; i < n; ++i) results[i] = tried[i];
+    if (n_results) *n_results = n;
+    return rc;
 }
 
 int sim_relaxed_init(sim_handle* h, double* U, double* B, void* stream)
@@ -417,9 +516,10 @@ size_t sim_relaxed_workspace_bytes(const sim_handle* h, int32_t T, int32_t ckpt_
     return relaxed_workspace_bytes(h->n_cells, T, ckpt_every);
 }
 
-static RelaxedInputs relaxed_inputs(const sim_handle* h)
+static RelaxedInputs relaxed_inputs(const sim_handle* h, int32_t form = 0)
 {
     RelaxedInputs in;
+    in.form = form;
     in.tiles = h->relaxed.d_tiles;
     in.n_tiles = h->relaxed.n_tiles;
     in.envs = h->d_envs;
@@ -441,18 +541,20 @@ static int check_relaxed_params(sim_handle* h, const sim_params* p)
 }
 
 int sim_step_relaxed_fwd(sim_handle* h, const sim_params* p, double* U, double* B, int32_t T,
-                         int32_t ckpt_every, void* workspace, size_t workspace_bytes, void* stream)
+                         int32_t ckpt_every, int32_t form, void* workspace, size_t workspace_bytes,
+                         void* stream)
 {
     if (!h) return fail(nullptr, SIM_EINVAL, "handle is NULL");
     int rc = check_relaxed_params(h, p);
     if (rc) return rc;
+    if (form != SIM_FORM_PRODUCT && form != SIM_FORM_EXP) return fail(h, SIM_EINVAL, "unknown form");
     if (!U || !B || T < 0 || ckpt_every < 1) return fail(h, SIM_EINVAL, "bad U/B/T/ckpt_every");
     if (T > 0 && (!workspace || workspace_bytes < relaxed_workspace_bytes(h->n_cells, T, ckpt_every)))
         return fail(h, SIM_EINVAL, "workspace too small (%zu < %zu)", workspace_bytes,
                     relaxed_workspace_bytes(h->n_cells, T, ckpt_every));
     if ((rc = relaxed_prepare(h->relaxed, h->envs)) != 0)
         return fail(h, SIM_ENOMEM, "relaxed tile list allocation failed");
-    hipError_t e = relaxed_forward((hipStream_t)stream, relaxed_inputs(h), *p, U, B, T, ckpt_every,
+    hipError_t e = relaxed_forward((hipStream_t)stream, relaxed_inputs(h, form), *p, U, B, T, ckpt_every,
                                    workspace);
     if (e != hipSuccess) return fail(h, SIM_EHIP, "relaxed forward failed: %s", hipGetErrorString(e));
     return SIM_OK;
@@ -471,19 +573,36 @@ int sim_relaxed_loss(sim_handle* h, const double* U_T, const uint8_t* target, fl
     return SIM_OK;
 }
 
+int sim_relaxed_loss_bce(sim_handle* h, const double* U_T, const uint8_t* target, int32_t pool,
+                         double mse_weight, double eps, float* loss, double* gU_T, double scale,
+                         void* stream)
+{
+    if (!h) return fail(nullptr, SIM_EINVAL, "handle is NULL");
+    if (!U_T || !target || !loss) return fail(h, SIM_EINVAL, "U_T, target and loss are required");
+    if (pool < 1 || pool > 64 || !(eps > 0.0 && eps < 0.5) || !(mse_weight >= 0.0))
+        return fail(h, SIM_EINVAL, "need 1 <= pool <= 64, 0 < eps < 0.5, mse_weight >= 0");
+    if (relaxed_prepare(h->relaxed, h->envs) != 0 || relaxed_prepare_pool(h->relaxed, h->envs, pool) != 0)
+        return fail(h, SIM_ENOMEM, "relaxed tables allocation failed");
+    hipError_t e = relaxed_loss_bce((hipStream_t)stream, relaxed_inputs(h), h->d_init_states, U_T,
+                                    target, pool, mse_weight, eps, loss, gU_T, scale, h->relaxed);
+    if (e != hipSuccess) return fail(h, SIM_EHIP, "relaxed loss failed: %s", hipGetErrorString(e));
+    return SIM_OK;
+}
+
 int sim_step_relaxed_bwd(sim_handle* h, const sim_params* p, const double* gU_T, const double* gB_T,
-                         int32_t T, int32_t ckpt_every, void* workspace, size_t workspace_bytes,
-                         double* grad, void* stream)
+                         int32_t T, int32_t ckpt_every, int32_t form, void* workspace,
+                         size_t workspace_bytes, double* grad, void* stream)
 {
     if (!h) return fail(nullptr, SIM_EINVAL, "handle is NULL");
     int rc = check_relaxed_params(h, p);
     if (rc) return rc;
+    if (form != SIM_FORM_PRODUCT && form != SIM_FORM_EXP) return fail(h, SIM_EINVAL, "unknown form");
     if (!gU_T || !grad || T < 0 || ckpt_every < 1) return fail(h, SIM_EINVAL, "bad gU_T/grad/T/ckpt_every");
     if (T > 0 && (!workspace || workspace_bytes < relaxed_workspace_bytes(h->n_cells, T, ckpt_every)))
         return fail(h, SIM_EINVAL, "workspace too small");
     if ((rc = relaxed_prepare(h->relaxed, h->envs)) != 0)
         return fail(h, SIM_ENOMEM, "relaxed tile list allocation failed");
-    hipError_t e = relaxed_backward((hipStream_t)stream, relaxed_inputs(h), *p, gU_T, gB_T, T,
+    hipError_t e = relaxed_backward((hipStream_t)stream, relaxed_inputs(h, form), *p, gU_T, gB_T, T,
                                     ckpt_every, workspace, grad, h->relaxed);
     if (e != hipSuccess) return fail(h, SIM_EHIP, "relaxed backward failed: %s", hipGetErrorString(e));
     return SIM_OK;

@@ -63,12 +63,27 @@ struct StepLaunch {
     bool skip_static;   // skip fuel/elevation loads of waves with no front
 };
 
+// Sparse scheduling of the step: a tile whose cells and neighbouring tiles
+// held no burning cell after the previous step (and that no drop touches) is
+// left as it is.  burn_prev / burn_next: burning cells per tile before and
+// after the step; eq[tile] != 0 when both state buffers hold the same content
+// on the tile; nbr: the 8 neighbouring tiles (-1 off the env).  burn_next ==
+// nullptr disables it; all_active forces every tile to run (first step of a
+// call, when nothing is known about the caller's states).
+struct SparseArgs {
+    const int32_t* burn_prev;
+    int32_t* burn_next;
+    int32_t* eq;
+    const int32_t* nbr;
+    int32_t all_active;
+};
+
 // One stochastic step t -> t+1 from src to dst, with t = *t_base + step.
 // t_base lives in device memory so that a captured sequence of launches can be
 // replayed for any starting step.
 hipError_t launch_stoch_step(hipStream_t s, const StepLaunch& L, const uint8_t* src,
                              uint8_t* dst, const uint32_t* t_base, uint32_t step,
-                             const int32_t* actions_row, int32_t* counts_row);
+                             const int32_t* actions_row, int32_t* counts_row, const SparseArgs& sp);
 hipError_t launch_set_u32(hipStream_t s, uint32_t* p, uint32_t v);
 
 hipError_t launch_debug_exp(hipStream_t s, const float* x, float* y, int64_t n);

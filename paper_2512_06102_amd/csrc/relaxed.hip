@@ -32,8 +32,9 @@
 // eventually ignites), so an fp32 state underflows and rounds its way onto a
 // different trajectory within ~100 steps on a 128 x 128 grid.  U, B, the
 // adjoint and the gradient sums are therefore fp64; the per-edge factors
-// exp(x), phi, q = -expm1(-y) and exp(-y) are fp32 from the accurate library
-// routines (small rates keep their relative accuracy).
+// exp(x), phi, q = 1 - exp(-y) and exp(-y) are fp32 from the hardware base-2
+// exponential (relative error ~1e-6 for |x| < 20), with q from its Taylor
+// series below y = 1/16 so that small rates keep their relative accuracy.
 #include <algorithm>
 #include <vector>
 
@@ -65,6 +66,18 @@ RelaxedArgs relaxed_args(const sim_params& p)
 struct Veg11 {
     float v[11];
 };
+
+// e^x by the hardware base-2 exponential.
+__device__ __forceinline__ float hexp(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896341f); }
+
+// 1 - e^{-y} for y >= 0: Taylor series through y^5 below 1/16 (relative
+// error < 2e-9 there), 1 - e^{-y} above (where it is at least 0.06).
+__device__ __forceinline__ float one_minus_exp_neg(float y)
+{
+    if (y < 0.0625f)
+        return y * (1.0f - y * (0.5f - y * ((float)(1.0 / 6.0) - y * ((float)(1.0 / 24.0) - y * (float)(1.0 / 120.0)))));
+    return 1.0f - hexp(-y);
+}
 
 constexpr int TW = kRelaxTW, TH = kRelaxTH;  // forward tile
 constexpr int BW = kRelaxBW, BH = kRelaxBH;  // adjoint tile
@@ -122,8 +135,9 @@ __device__ __forceinline__ float source_wind(int k, const float* ew, const float
         return ew[k];
 }
 
-// One relaxed forward step on a 32 x 16 tile.
-template <bool WC>
+// One relaxed forward step on a 32 x 16 tile.  FORM 0: p_ignite = 1 -
+// prod_k (1 - q_k B_k); FORM 1: p_ignite = 1 - exp(-gamma sum_k B_k phi_k).
+template <bool WC, int FORM>
 __global__ __launch_bounds__(256) void relaxed_fwd_kernel(
     const RelaxedTile* __restrict__ tiles, const EnvDev* __restrict__ envs, const float* __restrict__ g,
     const float* __restrict__ E, const float* __restrict__ wind, int64_t n_cells, RelaxedArgs A,
@@ -154,10 +168,11 @@ __global__ __launch_bounds__(256) void relaxed_fwd_kernel(
         const int64_t v = ed.offset + (int64_t)gi * W + gj;
         const int a = rr + 1, b = cc + 1;
         const double Uv = U[v], Bv = sB[a * EW + b];
-        double prod = 1.0;
+        double P = 0.0;
         if (Uv != 0.0) {
             const float gam = A.alpha_gamma * sg[a * EW + b];
             const float Ev = sE[a * EW + b];
+            double prod = 1.0, lam = 0.0;
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
                 const int s = (a - kDRow[k]) * EW + (b - kDCol[k]);
@@ -166,12 +181,15 @@ __global__ __launch_bounds__(256) void relaxed_fwd_kernel(
                 const int64_t u = v - (int64_t)kDRow[k] * W - kDCol[k];
                 const float x = source_wind<WC>(k, ew, wind, n_cells, u, A) +
                                 A.alpha_s * ((Ev - sE[s]) * ((k & 1) ? A.inv_diag : A.inv_orth));
-                const float phi = A.p_base * sg[s] * expf(x);
-                const float q = -expm1f(-(gam * phi));
-                prod = prod * (1.0 - (double)q * Bu);
+                const float phi = A.p_base * sg[s] * hexp(x);
+                if constexpr (FORM == 0)
+                    prod = prod * (1.0 - (double)one_minus_exp_neg(gam * phi) * Bu);
+                else
+                    lam = lam + (double)phi * Bu;
             }
+            P = FORM == 0 ? 1.0 - prod : -expm1(-(double)gam * lam);
         }
-        const double N = Uv * (1.0 - prod);
+        const double N = Uv * P;
         Uo[v] = Uv - N;
         Bo[v] = N + (double)A.p_continue * Bv;
     }
@@ -179,7 +197,12 @@ __global__ __launch_bounds__(256) void relaxed_fwd_kernel(
 
 // One adjoint step on a 32 x 8 tile: (U_t, B_t), (Ubar_{t+1}, Bbar_{t+1})
 // -> (Ubar_t, Bbar_t), and the step's contribution to the parameter gradient.
-template <bool WC>
+// Both forms reduce to per-edge phibar_k and per-target gammabar:
+//   FORM 0: ybar_k = Pbar B_k E_k exp(-y_k), phibar_k = ybar_k gamma,
+//           gammabar = sum_k ybar_k phi_k, c_k = Pbar q_k E_k;
+//   FORM 1: lambdabar = Pbar gamma (1 - P), phibar_k = lambdabar B_k,
+//           gammabar = Pbar lambda (1 - P), c_k = lambdabar phi_k.
+template <bool WC, int FORM>
 __global__ __launch_bounds__(256) void relaxed_bwd_kernel(
     const RelaxedTile* __restrict__ tiles, const EnvDev* __restrict__ envs, const float* __restrict__ g,
     const float* __restrict__ E, const float* __restrict__ wind, const uint8_t* __restrict__ cls,
@@ -233,8 +256,8 @@ __global__ __launch_bounds__(256) void relaxed_bwd_kernel(
         const double Pbar = nbar * Uv;
         const float gv = sg[a * XW + b], Ev = sE[a * XW + b];
         const float gam = A.alpha_gamma * gv;
-        float q[8], em[8], ex[8];
-        double Bs[8], fac[8];
+        float q[8], em[8], ex[8], ph[8];
+        double Bs[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const int s = (a - kDRow[k]) * XW + (b - kDCol[k]);
@@ -243,34 +266,56 @@ __global__ __launch_bounds__(256) void relaxed_bwd_kernel(
             q[k] = 0.0f;
             em[k] = 1.0f;
             ex[k] = 0.0f;
+            ph[k] = 0.0f;
             if (ui >= 0 && ui < H && uj >= 0 && uj < W && (Pbar != 0.0 || Bs[k] != 0.0)) {
                 const int64_t u = v - (int64_t)kDRow[k] * W - kDCol[k];
                 const float x = source_wind<WC>(k, ew, wind, n_cells, u, A) +
                                 A.alpha_s * ((Ev - sE[s]) * ((k & 1) ? A.inv_diag : A.inv_orth));
-                ex[k] = expf(x);
-                const float y = gam * (A.p_base * sg[s] * ex[k]);
-                q[k] = -expm1f(-y);
-                em[k] = expf(-y);
+                ex[k] = hexp(x);
+                ph[k] = A.p_base * sg[s] * ex[k];
+                if constexpr (FORM == 0) {
+                    const float y = gam * ph[k];
+                    q[k] = one_minus_exp_neg(y);
+                    em[k] = hexp(-y);
+                }
             }
-            fac[k] = 1.0 - (double)q[k] * Bs[k];
         }
-        double pre[9], suf[9];
-        pre[0] = 1.0;
-        suf[8] = 1.0;
+        // FORM 0: exclusive products from stored prefix and a running suffix
+        double pre[9];
+        double P, gam_bar = 0.0, lbar = 0.0;
+        if constexpr (FORM == 0) {
+            pre[0] = 1.0;
 #pragma unroll
-        for (int k = 0; k < 8; ++k) pre[k + 1] = pre[k] * fac[k];
+            for (int k = 0; k < 8; ++k) pre[k + 1] = pre[k] * (1.0 - (double)q[k] * Bs[k]);
+            P = 1.0 - pre[8];
+        } else {
+            double lam = 0.0;
 #pragma unroll
-        for (int k = 7; k >= 0; --k) suf[k] = suf[k + 1] * fac[k];
-        const double P = 1.0 - pre[8];
+            for (int k = 0; k < 8; ++k) lam = lam + (double)ph[k] * Bs[k];
+            const double surv = exp(-(double)gam * lam);
+            P = -expm1(-(double)gam * lam);
+            lbar = Pbar * (double)gam * surv;
+            gam_bar = Pbar * lam * surv;
+        }
         const bool interior = er >= 1 && er <= BH && ec >= 1 && ec <= BW;
-        double gt = 0.0;
+        double suf = 1.0;
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const double excl = pre[k] * suf[k + 1];
-            const double ybar = Pbar * Bs[k] * excl * (double)em[k];  // qbar dq/dy
-            sC[k * NE + idx] = Pbar * (double)q[k] * excl;
-            sD[k * NE + idx] = ybar * (double)gam * p_base * (double)ex[k];  // -> gbar(source)
-            if (interior && ybar != 0.0) {
+        for (int k = 7; k >= 0; --k) {
+            double c, phibar;
+            if constexpr (FORM == 0) {
+                const double excl = pre[k] * suf;
+                suf = suf * (1.0 - (double)q[k] * Bs[k]);
+                const double ybar = Pbar * Bs[k] * excl * (double)em[k];  // qbar dq/dy
+                c = Pbar * (double)q[k] * excl;
+                phibar = ybar * (double)gam;
+                gam_bar += ybar * (double)ph[k];
+            } else {
+                c = lbar * (double)ph[k];
+                phibar = lbar * Bs[k];
+            }
+            sC[k * NE + idx] = c;
+            sD[k * NE + idx] = phibar * p_base * (double)ex[k];  // -> gbar(source)
+            if (interior && phibar != 0.0) {
                 const int s = (a - kDRow[k]) * XW + (b - kDCol[k]);
                 const int64_t u = v - (int64_t)kDRow[k] * W - kDCol[k];
                 const double gu = sg[s];
@@ -285,19 +330,18 @@ __global__ __launch_bounds__(256) void relaxed_bwd_kernel(
                     Vx = ed.Vx;
                     Vy = ed.Vy;
                 }
-                const double xbar = ybar * (double)gam * phi;
-                acc[0] += ybar * (double)gam * gu * (double)ex[k];
+                const double xbar = phibar * phi;
+                acc[0] += phibar * gu * (double)ex[k];
                 acc[1] += xbar * (double)V;
                 acc[2] += xbar * (double)((kCos[k] * Vx + kSin[k] * Vy) - V);
                 acc[3] += xbar * ((double)(Ev - sE[s]) * (double)((k & 1) ? A.inv_diag : A.inv_orth));
-                acc[4] += ybar * phi * (double)gv;
-                gt += ybar * phi * a_gamma;
             }
         }
         if (interior) {
             gU0[v] = gU + nbar * P;
+            acc[4] += gam_bar * (double)gv;
             acc[5] += gB * sB[a * XW + b];
-            sgt[(er - 1) * BW + (ec - 1)] = gt;
+            sgt[(er - 1) * BW + (ec - 1)] = gam_bar * a_gamma;
         }
     }
     __syncthreads();
@@ -420,6 +464,76 @@ __global__ void loss_final_kernel(const double* __restrict__ acc, int32_t n_env,
     loss[e] = D > 0.0 ? (float)(1.0 - I / D) : 0.0f;
 }
 
+// The paper's calibration loss: BCE of the clipped soft scar plus the mean
+// squared error of pool x pool block averages.  One lane per pooled block.
+__global__ __launch_bounds__(256) void bce_pool_sums_kernel(
+    const RelaxedTile* __restrict__ blocks, int32_t n_pool, int32_t pool, const EnvDev* __restrict__ envs,
+    const uint8_t* __restrict__ init_states, const double* __restrict__ U_T,
+    const uint8_t* __restrict__ target, double eps, double* __restrict__ vals, double* __restrict__ acc,
+    int32_t n_env)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n_pool) return;
+    const RelaxedTile pb = blocks[b];
+    const EnvDev ed = envs[pb.env];
+    const int i1 = min(pb.r0 + pool, ed.H), j1 = min(pb.c0 + pool, ed.W);
+    double sS = 0.0, sY = 0.0, bce = 0.0;
+    for (int i = pb.r0; i < i1; ++i)
+        for (int j = pb.c0; j < j1; ++j) {
+            const int64_t v = ed.offset + (int64_t)i * ed.W + j;
+            const double S = init_states[v] != kUnburnable ? 1.0 - U_T[v] : 0.0;
+            const double Y = target[v] ? 1.0 : 0.0;
+            const double Sc = fmin(fmax(S, eps), 1.0 - eps);
+            bce -= Y * log(Sc) + (1.0 - Y) * log(1.0 - Sc);
+            sS += S;
+            sY += Y;
+        }
+    const double cnt = (double)(i1 - pb.r0) * (double)(j1 - pb.c0);
+    const double pS = sS / cnt, pY = sY / cnt;
+    vals[b] = pS;
+    vals[n_pool + b] = pY;
+    unsafeAtomicAdd(acc + pb.env, bce);
+    unsafeAtomicAdd(acc + n_env + pb.env, (pS - pY) * (pS - pY));
+}
+
+__global__ __launch_bounds__(256) void bce_pool_grad_kernel(
+    const RelaxedTile* __restrict__ blocks, int32_t n_pool, int32_t pool, const EnvDev* __restrict__ envs,
+    const int32_t* __restrict__ env_blocks, const uint8_t* __restrict__ init_states,
+    const double* __restrict__ U_T, const uint8_t* __restrict__ target, double eps, double mse_weight,
+    const double* __restrict__ vals, double scale, double* __restrict__ gU_T)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n_pool) return;
+    const RelaxedTile pb = blocks[b];
+    const EnvDev ed = envs[pb.env];
+    const int i1 = min(pb.r0 + pool, ed.H), j1 = min(pb.c0 + pool, ed.W);
+    const double n_e = (double)ed.H * (double)ed.W, m_e = (double)env_blocks[pb.env];
+    const double cnt = (double)(i1 - pb.r0) * (double)(j1 - pb.c0);
+    const double dmse = 2.0 * (vals[b] - vals[n_pool + b]) / m_e / cnt;  // d mse / d S of each cell
+    for (int i = pb.r0; i < i1; ++i)
+        for (int j = pb.c0; j < j1; ++j) {
+            const int64_t v = ed.offset + (int64_t)i * ed.W + j;
+            double gv = 0.0;
+            if (init_states[v] != kUnburnable) {
+                const double S = 1.0 - U_T[v];
+                const double Y = target[v] ? 1.0 : 0.0;
+                const double dbce = (S > eps && S < 1.0 - eps) ? (-(Y / S) + (1.0 - Y) / (1.0 - S)) / n_e : 0.0;
+                gv = -scale * (dbce + mse_weight * dmse);  // dL/dU = -dL/dS
+            }
+            gU_T[v] = gv;
+        }
+}
+
+__global__ void bce_pool_final_kernel(const double* __restrict__ acc, const EnvDev* __restrict__ envs,
+                                      const int32_t* __restrict__ env_blocks, int32_t n_env,
+                                      double mse_weight, float* __restrict__ loss)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n_env) return;
+    const double n_e = (double)envs[e].H * (double)envs[e].W;
+    loss[e] = (float)(acc[e] / n_e + mse_weight * acc[n_env + e] / (double)env_blocks[e]);
+}
+
 int blocks_for(int64_t n)
 {
     int64_t b = (n + 255) / 256;
@@ -476,16 +590,32 @@ hipError_t fuel(hipStream_t s, const RelaxedInputs& in, const sim_params& p, flo
     return hipGetLastError();
 }
 
+template <bool WC, int FORM>
+void launch_fwd(hipStream_t s, const RelaxedInputs& in, const RelaxedArgs& A, const float* g,
+                const double* U, const double* B, double* Uo, double* Bo)
+{
+    hipLaunchKernelGGL((relaxed_fwd_kernel<WC, FORM>), dim3(in.n_tiles), dim3(256), 0, s, in.tiles,
+                       in.envs, g, in.E, in.wind, in.n_cells, A, U, B, Uo, Bo);
+}
+
 hipError_t fwd_step(hipStream_t s, const RelaxedInputs& in, const RelaxedArgs& A, const float* g,
                     const double* U, const double* B, double* Uo, double* Bo)
 {
     if (in.wind)
-        hipLaunchKernelGGL(relaxed_fwd_kernel<true>, dim3(in.n_tiles), dim3(256), 0, s, in.tiles,
-                           in.envs, g, in.E, in.wind, in.n_cells, A, U, B, Uo, Bo);
+        in.form ? launch_fwd<true, 1>(s, in, A, g, U, B, Uo, Bo) : launch_fwd<true, 0>(s, in, A, g, U, B, Uo, Bo);
     else
-        hipLaunchKernelGGL(relaxed_fwd_kernel<false>, dim3(in.n_tiles), dim3(256), 0, s, in.tiles,
-                           in.envs, g, in.E, in.wind, in.n_cells, A, U, B, Uo, Bo);
+        in.form ? launch_fwd<false, 1>(s, in, A, g, U, B, Uo, Bo) : launch_fwd<false, 0>(s, in, A, g, U, B, Uo, Bo);
     return hipGetLastError();
+}
+
+template <bool WC, int FORM>
+void launch_bwd(hipStream_t s, const RelaxedInputs& in, const RelaxedState& R, const RelaxedArgs& A,
+                const float* g, const double* U, const double* B, const double* gU1, const double* gB1,
+                double* gU0, double* gB0, double* stripes)
+{
+    hipLaunchKernelGGL((relaxed_bwd_kernel<WC, FORM>), dim3(R.n_btiles), dim3(256), 0, s, R.d_btiles,
+                       in.envs, g, in.E, in.wind, in.cls, in.den, in.n_cells, A, U, B, gU1, gB1, gU0,
+                       gB0, stripes);
 }
 
 }  // namespace
@@ -515,11 +645,42 @@ int relaxed_prepare(RelaxedState& R, const std::vector<sim_env>& envs)
     return 0;
 }
 
+int relaxed_prepare_pool(RelaxedState& R, const std::vector<sim_env>& envs, int pool)
+{
+    if (R.d_pool && R.pool_k == pool) return 0;
+    for (void** p : {(void**)&R.d_pool, (void**)&R.d_env_blocks, (void**)&R.d_pool_vals,
+                     (void**)&R.d_bce_acc}) {
+        if (*p) (void)hipFree(*p);
+        *p = nullptr;
+    }
+    std::vector<RelaxedTile> blocks;
+    std::vector<int32_t> per_env;
+    for (int32_t e = 0; e < (int32_t)envs.size(); ++e) {
+        const size_t before = blocks.size();
+        for (int r0 = 0; r0 < envs[e].H; r0 += pool)
+            for (int c0 = 0; c0 < envs[e].W; c0 += pool) blocks.push_back(RelaxedTile{e, r0, c0, 0});
+        per_env.push_back((int32_t)(blocks.size() - before));
+    }
+    R.n_pool = (int32_t)blocks.size();
+    if (hipMalloc(&R.d_pool, blocks.size() * sizeof(RelaxedTile)) != hipSuccess ||
+        hipMalloc(&R.d_env_blocks, per_env.size() * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&R.d_pool_vals, 2 * blocks.size() * sizeof(double)) != hipSuccess ||
+        hipMalloc(&R.d_bce_acc, 2 * per_env.size() * sizeof(double)) != hipSuccess)
+        return -1;
+    if (hipMemcpy(R.d_pool, blocks.data(), blocks.size() * sizeof(RelaxedTile), hipMemcpyHostToDevice) !=
+            hipSuccess ||
+        hipMemcpy(R.d_env_blocks, per_env.data(), per_env.size() * sizeof(int32_t),
+                  hipMemcpyHostToDevice) != hipSuccess)
+        return -1;
+    R.pool_k = pool;
+    return 0;
+}
+
 void relaxed_free(RelaxedState& R)
 {
-    if (R.d_tiles) (void)hipFree(R.d_tiles);
-    if (R.d_btiles) (void)hipFree(R.d_btiles);
-    if (R.d_loss_acc) (void)hipFree(R.d_loss_acc);
+    for (void* p : {(void*)R.d_tiles, (void*)R.d_btiles, (void*)R.d_loss_acc, (void*)R.d_pool,
+                    (void*)R.d_env_blocks, (void*)R.d_pool_vals, (void*)R.d_bce_acc})
+        if (p) (void)hipFree(p);
     R = RelaxedState{};
 }
 
@@ -587,6 +748,28 @@ hipError_t relaxed_loss(hipStream_t s, const RelaxedInputs& in, const uint8_t* i
     return e;
 }
 
+hipError_t relaxed_loss_bce(hipStream_t s, const RelaxedInputs& in, const uint8_t* init_states,
+                            const double* U_T, const uint8_t* target, int pool, double mse_weight,
+                            double eps, float* loss, double* gU_T, double scale, RelaxedState& R)
+{
+    hipError_t e = fill_f64(s, R.d_bce_acc, (int64_t)2 * in.n_env, 0.0);
+    if (e != hipSuccess) return e;
+    const int nb = (R.n_pool + 255) / 256;
+    hipLaunchKernelGGL(bce_pool_sums_kernel, dim3(nb), dim3(256), 0, s, R.d_pool, R.n_pool, pool, in.envs,
+                       init_states, U_T, target, eps, R.d_pool_vals, R.d_bce_acc, in.n_env);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(bce_pool_final_kernel, dim3((in.n_env + 255) / 256), dim3(256), 0, s, R.d_bce_acc,
+                       in.envs, R.d_env_blocks, in.n_env, mse_weight, loss);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (gU_T) {
+        hipLaunchKernelGGL(bce_pool_grad_kernel, dim3(nb), dim3(256), 0, s, R.d_pool, R.n_pool, pool, in.envs,
+                           R.d_env_blocks, init_states, U_T, target, eps, mse_weight, R.d_pool_vals, scale,
+                           gU_T);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
 hipError_t relaxed_backward(hipStream_t s, const RelaxedInputs& in, const sim_params& p,
                             const double* gU_T, const double* gB_T, int32_t T, int32_t k,
                             void* workspace, double* grad, RelaxedState& R)
@@ -622,14 +805,13 @@ hipError_t relaxed_backward(hipStream_t s, const RelaxedInputs& in, const sim_pa
                          seg + (size_t)j * 2 * n + n);
         for (int32_t t = t1 - 1; t >= t0 && e == hipSuccess; --t) {
             const int32_t j = t - t0;
+            const double *Ut = state_u(j), *Bt = state_b(j);
             if (in.wind)
-                hipLaunchKernelGGL(relaxed_bwd_kernel<true>, dim3(R.n_btiles), dim3(256), 0, s, R.d_btiles,
-                                   in.envs, g, in.E, in.wind, in.cls, in.den, in.n_cells, A, state_u(j),
-                                   state_b(j), cu, cb, nu, nb, stripes);
+                in.form ? launch_bwd<true, 1>(s, in, R, A, g, Ut, Bt, cu, cb, nu, nb, stripes)
+                        : launch_bwd<true, 0>(s, in, R, A, g, Ut, Bt, cu, cb, nu, nb, stripes);
             else
-                hipLaunchKernelGGL(relaxed_bwd_kernel<false>, dim3(R.n_btiles), dim3(256), 0, s, R.d_btiles,
-                                   in.envs, g, in.E, in.wind, in.cls, in.den, in.n_cells, A, state_u(j),
-                                   state_b(j), cu, cb, nu, nb, stripes);
+                in.form ? launch_bwd<false, 1>(s, in, R, A, g, Ut, Bt, cu, cb, nu, nb, stripes)
+                        : launch_bwd<false, 0>(s, in, R, A, g, Ut, Bt, cu, cb, nu, nb, stripes);
             e = hipGetLastError();
             std::swap(cu, nu);
             std::swap(cb, nb);

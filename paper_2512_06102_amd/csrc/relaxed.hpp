@@ -28,6 +28,12 @@ struct RelaxedState {
     int32_t n_btiles = 0;
     double* d_loss_acc = nullptr;  // [3][n_env]: sum S Y, sum S, sum Y
     int32_t n_env = 0;
+    // pooled blocks of the BCE + pooled-MSE loss (built for one pool size)
+    RelaxedTile* d_pool = nullptr;  // env, r0, c0 of each pool x pool block
+    int32_t n_pool = 0, pool_k = 0;
+    int32_t* d_env_blocks = nullptr;  // blocks per env
+    double* d_pool_vals = nullptr;    // [2][n_pool]: block means of S and Y
+    double* d_bce_acc = nullptr;      // [2][n_env]: BCE sum, squared-error sum
 };
 
 struct RelaxedInputs {
@@ -40,9 +46,11 @@ struct RelaxedInputs {
     const float* E;
     const float* wind;  // [3][n_cells] or nullptr
     int64_t n_cells;
+    int32_t form;       // 0: product form of p_ignite, 1: 1 - exp(-gamma sum B phi)
 };
 
 int relaxed_prepare(RelaxedState& R, const std::vector<sim_env>& envs);
+int relaxed_prepare_pool(RelaxedState& R, const std::vector<sim_env>& envs, int pool);
 void relaxed_free(RelaxedState& R);
 size_t relaxed_workspace_bytes(int64_t n_cells, int32_t T, int32_t ckpt_every);
 
@@ -53,6 +61,9 @@ hipError_t relaxed_forward(hipStream_t s, const RelaxedInputs& in, const sim_par
 hipError_t relaxed_loss(hipStream_t s, const RelaxedInputs& in, const uint8_t* init_states,
                         const double* U_T, const uint8_t* target, float* loss, double* gU_T,
                         double scale, RelaxedState& R);
+hipError_t relaxed_loss_bce(hipStream_t s, const RelaxedInputs& in, const uint8_t* init_states,
+                            const double* U_T, const uint8_t* target, int pool, double mse_weight,
+                            double eps, float* loss, double* gU_T, double scale, RelaxedState& R);
 hipError_t relaxed_backward(hipStream_t s, const RelaxedInputs& in, const sim_params& p,
                             const double* gU_T, const double* gB_T, int32_t T, int32_t ckpt_every,
                             void* workspace, double* grad, RelaxedState& R);

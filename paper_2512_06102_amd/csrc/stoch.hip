@@ -195,7 +195,7 @@ __global__ __launch_bounds__(kWave) void stoch_step_kernel(
     const TileDesc* __restrict__ tiles, int32_t n_tiles, int32_t tiles_per_xcd,
     const EnvDev* __restrict__ envs, StaticFields F, StepArgs A, const uint8_t* __restrict__ src,
     uint8_t* __restrict__ dst, const uint32_t* __restrict__ t_base, uint32_t step,
-    const int32_t* __restrict__ actions_row, int32_t* __restrict__ counts_row)
+    const int32_t* __restrict__ actions_row, int32_t* __restrict__ counts_row, SparseArgs SP)
 {
     __shared__ uint32_t lds_cell[kCellCap];   // lane | m << 6 | c << 9 | nbk << 11 | group << 19
     __shared__ uint16_t lds_group[kGroupCap]; // lane | m << 6
@@ -219,6 +219,45 @@ __global__ __launch_bounds__(kWave) void stoch_step_kernel(
     const int64_t base = ed.offset;
     const uint8_t* env_src = src + base;
     const uint2 key = make_uint2(A.key0, A.key1);
+
+    // -- 0. sparse scheduling: an inactive tile keeps its cells
+    if (SP.burn_next) {
+        const int TH = (kWave >> gx_log) * RT;
+        bool active = SP.all_active != 0 || SP.burn_prev[tile] > 0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int nb = SP.nbr[8 * tile + i];
+            active = active || (nb >= 0 && SP.burn_prev[nb] > 0);
+        }
+        const int32_t a0 = actions_row ? actions_row[td.env] : -1;
+        if (!active && a0 >= 0) {
+            const int ar = (a0 >> 16) & 0x7FFF, ac = a0 & 0xFFFF;
+            active = ar < H && ac < W && ar + 2 >= td.r0 - 1 && ar - 2 <= td.r0 + TH &&
+                     ac + 2 >= td.c0 - 1 && ac - 2 <= td.c0 + td.width;
+        }
+        if (!active) {
+            if (SP.eq[tile] == 0) {  // the other buffer is stale on this tile: copy it over
+#pragma unroll
+                for (int m = 0; m < RT; ++m) {
+                    const int gi = row0 + m;
+                    if (!(gi < H && gj0 < W)) continue;
+                    const int64_t c0 = base + (int64_t)gi * W + gj0;
+                    if constexpr (ALIGNED) {
+                        *reinterpret_cast<uint32_t*>(dst + c0) = *reinterpret_cast<const uint32_t*>(src + c0);
+                    } else {
+#pragma unroll
+                        for (int c = 0; c < 4; ++c)
+                            if (gj0 + c < W) dst[c0 + c] = src[c0 + c];
+                    }
+                }
+            }
+            if (lane == 0) {
+                SP.eq[tile] = 1;
+                SP.burn_next[tile] = 0;
+            }
+            return;
+        }
+    }
 
     // -- 1. loads: RT own dwords plus the one above and below; halo bytes at
     //       the segment ends; fuel and elevation of own cells (dense plan)
@@ -434,11 +473,17 @@ __global__ __launch_bounds__(kWave) void stoch_step_kernel(
         cnt += __popc(pack4(burning_flags(out)));
     }
 
-    // -- BURNING count of the env after the step --
-    if (counts_row) {
+    // -- BURNING count of the env (and of the tile) after the step --
+    if (counts_row || SP.burn_next) {
 #pragma unroll
         for (int o2 = 32; o2 > 0; o2 >>= 1) cnt += __shfl_xor(cnt, o2);
-        if (lane == 0 && cnt) atomicAdd(counts_row + td.env, cnt);
+        if (lane == 0) {
+            if (counts_row && cnt) atomicAdd(counts_row + td.env, cnt);
+            if (SP.burn_next) {
+                SP.burn_next[tile] = cnt;
+                SP.eq[tile] = 0;
+            }
+        }
     }
 }
 
@@ -534,24 +579,26 @@ int grid_for(int64_t n, int block)
 
 template <bool AL, bool WC, int RT, bool SK>
 hipError_t launch_variant(hipStream_t s, const StepLaunch& L, const uint8_t* src, uint8_t* dst,
-                          const uint32_t* t_base, uint32_t step, const int32_t* act, int32_t* cnt)
+                          const uint32_t* t_base, uint32_t step, const int32_t* act, int32_t* cnt,
+                          const SparseArgs& sp)
 {
     const int32_t per_xcd = (L.n_tiles + 7) / 8;
     hipLaunchKernelGGL((stoch_step_kernel<AL, WC, RT, SK>), dim3(8 * per_xcd), dim3(kWave), 0, s,
                        L.tiles, L.n_tiles, per_xcd, L.envs, L.fields, L.args, src, dst, t_base,
-                       step, act, cnt);
+                       step, act, cnt, sp);
     return hipGetLastError();
 }
 
 template <bool AL, bool WC, bool SK>
 hipError_t launch_rt(hipStream_t s, const StepLaunch& L, const uint8_t* src, uint8_t* dst,
-                     const uint32_t* t_base, uint32_t step, const int32_t* act, int32_t* cnt)
+                     const uint32_t* t_base, uint32_t step, const int32_t* act, int32_t* cnt,
+                     const SparseArgs& sp)
 {
     switch (L.rows_per_thread) {
-    case 1: return launch_variant<AL, WC, 1, SK>(s, L, src, dst, t_base, step, act, cnt);
-    case 2: return launch_variant<AL, WC, 2, SK>(s, L, src, dst, t_base, step, act, cnt);
-    case 8: return launch_variant<AL, WC, 8, SK>(s, L, src, dst, t_base, step, act, cnt);
-    default: return launch_variant<AL, WC, 4, SK>(s, L, src, dst, t_base, step, act, cnt);
+    case 1: return launch_variant<AL, WC, 1, SK>(s, L, src, dst, t_base, step, act, cnt, sp);
+    case 2: return launch_variant<AL, WC, 2, SK>(s, L, src, dst, t_base, step, act, cnt, sp);
+    case 8: return launch_variant<AL, WC, 8, SK>(s, L, src, dst, t_base, step, act, cnt, sp);
+    default: return launch_variant<AL, WC, 4, SK>(s, L, src, dst, t_base, step, act, cnt, sp);
     }
 }
 
@@ -559,25 +606,25 @@ hipError_t launch_rt(hipStream_t s, const StepLaunch& L, const uint8_t* src, uin
 
 hipError_t launch_stoch_step(hipStream_t s, const StepLaunch& L, const uint8_t* src, uint8_t* dst,
                              const uint32_t* t_base, uint32_t step, const int32_t* actions_row,
-                             int32_t* counts_row)
+                             int32_t* counts_row, const SparseArgs& sp)
 {
     const bool wc = L.fields.wind != nullptr;
     if (L.aligned) {
         if (wc)
             return L.skip_static
-                       ? launch_rt<true, true, true>(s, L, src, dst, t_base, step, actions_row, counts_row)
-                       : launch_rt<true, true, false>(s, L, src, dst, t_base, step, actions_row, counts_row);
+                       ? launch_rt<true, true, true>(s, L, src, dst, t_base, step, actions_row, counts_row, sp)
+                       : launch_rt<true, true, false>(s, L, src, dst, t_base, step, actions_row, counts_row, sp);
         return L.skip_static
-                   ? launch_rt<true, false, true>(s, L, src, dst, t_base, step, actions_row, counts_row)
-                   : launch_rt<true, false, false>(s, L, src, dst, t_base, step, actions_row, counts_row);
+                   ? launch_rt<true, false, true>(s, L, src, dst, t_base, step, actions_row, counts_row, sp)
+                   : launch_rt<true, false, false>(s, L, src, dst, t_base, step, actions_row, counts_row, sp);
     }
     if (wc)
         return L.skip_static
-                   ? launch_rt<false, true, true>(s, L, src, dst, t_base, step, actions_row, counts_row)
-                   : launch_rt<false, true, false>(s, L, src, dst, t_base, step, actions_row, counts_row);
+                   ? launch_rt<false, true, true>(s, L, src, dst, t_base, step, actions_row, counts_row, sp)
+                   : launch_rt<false, true, false>(s, L, src, dst, t_base, step, actions_row, counts_row, sp);
     return L.skip_static
-               ? launch_rt<false, false, true>(s, L, src, dst, t_base, step, actions_row, counts_row)
-               : launch_rt<false, false, false>(s, L, src, dst, t_base, step, actions_row, counts_row);
+               ? launch_rt<false, false, true>(s, L, src, dst, t_base, step, actions_row, counts_row, sp)
+               : launch_rt<false, false, false>(s, L, src, dst, t_base, step, actions_row, counts_row, sp);
 }
 
 hipError_t launch_init_cells(hipStream_t s, int64_t n, const uint8_t* cls, const float* den,

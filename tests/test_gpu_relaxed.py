@@ -40,15 +40,16 @@ def _theta32(params):
     return relaxed64.theta_from_params(params).astype(np.float32).astype(np.float64)
 
 
-def _gpu_loss_grad(batch, params, Y, T, k):
+def _gpu_loss_grad(batch, params, Y, T, k, form="product", loss_kind="iou", **loss_kw):
     sim = fs.FireSim.from_batch(batch, params, seed=0)
     p = fs.make_params(params)
     p.unburnable_mask = batch.unburnable_mask
     U, B = sim.relaxed_init()
     ws = sim.relaxed_workspace(T, k)
-    sim.relaxed_fwd(p, U, B, T, k, ws)
-    loss, gU = sim.relaxed_loss(U, torch.from_numpy(Y).cuda(), scale=1.0 / batch.n_env)
-    grad = sim.relaxed_bwd(p, gU, None, T, k, ws)
+    sim.relaxed_fwd(p, U, B, T, k, ws, form)
+    loss, gU = sim.relaxed_loss_any(loss_kind, U, torch.from_numpy(Y).cuda(), scale=1.0 / batch.n_env,
+                                    **loss_kw)
+    grad = sim.relaxed_bwd(p, gU, None, T, k, ws, form)
     torch.cuda.synchronize()
     return U.cpu().numpy(), B.cpu().numpy(), loss.cpu().numpy(), grad.cpu().numpy()
 
@@ -64,9 +65,10 @@ def _check_grad(g, g64):
         assert g[6 + c] == 0.0
 
 
-def _oracle(batch, params, Y, T):
+def _oracle(batch, params, Y, T, form="product", loss_kind="iou", **loss_kw):
     Ys = [batch.env_view(Y, e).astype(bool) for e in range(batch.n_env)]
-    return relaxed64.loss_and_grad(batch, _theta32(params), T, Ys, cell_size=params.cell_size)
+    return relaxed64.loss_and_grad(batch, _theta32(params), T, Ys, cell_size=params.cell_size,
+                                   form=form, loss=loss_kind, **loss_kw)
 
 
 def test_relaxed_init_matches_fire_state():
@@ -92,6 +94,68 @@ def test_forward_loss_and_gradient_small(per_cell_wind):
         assert np.max(np.abs(batch.env_view(B, e) - finals[e][1])) <= 1e-5
     assert abs(float(loss.mean()) - L64) <= 1e-5
     _check_grad(grad, g64)
+
+
+@pytest.mark.parametrize("form,loss_kind,loss_kw", [
+    ("exp", "iou", {}),
+    ("product", "bce", {"pool": 8}),
+    ("exp", "bce", {"pool": 5, "mse_weight": 2.5}),
+    ("product", "bce", {"pool": 1, "mse_weight": 0.0, "eps": 1e-4}),
+])
+def test_forms_and_losses(form, loss_kind, loss_kw):
+    """The paper's exponential-rate form and its BCE + pooled-MSE loss (ragged
+    pool blocks at the env edges) against the fp64 oracle."""
+    batch = firegen.landscape_batch(11, [(40, 56), (33, 17), (64, 64)], per_cell_wind=True,
+                                    elev_max=80.0)
+    params = _params(5)
+    T, k = 20, 6
+    Y = _target(batch, params, T, 9)
+    U, B, loss, grad = _gpu_loss_grad(batch, params, Y, T, k, form, loss_kind, **loss_kw)
+    L64, g64, finals = _oracle(batch, params, Y, T, form, loss_kind, **loss_kw)
+    for e in range(batch.n_env):
+        assert np.max(np.abs(batch.env_view(U, e) - finals[e][0])) <= 1e-5
+        assert np.max(np.abs(batch.env_view(B, e) - finals[e][1])) <= 1e-5
+    assert abs(float(loss.astype(np.float64).mean()) - L64) <= 1e-5 * max(1.0, abs(L64))
+    _check_grad(grad, g64)
+
+
+def test_bad_form_and_pool_rejected():
+    batch = firegen.landscape_batch(2, [(16, 16)])
+    sim = fs.FireSim.from_batch(batch, _params())
+    p = fs.make_params(_params())
+    U, B = sim.relaxed_init()
+    ws = sim.relaxed_workspace(4, 2)
+    with pytest.raises(ValueError):
+        sim.relaxed_fwd(p, U, B, 4, 2, ws, "linear")
+    rc = fs.lib().sim_step_relaxed_fwd(sim.handle, fs.ctypes.byref(p), fs._ptr(U), fs._ptr(B), 4, 2, 7,
+                                       fs._ptr(ws), ws.numel(), sim._s())
+    assert rc != 0
+    Y = torch.zeros(batch.n_cells, dtype=torch.uint8, device="cuda")
+    for pool in (0, -3):
+        with pytest.raises(RuntimeError):
+            sim.relaxed_loss_bce(U, Y, pool=pool)
+    with pytest.raises(RuntimeError):
+        sim.relaxed_loss_bce(U, Y, eps=0.6)
+    torch.cuda.synchronize()
+
+
+def test_calibration_reduces_loss():
+    """Adam through the library's adjoint: from perturbed parameters the
+    relaxed loss against a stochastic scar at the true ones falls."""
+    batch = firegen.landscape_batch(13, [(64, 64)] * 4, elev_max=120.0)
+    truth = _params(6)
+    T = 30
+    Y = torch.from_numpy(_target(batch, truth, T, 10)).cuda()
+    start = truth.replace(p_base=truth.p_base * 0.5, alpha_s=truth.alpha_s * 0.5)
+    sim = fs.FireSim.from_batch(batch, start, seed=0)
+    theta0 = relaxed64.theta_from_params(start)
+    for form, loss_kind, kw in (("product", "iou", None), ("exp", "bce", {"pool": 8})):
+        theta, losses = fs.calibrate(sim, Y, T, theta0, steps=12, lr=0.03, ckpt_every=6, form=form,
+                                     loss=loss_kind, loss_kw=kw, fixed=range(6, 17))
+        assert min(losses[-3:]) < 0.85 * losses[0], (form, loss_kind, losses)
+        assert np.all(theta[6:].numpy() == theta0[6:])
+        assert theta[0] > start.p_base
+        assert 0.0 <= float(theta[5]) <= 1.0
 
 
 @pytest.mark.parametrize("k", [1, 3, 7, 30])

@@ -275,3 +275,42 @@ def test_large_grids_per_cell_wind_sampled():
         sim.step(150)
         torch.cuda.synchronize()
         assert np.array_equal(sim.states.cpu().numpy(), ref.states), skip
+
+
+def test_autotune_keeps_state_and_results():
+    """The autotuner leaves states and step counter alone, adopts its fastest
+    plan, and the run continues bit-exact."""
+    batch = firegen.landscape_batch(91, [(256, 256)] * 6 + [(128, 200)])
+    params = firegen.Params(p_base=0.8, veg=_veg(10))
+    sim = fs.FireSim.from_batch(batch, params, seed=21)
+    sim.step(7)
+    before = sim.states.clone()
+    res = sim.autotune(T_probe=4)
+    torch.cuda.synchronize()
+    assert torch.equal(sim.states, before) and sim.t == 7
+    assert len(res) == 16 and all(res[i][1] <= res[i + 1][1] for i in range(15))
+    best = res[0][0]
+    plan = sim.plan()
+    assert (plan["tile_rows"], plan["tile_width"], plan["skip_static"]) == \
+        (best["tile_rows"], best["tile_width"], best["skip_static"])
+    sim.step(13)
+    ref = oracle.Sim(batch, params, seed=21)
+    ref.step(20, threads=8)
+    torch.cuda.synchronize()
+    assert np.array_equal(sim.states.cpu().numpy(), ref.states)
+
+
+@pytest.mark.parametrize("skip_static", [0, 1])
+@pytest.mark.parametrize("tile_width,tile_rows", [(64, 1), (64, 4), (256, 2), (256, 8)])
+def test_sparse_plan_with_drops_graph_and_splits(skip_static, tile_width, tile_rows):
+    """Sparse scheduling (tiles without fire nearby are not computed) gives
+    the same bits across drops, graph replay and split calls."""
+    batch = firegen.landscape_batch(33, [(256, 256), (512, 128), (64, 64), (96, 200), (37, 300)])
+    params = firegen.Params(p_base=0.7, veg=_veg(11))
+    acts = firegen.random_actions(17, batch, 60, p_none=0.7)
+    sim, ref, got, want = _run_both(batch, params, 60, seed=19, actions=acts,
+                                    plan={"tile_rows": tile_rows, "tile_width": tile_width,
+                                          "skip_static": skip_static, "sparse": 1, "graph": 1},
+                                    split=[7, 20, 20, 13])
+    assert np.array_equal(sim.states.cpu().numpy(), ref.states)
+    assert np.array_equal(got, want)

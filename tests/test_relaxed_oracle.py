@@ -44,21 +44,24 @@ def _target(batch, T, seed):
 
 
 @pytest.mark.parametrize("per_cell_wind", [False, True])
-def test_adjoint_matches_central_differences(per_cell_wind):
+@pytest.mark.parametrize("form", ["product", "exp"])
+@pytest.mark.parametrize("loss", ["iou", "bce"])
+def test_adjoint_matches_central_differences(per_cell_wind, form, loss):
     b = _small_batch(3, ((16, 16), (12, 20)), per_cell_wind)
     prm = _params(1)
     T = 12
     Y = _target(b, T, 2)
     theta = relaxed64.theta_from_params(prm)
-    L, grad, _ = relaxed64.loss_and_grad(b, theta, T, Y)
-    assert 0 < L < 1
+    kw = dict(form=form, loss=loss, **({"pool": 4} if loss == "bce" else {}))
+    L, grad, _ = relaxed64.loss_and_grad(b, theta, T, Y, **kw)
+    assert 0 < L < (1 if loss == "iou" else 20)
     fd = np.zeros_like(grad)
     for i in range(theta.size):
         h = 1e-6 * max(1.0, abs(theta[i]))
         tp, tm = theta.copy(), theta.copy()
         tp[i] += h
         tm[i] -= h
-        fd[i] = (relaxed64.loss_only(b, tp, T, Y) - relaxed64.loss_only(b, tm, T, Y)) / (2 * h)
+        fd[i] = (relaxed64.loss_only(b, tp, T, Y, **kw) - relaxed64.loss_only(b, tm, T, Y, **kw)) / (2 * h)
     scale = np.max(np.abs(fd))
     assert scale > 0
     for i in range(theta.size):
@@ -68,7 +71,7 @@ def test_adjoint_matches_central_differences(per_cell_wind):
         assert grad[6 + c] == 0.0
 
 
-def _torch_forward_loss(env, theta_t, U0, B0, T, Y, burnable):
+def _torch_forward_loss(env, theta_t, U0, B0, T, Y, burnable, form="product", loss="iou"):
     """The relaxed forward in torch (fp64), to differentiate with autograd."""
     p_base, a_w1, a_w2, a_s, a_g, p_c = (theta_t[i] for i in range(6))
     veg = theta_t[6:17]
@@ -77,7 +80,7 @@ def _torch_forward_loss(env, theta_t, U0, B0, T, Y, burnable):
     g = (1 + veg[cls]) * (1 + den)
     gamma = a_g * g
     H, W = env.cls.shape
-    q = []
+    q, phis = [], []
     for k, (di, dj) in enumerate(relaxed64.DIRS):
         pad = torch.nn.functional.pad
 
@@ -94,33 +97,51 @@ def _torch_forward_loss(env, theta_t, U0, B0, T, Y, burnable):
         phi = p_base * src(g) * torch.exp(a_w1 * V + a_w2 * ((ca * Vx + sa * Vy) - V) + a_s * S)
         valid = torch.from_numpy(env.valid[k])
         q.append(torch.where(valid, -torch.expm1(-gamma * phi), torch.zeros_like(phi)))
+        phis.append(torch.where(valid, phi, torch.zeros_like(phi)))
     U = torch.from_numpy(U0)
     B = torch.from_numpy(B0)
     for _ in range(T):
-        prod = torch.ones_like(U)
         Bp = torch.nn.functional.pad(B[None, None], (1, 1, 1, 1))[0, 0]
-        for k, (di, dj) in enumerate(relaxed64.DIRS):
-            prod = prod * (1 - q[k] * Bp[1 - di:1 - di + H, 1 - dj:1 - dj + W])
-        newly = U * (1 - prod)
+        if form == "product":
+            prod = torch.ones_like(U)
+            for k, (di, dj) in enumerate(relaxed64.DIRS):
+                prod = prod * (1 - q[k] * Bp[1 - di:1 - di + H, 1 - dj:1 - dj + W])
+            P = 1 - prod
+        else:
+            lam = torch.zeros_like(U)
+            for k, (di, dj) in enumerate(relaxed64.DIRS):
+                lam = lam + phis[k] * Bp[1 - di:1 - di + H, 1 - dj:1 - dj + W]
+            P = -torch.expm1(-gamma * lam)
+        newly = U * P
         U, B = U - newly, newly + p_c * B
     Sg = torch.where(torch.from_numpy(burnable), 1 - U, torch.zeros_like(U))
     Yt = torch.from_numpy(Y.astype(np.float64))
-    I = (Sg * Yt).sum()
-    D = Sg.sum() + Yt.sum() - I
-    return 1 - I / D
+    if loss == "iou":
+        I = (Sg * Yt).sum()
+        D = Sg.sum() + Yt.sum() - I
+        return 1 - I / D
+    Sc = torch.clamp(Sg, 1e-6, 1 - 1e-6)
+    bce = -(Yt * torch.log(Sc) + (1 - Yt) * torch.log(1 - Sc)).mean()
+    pool = torch.nn.functional.avg_pool2d
+    pS = pool(Sg[None, None], 4, ceil_mode=True, count_include_pad=False)
+    pY = pool(Yt[None, None], 4, ceil_mode=True, count_include_pad=False)
+    return bce + ((pS - pY) ** 2).mean()
 
 
-def test_adjoint_matches_torch_autograd():
+@pytest.mark.parametrize("form,loss", [("product", "iou"), ("exp", "iou"), ("product", "bce"),
+                                       ("exp", "bce")])
+def test_adjoint_matches_torch_autograd(form, loss):
     b = _small_batch(5, ((20, 14),))
     prm = _params(2)
     T = 15
     Y = _target(b, T, 3)
     theta = relaxed64.theta_from_params(prm)
-    L, grad, _ = relaxed64.loss_and_grad(b, theta, T, Y)
+    kw = dict(form=form, loss=loss, **({"pool": 4} if loss == "bce" else {}))
+    L, grad, _ = relaxed64.loss_and_grad(b, theta, T, Y, **kw)
     th = torch.tensor(theta, dtype=torch.float64, requires_grad=True)
     env = relaxed64.from_batch(b, 0, 30.0)
     U0, B0, burnable = relaxed64.initial_state(b, 0)
-    Lt = _torch_forward_loss(env, th, U0, B0, T, Y[0], burnable)
+    Lt = _torch_forward_loss(env, th, U0, B0, T, Y[0], burnable, form, loss)
     Lt.backward()
     assert abs(Lt.item() - L) < 1e-13
     assert np.allclose(th.grad.numpy(), grad, rtol=1e-10, atol=1e-14)
@@ -142,9 +163,10 @@ def test_one_step_from_binary_state_is_exact_marginal():
     exact = enumerate_exact.exact_marginals(env, theta, F0, 1)
     U0 = (F0 == firegen.FLAMMABLE).astype(np.float64)
     B0 = (F0 == firegen.BURNING).astype(np.float64)
-    Us, Bs, _ = relaxed64.forward(env, theta, U0, B0, 1)
-    assert np.allclose(Us[1], exact[1, :, :, firegen.FLAMMABLE], atol=1e-14)
-    assert np.allclose(Bs[1], exact[1, :, :, firegen.BURNING], atol=1e-14)
+    for form in relaxed64.FORMS:
+        Us, Bs, _ = relaxed64.forward(env, theta, U0, B0, 1, form)
+        assert np.allclose(Us[1], exact[1, :, :, firegen.FLAMMABLE], atol=1e-14), form
+        assert np.allclose(Bs[1], exact[1, :, :, firegen.BURNING], atol=1e-14), form
 
 
 def test_saturated_relaxed_step_is_deterministic_ca():
