@@ -3,9 +3,18 @@
 One benchmark step = one pass of the hot path over the batch: the 1024 envs
 of 256 x 256 cells are reset to their initial fire state and advanced 200
 stochastic steps (one sim_step call, in-kernel burning counts).  `value` is
-cell-updates per second over the timed steps (1024 * 65536 * 200 per step).
-The relaxed forward + adjoint (256 envs of 128 x 128, 100 steps, checkpoints
-every 10) is timed after it and reported in its own object.
+cell-updates per second over the timed steps (1024 * 65536 * 200 per step),
+with the dense plan (every step reads the whole state, fuel and elevation).
+
+Reported beside it, each in its own object:
+  variants    - the same workload under the front-skipping plans (static
+                fields skipped off the front, sparse active tiles, autotuned);
+                effective rates, not roofline evidence;
+  dense_front - an ALU-bound case: a stationary checkerboard front where every
+                cell evaluates its neighbourhood each step;
+  relaxed     - the relaxed forward + adjoint on 256 envs of 128 x 128 (T 100)
+                and on one 2048 x 2048 env (T 500), checkpoints every 10;
+  cpu_baseline - the CPU oracle on the same stochastic workload.
 
 Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -22,11 +31,20 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+# 256 CUs x 64 lanes x 2.4 GHz: one non-packed 32-bit VALU op per lane per cycle
+ALU_PEAK_GOPS = 256 * 64 * 2.4
 STOCH_BYTES_PER_CELL = 10      # state r/w 2 B + fuel 4 B + elevation 4 B per cell-update
 # relaxed, fp64 state: forward 40 B (U,B r/w 32 + fuel, elevation 8); adjoint
 # 61 B (U,B 16, adjoint r/w 32, fuel, elevation, density 12, class 1); the
 # forward is recomputed from checkpoints (40 B) and every 10th state stored (1.6 B)
 RELAXED_BYTES_PER_CELL_STEP = 40 + 40 + 61 + 1.6
+# per-cell wind adds V, Vx, Vy (12 B) to each of the three passes
+RELAXED_WIND_CELL_BYTES = 3 * 12
+# fp32/int32 operations of the method (separate multiply and add, as the step
+# is specified): one phi term 30 (slope 2, exponent 2, exp 23, scale 2, sum 1),
+# the ignition probability 26 (gamma 1, product 1, exp 23, 1-e 1), one draw 29
+# (a quarter of a Philox4x32-10 block 25, uniform 2, compare 2)
+OPS_PHI, OPS_PROB, OPS_DRAW = 30, 26, 29
 KERNEL_SOURCES = ("paper_2512_06102_amd/csrc/stoch.hip", "paper_2512_06102_amd/csrc/devmath.hpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stoch_step_batch256_traffic.json")
 
@@ -59,7 +77,7 @@ def cpu_baseline(batch, params, T, seed):
     import oracle
 
     threads = min(16, len(os.sched_getaffinity(0)))
-    n_env = min(batch.n_env, 24 * threads)
+    n_env = min(batch.n_env, 64 * threads)
     sub = batch.subset(range(n_env))
     sim = oracle.Sim(sub, params, seed=seed)
     t0 = time.perf_counter()
@@ -68,7 +86,48 @@ def cpu_baseline(batch, params, T, seed):
     cells = float(sub.n_cells) * T
     return {"value": cells / dt, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
             "sample": "%d of the 1024 envs (256x256), %d steps from the initial state, "
-                      "one env per thread, %.1f s" % (n_env, T, dt)}
+                      "one env per thread at a time, %.1f s" % (n_env, T, dt)}
+
+
+class StepTimer:
+    """HIP events on the launch stream around a region."""
+
+    def __init__(self, torch, stream):
+        self.torch, self.stream = torch, stream
+
+    def __enter__(self):
+        ev = self.torch.cuda.Event
+        self.a, self.b = ev(enable_timing=True), ev(enable_timing=True)
+        self.a.record(self.stream)
+        return self
+
+    def __exit__(self, *exc):
+        self.b.record(self.stream)
+
+    def ms(self):
+        self.torch.cuda.synchronize()
+        return self.a.elapsed_time(self.b)
+
+
+def timed_runs(torch, stream, sim, init, T, steps, warmup):
+    """Reset + T steps, `warmup` untimed then `steps` timed; returns (ms per
+    reset+T-steps, ms per step launch of the last timed run)."""
+    def one():
+        sim.states.copy_(init)
+        sim.t = 0
+        sim.step(T, counts=True)
+
+    for _ in range(warmup):
+        one()
+    torch.cuda.synchronize()
+    with StepTimer(torch, stream) as whole:
+        for i in range(steps - 1):
+            one()
+        sim.states.copy_(init)
+        sim.t = 0
+        with StepTimer(torch, stream) as last:
+            sim.step(T, counts=True)
+    return whole.ms() / steps, last.ms() / T
 
 
 def bench_stochastic(args, torch, fs, firegen):
@@ -80,53 +139,114 @@ def bench_stochastic(args, torch, fs, firegen):
     sim.set_plan(**plan)
     init = sim.states.clone()
     stream = torch.cuda.current_stream()
-
-    def one_step():
-        sim.states.copy_(init)
-        sim.t = 0
-        return sim.step(T, counts=True)
-
-    for _ in range(args.warmup):
-        one_step()
-    torch.cuda.synchronize()
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    # kernel-only events around the launches of the last timed step
-    k0, k1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    if args.no_stochastic:
+        return dict(batch=batch, params=params, T=T, seed=seed, value=None, ms=float("nan"), roof=None,
+                    plan=plan, burning=None, sim=sim, init=init)
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
-    start.record(stream)
-    for i in range(args.steps):
-        sim.states.copy_(init)
-        sim.t = 0
-        if i == args.steps - 1:
-            k0.record(stream)
-        sim.step(T, counts=True)
-        if i == args.steps - 1:
-            k1.record(stream)
-    stop.record(stream)
-    torch.cuda.synchronize()
+    ms, launch_ms = timed_runs(torch, stream, sim, init, T, args.steps, args.warmup)
     wall = time.perf_counter() - wall0
-    ms = start.elapsed_time(stop) / args.steps
-    launch_ms = k0.elapsed_time(k1) / T       # average step-kernel duration (fill/set kernels included)
     cells = float(batch.n_cells)
     value = cells * T / (ms / 1e3)
     achieved = STOCH_BYTES_PER_CELL * cells / (launch_ms / 1e3) / 1e9
     plan_key = "tile_rows=%d,tile_width=%d,skip_static=%d,sparse=%d" % (
         sim.plan()["tile_rows"], sim.plan()["tile_width"], args.skip_static, args.sparse)
-    traffic = stored_traffic(plan_key)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic,
+            "traffic": stored_traffic(plan_key),
             "kernel": "stoch_step_kernel", "launch_ms": round(launch_ms, 5),
             "algorithmic_bytes_per_launch": STOCH_BYTES_PER_CELL * int(cells)}
     log("[bench] stochastic: %.3f ms/step, %.3e cell-updates/s, kernel %.4f ms = %.0f GB/s (wall %.2fs)"
         % (ms, value, launch_ms, achieved, wall))
-    counts = one_step().cpu()
-    return batch, params, T, seed, value, ms, roof, plan, int(counts.sum())
+    sim.states.copy_(init)
+    sim.t = 0
+    burning = int(sim.step(T, counts=True).sum())
+    return dict(batch=batch, params=params, T=T, seed=seed, value=value, ms=ms, roof=roof, plan=plan,
+                burning=burning, sim=sim, init=init)
 
 
-def bench_relaxed(args, torch, fs, firegen):
-    batch, params, T, k = firegen.workload_relaxed()
+def bench_variants(args, torch, fs, st):
+    """The same workload under the front-skipping plans: effective rates."""
+    sim, init, T = st["sim"], st["init"], st["T"]
+    cells = float(st["batch"].n_cells)
+    stream = torch.cuda.current_stream()
+    out = {}
+    for name, plan in (("skip_static", dict(tile_rows=4, tile_width=64, skip_static=1, graph=1)),
+                       ("sparse", dict(tile_rows=4, tile_width=64, skip_static=1, sparse=1, graph=1))):
+        sim.set_plan(**plan)
+        ms, launch_ms = timed_runs(torch, stream, sim, init, T, args.steps, 1)
+        out[name] = {"plan": plan, "ms_per_step": round(ms, 4), "value": cells * T / (ms / 1e3),
+                     "launch_ms_last_run": round(launch_ms, 5)}
+        log("[bench] variant %s: %.3f ms/step, %.3e cell-updates/s" % (name, ms, out[name]["value"]))
+    sim.states.copy_(init)
+    sim.t = 0
+    tuned = sim.autotune(T_probe=T, allow_skip=True, allow_sparse=True)
+    best = sim.plan()
+    sim.set_plan(**{k: best[k] for k in ("tile_rows", "tile_width", "skip_static", "sparse")}, graph=1)
+    ms, launch_ms = timed_runs(torch, stream, sim, init, T, args.steps, 1)
+    out["autotuned"] = {"plan": {k: best[k] for k in ("tile_rows", "tile_width", "skip_static", "sparse")},
+                        "candidates": len(tuned), "ms_per_step": round(ms, 4),
+                        "value": cells * T / (ms / 1e3)}
+    log("[bench] autotuned %s: %.3f ms/step" % (out["autotuned"]["plan"], ms))
+    out["note"] = ("effective rates: these plans read fuel and elevation only near burning cells "
+                   "(and skip quiescent tiles), so their bytes moved per cell-update are below the "
+                   "10 B the roofline counts; not roofline evidence")
+    return out
+
+
+def dense_front_ops(batch, states, firegen):
+    """Operations of one step of the method on a state (count of phi terms,
+    ignition probabilities and draws), priced with OPS_*."""
+    import numpy as np
+
+    n_phi = n_front = n_draw = 0
+    for e in range(batch.n_env):
+        st = batch.env_view(states, e)
+        burn = np.pad(st == firegen.BURNING, 1)
+        H, W = st.shape
+        nb = np.zeros((H, W), np.int32)
+        for di in (-1, 0, 1):
+            for dj in (-1, 0, 1):
+                if di or dj:
+                    nb += burn[1 + di:1 + di + H, 1 + dj:1 + dj + W]
+        flam = st == firegen.FLAMMABLE
+        front = flam & (nb > 0)
+        n_phi += int(nb[flam].sum())
+        n_front += int(front.sum())
+        n_draw += int(front.sum() + (st == firegen.BURNING).sum())
+    return n_phi, n_front, n_draw, OPS_PHI * n_phi + OPS_PROB * n_front + OPS_DRAW * n_draw
+
+
+def bench_dense_front(args, torch, fs, firegen, st):
+    """A stationary dense front: p_continue 1 keeps burning cells burning and a
+    negligible p_base keeps flammable ones flammable, while every cell still
+    evaluates its burning neighbours each step."""
+    batch, seed = st["batch"], st["seed"]
+    params = st["params"].replace(p_base=1e-30, p_continue=1.0)
+    dense = firegen.dense_front_states(batch)
+    n_phi, n_front, n_draw, ops = dense_front_ops(batch, dense, firegen)
+    sim = fs.FireSim.from_batch(batch, params, seed=seed)
+    sim.set_plan(tile_rows=args.tile_rows, tile_width=args.tile_width, skip_static=0, sparse=0, graph=1)
+    init = torch.from_numpy(dense).to(sim.states.device)
+    T = 20
+    stream = torch.cuda.current_stream()
+    ms, launch_ms = timed_runs(torch, stream, sim, init, T, args.steps, 1)
+    same = bool(torch.equal(sim.states, init))
+    cells = float(batch.n_cells)
+    gops = ops / (launch_ms / 1e3) / 1e9
+    log("[bench] dense front: %.4f ms per launch, %.3e cell-updates/s, %.0f Gop/s (stationary %s)"
+        % (launch_ms, cells / (launch_ms / 1e3), gops, same))
+    return {"workload": "1024 envs x 256x256, checkerboard BURNING/FLAMMABLE front, p_continue 1, "
+                        "p_base 1e-30 (stationary), 20 steps per call",
+            "value": cells / (launch_ms / 1e3), "unit": "cell-updates/s", "stationary": same,
+            "roofline": {"bound": "alu", "achieved": round(gops, 1), "peak": ALU_PEAK_GOPS,
+                         "unit": "Gop/s", "frac": round(gops / ALU_PEAK_GOPS, 4),
+                         "ops_per_launch": ops, "phi_terms": n_phi, "front_cells": n_front,
+                         "draws": n_draw, "launch_ms": round(launch_ms, 5),
+                         "hbm_GBs_at_10B": round(STOCH_BYTES_PER_CELL * cells / (launch_ms / 1e3) / 1e9, 1)}}
+
+
+def relaxed_case(args, torch, fs, firegen, batch, params, T, k, label):
     sim = fs.FireSim.from_batch(batch, params, seed=0)
     sim.step(T)   # target scar: a stochastic run at the known parameters
     Y = ((sim.states == firegen.BURNING) | (sim.states == firegen.BURNT)).to(torch.uint8)
@@ -134,6 +254,7 @@ def bench_relaxed(args, torch, fs, firegen):
                                               params.alpha_w2 * 1.2, params.alpha_s * 1.2,
                                               params.alpha_gamma, params.p_continue, *params.veg])
     ws = sim.relaxed_workspace(T, k)
+    stream = torch.cuda.current_stream()
 
     def fwd_bwd():
         U, B = sim.relaxed_init()
@@ -144,22 +265,34 @@ def bench_relaxed(args, torch, fs, firegen):
     fwd_bwd()
     torch.cuda.synchronize()
     reps = max(1, args.relaxed_reps)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        loss, grad = fwd_bwd()
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
+    with StepTimer(torch, stream) as tm:
+        for _ in range(reps):
+            loss, grad = fwd_bwd()
+    ms = tm.ms() / reps
     cs = float(batch.n_cells) * T / (ms / 1e3)
-    gbs = cs * RELAXED_BYTES_PER_CELL_STEP / 1e9
-    log("[bench] relaxed: %.2f ms per fwd+bwd, %.3e cell-steps/s, loss %.4f"
-        % (ms, cs, float(loss.mean())))
-    return {"value": cs, "unit": "cell-steps/s", "ms_per_fwd_bwd": round(ms, 3),
-            "workload": "relaxed128: 256 envs x 128x128, T=100, checkpoint every 10, fp64 state",
-            "algorithmic_bytes_per_cell_step": RELAXED_BYTES_PER_CELL_STEP,
-            "achieved_GBs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
-            "loss": round(float(loss.mean()), 6)}
+    bpc = RELAXED_BYTES_PER_CELL_STEP + (RELAXED_WIND_CELL_BYTES if batch.wind_cell is not None else 0)
+    gbs = cs * bpc / 1e9
+    log("[bench] relaxed %s: %.2f ms per fwd+bwd, %.3e cell-steps/s, %.0f GB/s, loss %.4f"
+        % (label, ms, cs, gbs, float(loss.mean())))
+    return {"value": cs, "unit": "cell-steps/s", "ms_per_fwd_bwd": round(ms, 3), "workload": label,
+            "algorithmic_bytes_per_cell_step": bpc, "achieved_GBs": round(gbs, 1),
+            "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "loss": round(float(loss.mean()), 6)}
+
+
+def bench_relaxed(args, torch, fs, firegen):
+    batch, params, T, k = firegen.workload_relaxed()
+    small = relaxed_case(args, torch, fs, firegen, batch, params, T, k,
+                         "relaxed128: 256 envs x 128x128, T=100, checkpoint every 10, fp64 state")
+    del batch
+    batch, params, T, k = firegen.workload_relaxed_large()
+    large = relaxed_case(args, torch, fs, firegen, batch, params, T, k,
+                         "relaxed2048: 1 env 2048x2048, per-cell wind, T=500, checkpoint every 10, "
+                         "fp64 state")
+    large["roofline"] = {"bound": "hbm", "achieved": large["achieved_GBs"], "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": large["hbm_frac"],
+                         "note": "whole fwd+bwd (forward, recompute, adjoint, loss) at the "
+                                 "algorithmic bytes per cell-step"}
+    return {"relaxed128": small, "relaxed2048": large}
 
 
 def main():
@@ -172,8 +305,12 @@ def main():
     ap.add_argument("--skip-static", type=int, default=0)
     ap.add_argument("--sparse", type=int, default=0)
     ap.add_argument("--graph", type=int, default=1)
-    ap.add_argument("--relaxed-reps", type=int, default=3)
+    ap.add_argument("--relaxed-reps", type=int, default=2)
+    ap.add_argument("--no-stochastic", action="store_true",
+                    help="skip the timed headline run (profiling of the other parts)")
     ap.add_argument("--no-relaxed", action="store_true")
+    ap.add_argument("--no-variants", action="store_true", help="skip the front-skipping plans")
+    ap.add_argument("--no-dense-front", action="store_true")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (HBM counter calibration)")
@@ -192,7 +329,10 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     fs.lib()
-    batch, params, T, seed, value, ms, roof, plan, burning = bench_stochastic(args, torch, fs, firegen)
+    st = bench_stochastic(args, torch, fs, firegen)
+    variants = None if args.no_variants else bench_variants(args, torch, fs, st)
+    dense = None if args.no_dense_front else bench_dense_front(args, torch, fs, firegen, st)
+    st.pop("sim")
     relaxed = None if args.no_relaxed else bench_relaxed(args, torch, fs, firegen)
     if args.copy_calibration:
         a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
@@ -200,16 +340,18 @@ def main():
         for _ in range(3):
             b.copy_(a)
         torch.cuda.synchronize()
-    cpu = None if args.no_cpu else cpu_baseline(batch, params, T, seed)
+    cpu = None if args.no_cpu else cpu_baseline(st["batch"], st["params"], st["T"], st["seed"])
+    batch = st["batch"]
     out = {"metric": "cell-updates/s stochastic step + relaxed fwd+bwd cell-steps/s, % HBM peak",
-           "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
+           "value": st["value"], "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(st["ms"], 4), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "batch256: 1024 envs x 256x256 cells (uint8 state), 200 steps, "
                                   "11-class land cover, fractal terrain, per-env wind, 1-5 ignitions",
-                      "n_env": int(batch.n_env), "H": 256, "W": 256, "T": T, "plan": plan,
-                      "burning_cell_steps": burning},
-           "roofline": roof, "relaxed": relaxed, "cpu_baseline": cpu}
+                      "n_env": int(batch.n_env), "H": 256, "W": 256, "T": st["T"], "plan": st["plan"],
+                      "burning_cell_steps": st["burning"]},
+           "roofline": st["roof"], "variants": variants, "dense_front": dense, "relaxed": relaxed,
+           "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
 
 

@@ -192,6 +192,37 @@ def wind_components(V: np.ndarray, theta: np.ndarray) -> np.ndarray:
                      (V64 * np.sin(th)).astype(np.float32)], axis=-1)
 
 
+def wind_series(seed: int, batch: "Batch", S: int, per_cell: bool = False,
+                speed_step: float = 0.3, turn_step: float = 0.05) -> np.ndarray:
+    """Time-varying wind for steps 0..S-1, as random walks from the batch's
+    static wind: per env, V_t = clip(V_0 + walk, 0, 15) m/s and Theta_t =
+    Theta_0 + walk (float32 [S][n_env][3]); per cell, every cell's static
+    speed is scaled by a common factor walk and its direction turned by a
+    common angle walk (float32 [S][3][n_cells])."""
+    rng = np.random.default_rng(seed)
+    if not per_cell:
+        V0 = batch.wind_env[:, 0].astype(np.float64)
+        th0 = np.arctan2(batch.wind_env[:, 2], batch.wind_env[:, 1]).astype(np.float64)
+        V = np.clip(V0[None, :] + np.cumsum(rng.normal(0, speed_step, (S, batch.n_env)), axis=0), 0, 15)
+        th = th0[None, :] + np.cumsum(rng.normal(0, turn_step, (S, batch.n_env)), axis=0)
+        return np.ascontiguousarray(wind_components(V, th))
+    if batch.wind_cell is not None:
+        V0 = batch.wind_cell[0].astype(np.float64)
+        th0 = np.arctan2(batch.wind_cell[2], batch.wind_cell[1]).astype(np.float64)
+    else:
+        V0 = np.concatenate([np.full(int(batch.H[e]) * int(batch.W[e]), batch.wind_env[e, 0], np.float64)
+                             for e in range(batch.n_env)])
+        th0 = np.concatenate([np.full(int(batch.H[e]) * int(batch.W[e]),
+                                      np.arctan2(batch.wind_env[e, 2], batch.wind_env[e, 1]), np.float64)
+                              for e in range(batch.n_env)])
+    scale = np.clip(1.0 + np.cumsum(rng.normal(0, speed_step / 10, S)), 0.0, 2.0)
+    turn = np.cumsum(rng.normal(0, turn_step, S))
+    out = np.empty((S, 3, batch.n_cells), np.float32)
+    for t in range(S):
+        out[t] = wind_components(V0 * scale[t], th0 + turn[t]).T
+    return out
+
+
 # --------------------------------------------------------------------------
 # batches
 # --------------------------------------------------------------------------
@@ -339,3 +370,28 @@ def workload_large(n_env: int = 8, side: int = 2048, seed: int = 5) -> tuple:
     batch = landscape_batch(seed, [(side, side)] * n_env, elev_max=2000.0, per_cell_wind=True,
                             class_sigma=12.0)
     return batch, params, 1000, 0
+
+
+def workload_relaxed_large(side: int = 2048, seed: int = 6) -> tuple:
+    """1 env of 2048x2048 for the relaxed path (fractal terrain 0..2000 m,
+    per-cell wind), T = 500, checkpoints every 10."""
+    rng = np.random.default_rng(seed + 1000)
+    params = Params(veg=tuple(float(v) for v in veg_table(rng)))
+    batch = landscape_batch(seed, [(side, side)], elev_max=2000.0, per_cell_wind=True, class_sigma=12.0)
+    return batch, params, 500, 10
+
+
+def dense_front_states(batch: Batch) -> np.ndarray:
+    """A checkerboard of BURNING and FLAMMABLE over every burnable cell
+    (UNBURNABLE cells kept): every flammable cell then touches a burning one.
+    With p_continue = 1 and a negligible p_base the pattern is stationary, so
+    each step evaluates the whole neighbourhood arithmetic at every cell."""
+    out = np.empty(batch.n_cells, np.uint8)
+    for e in range(batch.n_env):
+        H, W = int(batch.H[e]), int(batch.W[e])
+        ii, jj = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+        st = np.where((ii + jj) % 2 == 0, BURNING, FLAMMABLE).astype(np.uint8)
+        burnable = ~np.isin(batch.env_view(batch.cls, e), UNBURNABLE_CLASSES)
+        st[~burnable] = UNBURNABLE
+        batch.env_view(out, e)[...] = st
+    return out

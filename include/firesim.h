@@ -124,6 +124,21 @@ int sim_init(sim_handle** out, const sim_params* p, int32_t n_env, const sim_env
 int sim_step(sim_handle* h, uint8_t* states, const int32_t* actions, int32_t T, int32_t* counts,
              void* stream);
 
+/* sim_set_wind_series -- time-varying wind (section 3, state representation:
+ * wind speed and direction are per-step fields; section 4 mentions weather
+ * given as a time series).  Step t (F_t -> F_{t+1}, absolute t) takes its
+ * wind from row t of the series instead of the static wind:
+ *  env_wind   device float[series_T][n_env][3] (V, V cos Theta, V sin Theta)
+ *             per env and step, or NULL;
+ *  cell_wind  device float[series_T][3][n_cells] (the V | Vx | Vy planes of
+ *             step t, packed like sim_init's wind_cell), or NULL.
+ * At most one of the two; both NULL returns to the static wind.  A handle
+ * created with per-cell wind accepts only a per-cell series.  The memory is
+ * the caller's and must stay valid while steps run.  sim_step and
+ * sim_autotune fail with SIM_EINVAL when a call would read past row
+ * series_T - 1.  The relaxed calls keep the static wind. */
+int sim_set_wind_series(sim_handle* h, const float* env_wind, const float* cell_wind, int64_t series_T);
+
 /* Step counter: get it, or set it to resume a saved run (states saved by
  * the caller, same handle inputs and seed). */
 int sim_get_step(const sim_handle* h, uint64_t* t);

@@ -62,6 +62,7 @@ def lib():
         L.oracle_cell_prob.restype = ctypes.c_float
         L.oracle_run.argtypes = [P, ctypes.c_int32, P, P, P, P, ctypes.c_int64, P, ctypes.c_uint64,
                                  ctypes.c_int32, P, P, ctypes.c_uint64, ctypes.c_int32]
+        L.oracle_run_series.argtypes = L.oracle_run.argtypes + [P, P]
         _lib = L
     return _lib
 
@@ -148,15 +149,26 @@ class Sim:
         self.states = init_states(batch)
         self.t = 0
 
-    def step(self, T: int, actions=None, counts: bool = False, threads: int = 1):
+    def step(self, T: int, actions=None, counts: bool = False, threads: int = 1,
+             wind_env_series=None, wind_cell_series=None):
+        """T steps from the current step t.  A wind series (float32
+        [S][n_env][3] per env, or [S][3][n_cells] per cell, row = absolute
+        step) replaces the static wind for steps t .. t+T-1."""
         n_env = self.batch.n_env
         act = None if actions is None else np.ascontiguousarray(actions, np.int32)
         if act is not None and act.shape != (T, n_env):
             raise ValueError("actions must be [T, n_env]")
+        es = None if wind_env_series is None else np.ascontiguousarray(wind_env_series, np.float32)
+        cs = None if wind_cell_series is None else np.ascontiguousarray(wind_cell_series, np.float32)
+        if es is not None and (es.ndim != 3 or es.shape[1:] != (n_env, 3) or es.shape[0] < self.t + T):
+            raise ValueError("wind_env_series must be [>= t+T, n_env, 3]")
+        if cs is not None and (cs.ndim != 3 or cs.shape[1:] != (3, self.batch.n_cells)
+                               or cs.shape[0] < self.t + T):
+            raise ValueError("wind_cell_series must be [>= t+T, 3, n_cells]")
         cnt = np.zeros((T, n_env), np.int32) if counts else None
-        lib().oracle_run(ctypes.byref(self.P), n_env, self.envs, _ptr(self.g), _ptr(self.E),
-                         _ptr(self.wind_cell), self.batch.n_cells, _ptr(self.states), self.t, T,
-                         _ptr(act), _ptr(cnt), self.seed, threads)
+        lib().oracle_run_series(ctypes.byref(self.P), n_env, self.envs, _ptr(self.g), _ptr(self.E),
+                                _ptr(self.wind_cell), self.batch.n_cells, _ptr(self.states), self.t, T,
+                                _ptr(act), _ptr(cnt), self.seed, threads, _ptr(es), _ptr(cs))
         self.t += T
         return cnt
 

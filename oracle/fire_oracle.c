@@ -261,8 +261,9 @@ int oracle_init_states(int32_t n_env, const oracle_env* envs, const uint8_t* cls
     return 0;
 }
 
-/* Wind at the source cell u: per env, or per cell when wind_cell is given   */
-/* as three planes [V | Vx | Vy] of n_cells each.                            */
+/* Wind at the source cell u: per env (V, Vx, Vy of the current step), or   */
+/* per cell when wind_cell is given as three planes [V | Vx | Vy] of n_cells */
+/* each (the planes of the current step).                                    */
 typedef struct {
     const oracle_params* P;
     const oracle_env* env;
@@ -270,6 +271,7 @@ typedef struct {
     const float* E;
     const float* wind_cell;
     int64_t n_cells;
+    float V, Vx, Vy;
     float cx[8], sy[8], invd[8];
 } step_ctx;
 
@@ -282,6 +284,9 @@ static void init_ctx(step_ctx* c, const oracle_params* P, const oracle_env* env,
     c->E = E;
     c->wind_cell = wind_cell;
     c->n_cells = n_cells;
+    c->V = env->V;
+    c->Vx = env->Vx;
+    c->Vy = env->Vy;
     direction_cos_sin(c->cx, c->sy);
     for (int k = 0; k < 8; ++k)
         c->invd[k] = (k & 1) ? (float)(1.0 / ((double)P->cell_size * sqrt(2.0)))
@@ -298,9 +303,9 @@ static float phi_uk(const step_ctx* c, int64_t u, int64_t v, int k)
         Vx = c->wind_cell[c->n_cells + u];
         Vy = c->wind_cell[2 * c->n_cells + u];
     } else {
-        V = c->env->V;
-        Vx = c->env->Vx;
-        Vy = c->env->Vy;
+        V = c->V;
+        Vx = c->Vx;
+        Vy = c->Vy;
     }
     /* exponent of kappa_wind: alpha_w1 V + alpha_w2 V (cos(phi_k - Theta) - 1) */
     float wind_exp = P->alpha_w1 * V + P->alpha_w2 * ((c->cx[k] * Vx + c->sy[k] * Vy) - V);
@@ -353,11 +358,13 @@ static void apply_action(const oracle_env* e, uint8_t* F, int32_t a)
 }
 
 /* Advance one env by T steps from absolute step t0.  actions/counts are    */
-/* [T][n_env] (row s holds step t0+s) or NULL.                              */
+/* [T][n_env] (row s holds step t0+s) or NULL.  A wind series, when given,   */
+/* is indexed by the absolute step t: env_series [t][n_env][3] or            */
+/* cell_series [t][3][n_cells]; it replaces the static wind of that step.    */
 static void run_env(const oracle_params* P, int32_t n_env, int32_t e, const oracle_env* envs,
                     const float* g, const float* E, const float* wind_cell, int64_t n_cells,
                     uint8_t* states, uint64_t t0, int32_t T, const int32_t* actions, int32_t* counts,
-                    uint64_t seed)
+                    uint64_t seed, const float* env_series, const float* cell_series)
 {
     const oracle_env* env = &envs[e];
     int64_t n = (int64_t)env->H * env->W;
@@ -367,6 +374,13 @@ static void run_env(const oracle_params* P, int32_t n_env, int32_t e, const orac
     uint8_t* F = states; /* F indexed by packed index; this env's cells only */
     for (int32_t s = 0; s < T; ++s) {
         uint64_t t = t0 + (uint64_t)s;
+        if (env_series) {
+            const float* w = env_series + ((int64_t)t * n_env + e) * 3;
+            c.V = w[0];
+            c.Vx = w[1];
+            c.Vy = w[2];
+        }
+        if (cell_series) c.wind_cell = cell_series + (int64_t)t * 3 * n_cells;
         if (actions) apply_action(env, F, actions[(int64_t)s * n_env + e]);
         int32_t burning = 0;
         for (int32_t i = 0; i < env->H; ++i) {
@@ -404,6 +418,7 @@ typedef struct {
     int32_t* counts;
     uint64_t seed;
     int32_t first, stride;
+    const float *env_series, *cell_series;
 } run_job;
 
 static void* run_worker(void* arg)
@@ -411,15 +426,16 @@ static void* run_worker(void* arg)
     run_job* j = (run_job*)arg;
     for (int32_t e = j->first; e < j->n_env; e += j->stride)
         run_env(j->P, j->n_env, e, j->envs, j->g, j->E, j->wind_cell, j->n_cells, j->states, j->t0,
-                j->T, j->actions, j->counts, j->seed);
+                j->T, j->actions, j->counts, j->seed, j->env_series, j->cell_series);
     return NULL;
 }
 
 /* Run T steps on every env.  Envs are independent, so n_threads > 1 only   */
 /* spreads whole envs over threads; each env is still stepped as above.     */
-void oracle_run(const oracle_params* P, int32_t n_env, const oracle_env* envs, const float* g,
-                const float* E, const float* wind_cell, int64_t n_cells, uint8_t* states, uint64_t t0,
-                int32_t T, const int32_t* actions, int32_t* counts, uint64_t seed, int32_t n_threads)
+void oracle_run_series(const oracle_params* P, int32_t n_env, const oracle_env* envs, const float* g,
+                       const float* E, const float* wind_cell, int64_t n_cells, uint8_t* states,
+                       uint64_t t0, int32_t T, const int32_t* actions, int32_t* counts, uint64_t seed,
+                       int32_t n_threads, const float* env_series, const float* cell_series)
 {
     if (n_threads < 1) n_threads = 1;
     if (n_threads > 256) n_threads = 256;
@@ -427,7 +443,7 @@ void oracle_run(const oracle_params* P, int32_t n_env, const oracle_env* envs, c
     pthread_t th[256];
     for (int32_t i = 0; i < n_threads; ++i) {
         run_job j = {P, n_env, envs, g, E, wind_cell, n_cells, states, t0, T, actions, counts, seed, i,
-                     n_threads};
+                     n_threads, env_series, cell_series};
         jobs[i] = j;
     }
     if (n_threads == 1) {
@@ -436,4 +452,12 @@ void oracle_run(const oracle_params* P, int32_t n_env, const oracle_env* envs, c
     }
     for (int32_t i = 0; i < n_threads; ++i) pthread_create(&th[i], NULL, run_worker, &jobs[i]);
     for (int32_t i = 0; i < n_threads; ++i) pthread_join(th[i], NULL);
+}
+
+void oracle_run(const oracle_params* P, int32_t n_env, const oracle_env* envs, const float* g,
+                const float* E, const float* wind_cell, int64_t n_cells, uint8_t* states, uint64_t t0,
+                int32_t T, const int32_t* actions, int32_t* counts, uint64_t seed, int32_t n_threads)
+{
+    oracle_run_series(P, n_env, envs, g, E, wind_cell, n_cells, states, t0, T, actions, counts, seed,
+                      n_threads, NULL, NULL);
 }

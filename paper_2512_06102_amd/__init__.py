@@ -25,7 +25,7 @@ THETA_NAMES = ("p_base", "alpha_w1", "alpha_w2", "alpha_s", "alpha_gamma", "p_co
     tuple("veg%d" % c for c in range(N_CLASSES))
 
 EXPORTED = ("sim_init", "sim_step", "sim_get_step", "sim_set_step", "sim_set_plan", "sim_get_plan",
-            "sim_autotune",
+            "sim_autotune", "sim_set_wind_series",
             "sim_relaxed_init", "sim_relaxed_workspace_bytes", "sim_step_relaxed_fwd",
             "sim_relaxed_loss", "sim_relaxed_loss_bce", "sim_step_relaxed_bwd", "sim_debug_exp", "sim_debug_philox",
             "sim_last_error", "sim_destroy")
@@ -78,6 +78,7 @@ def lib() -> ctypes.CDLL:
         L.sim_set_step.argtypes = [P, U64]
         L.sim_set_plan.argtypes = [P, P]
         L.sim_get_plan.argtypes = [P, P]
+        L.sim_set_wind_series.argtypes = [P, P, P, I64]
         L.sim_autotune.argtypes = [P, P, I32, I32, I32, P, I32, ctypes.POINTER(I32), P]
         L.sim_relaxed_init.argtypes = [P, P, P, P]
         L.sim_relaxed_workspace_bytes.argtypes = [P, I32, I32]
@@ -232,6 +233,24 @@ class FireSim:
         _check(lib().sim_step(self.handle, _ptr(st), _ptr(actions), int(T), _ptr(cnt), self._s()),
                self.handle)
         return cnt
+
+    def set_wind_series(self, env_series: Optional[torch.Tensor] = None,
+                        cell_series: Optional[torch.Tensor] = None):
+        """Time-varying wind: float32 device [S][n_env][3] per env or
+        [S][3][n_cells] per cell, (V, V cos Theta, V sin Theta), row = absolute
+        step.  None for both restores the static wind.  The tensor is kept
+        alive by the simulator until replaced."""
+        S = 0
+        for ser, shape in ((env_series, (self.n_env, 3)), (cell_series, (3, self.n_cells))):
+            if ser is None:
+                continue
+            if ser.dtype != torch.float32 or ser.device != self.device or ser.dim() != 3 \
+                    or tuple(ser.shape[1:]) != shape or not ser.is_contiguous():
+                raise ValueError("wind series must be a contiguous float32 [S, %d, %d] tensor on %s"
+                                 % (shape + (self.device,)))
+            S = int(ser.shape[0])
+        _check(lib().sim_set_wind_series(self.handle, _ptr(env_series), _ptr(cell_series), S), self.handle)
+        self._wind_series = (env_series, cell_series)
 
     @property
     def t(self) -> int:

@@ -45,6 +45,10 @@ struct sim_handle {
     uint64_t seed = 0;
     uint64_t t = 0;
     sim_plan plan{4, 256, 1, 0, 0, 0};
+    // wind series (caller-owned device memory, indexed by the absolute step)
+    const float* series_env = nullptr;   // [series_T][n_env][3]
+    const float* series_cell = nullptr;  // [series_T][3][n_cells]
+    int64_t series_T = 0;
 
     EnvDev* d_envs = nullptr;
     float* d_g = nullptr;
@@ -175,7 +179,14 @@ StepLaunch step_launch(const sim_handle* h)
     L.n_tiles = h->n_tiles;
     L.envs = h->d_envs;
     L.n_env = h->n_env;
-    L.fields = StaticFields{h->d_g, h->d_E, h->wind_cell ? h->d_wind : nullptr, h->n_cells};
+    L.fields = StaticFields{h->d_g, h->d_E, h->wind_cell ? h->d_wind : nullptr, h->n_cells, 0, nullptr,
+                            h->n_env};
+    if (h->series_cell) {
+        L.fields.wind = h->series_cell;
+        L.fields.wind_stride = 3 * h->n_cells;
+    } else if (h->series_env) {
+        L.fields.env_wind = h->series_env;
+    }
     L.args = step_args(h);
     L.aligned = h->aligned;
     L.rows_per_thread = h->plan.tile_rows;
@@ -369,6 +380,9 @@ int sim_step(sim_handle* h, uint8_t* states, const int32_t* actions, int32_t T, 
     if (T == 0) return SIM_OK;
     if (h->t + (uint64_t)T > 0xFFFFFFFFull)
         return fail(h, SIM_ESTATE, "step counter would pass 2^32");
+    if ((h->series_env || h->series_cell) && h->t + (uint64_t)T > (uint64_t)h->series_T)
+        return fail(h, SIM_EINVAL, "the wind series covers steps 0..%lld, the call needs up to step %llu",
+                    (long long)h->series_T - 1, (unsigned long long)(h->t + T - 1));
     hipStream_t s = (hipStream_t)stream;
     if (h->tiles_rt != h->plan.tile_rows || h->tiles_tw != h->plan.tile_width) {
         const int rc = build_tiles(h, h->plan.tile_rows, h->plan.tile_width);
@@ -407,6 +421,21 @@ int sim_step(sim_handle* h, uint8_t* states, const int32_t* actions, int32_t T, 
         HIP_OR_FAIL(h, enqueue_steps(h, s, states, actions, T, counts));
     }
     h->t += (uint64_t)T;
+    return SIM_OK;
+}
+
+int sim_set_wind_series(sim_handle* h, const float* env_wind, const float* cell_wind, int64_t series_T)
+{
+    if (!h) return fail(nullptr, SIM_EINVAL, "handle is NULL");
+    if (env_wind && cell_wind) return fail(h, SIM_EINVAL, "give a per-env or a per-cell series, not both");
+    if ((env_wind || cell_wind) && series_T < 1) return fail(h, SIM_EINVAL, "series_T must be >= 1");
+    if (!env_wind && !cell_wind) series_T = 0;
+    if (env_wind && h->wind_cell)
+        return fail(h, SIM_EINVAL, "this handle has per-cell wind: give a per-cell series");
+    h->series_env = env_wind;
+    h->series_cell = cell_wind;
+    h->series_T = series_T;
+    h->graph.valid = false;  // the series pointers are kernel arguments
     return SIM_OK;
 }
 
@@ -449,6 +478,8 @@ int sim_autotune(sim_handle* h, const uint8_t* states, int32_t T_probe, int32_t 
     if (!h) return fail(nullptr, SIM_EINVAL, "handle is NULL");
     if (!states || T_probe < 1 || max_results < 0 || (max_results > 0 && !results))
         return fail(h, SIM_EINVAL, "need states, T_probe >= 1 and a results array");
+    if ((h->series_env || h->series_cell) && h->t + (uint64_t)T_probe > (uint64_t)h->series_T)
+        return fail(h, SIM_EINVAL, "T_probe steps from the current step run past the wind series");
     hipStream_t s = (hipStream_t)stream;
     const sim_plan saved = h->plan;
     uint8_t* work = nullptr;

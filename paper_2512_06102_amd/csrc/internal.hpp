@@ -24,12 +24,18 @@ struct StepArgs {
     uint32_t key0, key1;               // Philox key (seed lo, seed hi)
 };
 
-// Static inputs resident in HBM for the whole life of a handle.
+// Inputs of the step resident in HBM: fuel and elevation for the life of a
+// handle; wind either static (per env in EnvDev, or per cell) or a series
+// indexed by the absolute step t.
 struct StaticFields {
-    const float* g;      // fuel term (1 + veg[class]) (1 + den), fp32 [n_cells]
-    const float* E;      // elevation, m [n_cells]
-    const float* wind;   // [3][n_cells] (V | Vx | Vy) or nullptr (per-env wind)
+    const float* g;         // fuel term (1 + veg[class]) (1 + den), fp32 [n_cells]
+    const float* E;         // elevation, m [n_cells]
+    const float* wind;      // [3][n_cells] (V | Vx | Vy), or [T][3][n_cells] when
+                            // wind_stride != 0, or nullptr (per-env wind)
     int64_t n_cells;
+    int64_t wind_stride;    // elements between the per-cell wind of steps t and t+1
+    const float* env_wind;  // [T][n_env][3] per-env wind series or nullptr
+    int32_t n_env;
 };
 
 // One workgroup tile of the stochastic step: env, first row, first column and

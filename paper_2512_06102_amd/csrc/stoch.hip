@@ -193,7 +193,7 @@ __device__ __forceinline__ uint32_t apply_drop(uint32_t w, int gi, int gj, int a
 template <bool ALIGNED, bool WIND_CELL, int RT, bool SKIP>
 __global__ __launch_bounds__(kWave) void stoch_step_kernel(
     const TileDesc* __restrict__ tiles, int32_t n_tiles, int32_t tiles_per_xcd,
-    const EnvDev* __restrict__ envs, StaticFields F, StepArgs A, const uint8_t* __restrict__ src,
+    const EnvDev* __restrict__ envs, StaticFields F0, StepArgs A, const uint8_t* __restrict__ src,
     uint8_t* __restrict__ dst, const uint32_t* __restrict__ t_base, uint32_t step,
     const int32_t* __restrict__ actions_row, int32_t* __restrict__ counts_row, SparseArgs SP)
 {
@@ -216,6 +216,8 @@ __global__ __launch_bounds__(kWave) void stoch_step_kernel(
     const int row0 = td.r0 + ty * RT;  // first own row
     const int gj0 = td.c0 + 4 * tx;    // first own column
     const uint32_t t = *t_base + step;
+    StaticFields F = F0;
+    if (F0.wind_stride != 0) F.wind = F0.wind + (int64_t)t * F0.wind_stride;
     const int64_t base = ed.offset;
     const uint8_t* env_src = src + base;
     const uint2 key = make_uint2(A.key0, A.key1);
@@ -313,7 +315,16 @@ __global__ __launch_bounds__(kWave) void stoch_step_kernel(
         }
     }
     if constexpr (!WIND_CELL) {
-        if (lane < 8) lds_ew[lane] = wind_exponent(lane, A.alpha_w1, A.alpha_w2, ed.V, ed.Vx, ed.Vy);
+        if (lane < 8) {
+            float V = ed.V, Vx = ed.Vx, Vy = ed.Vy;
+            if (F.env_wind) {
+                const float* w = F.env_wind + ((int64_t)t * F.n_env + td.env) * 3;
+                V = w[0];
+                Vx = w[1];
+                Vy = w[2];
+            }
+            lds_ew[lane] = wind_exponent(lane, A.alpha_w1, A.alpha_w2, V, Vx, Vy);
+        }
     }
 
     // -- 2. suppression drop on the loaded dwords and halo bytes, before the step

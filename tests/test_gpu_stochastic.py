@@ -153,6 +153,26 @@ def test_dense_fronts_overflow_the_lists(tile_rows):
     assert np.array_equal(c, rc)
 
 
+def test_stationary_dense_front_benchmark_case():
+    """The benchmark's ALU-bound case (checkerboard front, p_base 1e-30,
+    p_continue 1) on envs of the 1024 x 256^2 workload in the benchmark's plan:
+    bit-exact against the oracle and stationary."""
+    batch, params, T, seed = firegen.workload_batch256(n_env=6)
+    params = params.replace(p_base=1e-30, p_continue=1.0)
+    dense = firegen.dense_front_states(batch)
+    sim = fs.FireSim.from_batch(batch, params, seed=seed)
+    sim.set_plan(tile_rows=4, tile_width=256, skip_static=0, sparse=0, graph=1)
+    ref = oracle.Sim(batch, params, seed=seed)
+    ref.states[:] = dense
+    sim.states.copy_(torch.from_numpy(dense))
+    c = sim.step(5, counts=True).cpu().numpy()
+    rc = ref.step(5, counts=True, threads=6)
+    torch.cuda.synchronize()
+    assert np.array_equal(sim.states.cpu().numpy(), ref.states)
+    assert np.array_equal(c, rc)
+    assert np.array_equal(ref.states, dense)
+
+
 def test_graph_replay_and_resume_split():
     """Graph-captured calls replayed several times, and T1 + T2 + T3 split
     calls, equal one oracle run of T1 + T2 + T3 steps."""
@@ -314,3 +334,50 @@ def test_sparse_plan_with_drops_graph_and_splits(skip_static, tile_width, tile_r
                                     split=[7, 20, 20, 13])
     assert np.array_equal(sim.states.cpu().numpy(), ref.states)
     assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("per_cell", [False, True])
+def test_wind_series(per_cell):
+    """Time-varying wind (per env or per cell, indexed by the absolute step):
+    bit-exact against the oracle across split calls, graph replays and a
+    sparse plan; a call reaching past the series is rejected."""
+    batch = firegen.landscape_batch(21, [(128, 128), (64, 200), (37, 53)], per_cell_wind=per_cell)
+    params = firegen.Params(p_base=0.8, veg=_veg(21))
+    S = 40
+    ser = firegen.wind_series(5, batch, S, per_cell=per_cell, speed_step=1.0, turn_step=0.3)
+    kw = {"wind_cell_series" if per_cell else "wind_env_series": ser}
+    ref = oracle.Sim(batch, params, seed=9)
+    want = [ref.step(15, counts=True, threads=6, **kw), ref.step(25, counts=True, threads=6, **kw)]
+    for plan in (dict(graph=1), dict(graph=0, tile_width=64, tile_rows=2, skip_static=1, sparse=1)):
+        sim = fs.FireSim.from_batch(batch, params, seed=9)
+        sim.set_plan(**plan)
+        dev = torch.from_numpy(ser).cuda()
+        sim.set_wind_series(cell_series=dev) if per_cell else sim.set_wind_series(env_series=dev)
+        got = [sim.step(15, counts=True).cpu().numpy(), sim.step(25, counts=True).cpu().numpy()]
+        torch.cuda.synchronize()
+        assert np.array_equal(sim.states.cpu().numpy(), ref.states), plan
+        for g, w in zip(got, want):
+            assert np.array_equal(g, w), plan
+        with pytest.raises(fs.SimError):
+            sim.step(1)
+        sim.set_wind_series()          # back to the static wind
+        sim.step(1)
+    static = oracle.Sim(batch, params, seed=9)
+    static.step(40, threads=6)
+    assert not np.array_equal(static.states, ref.states)
+
+
+def test_wind_series_argument_checks():
+    batch = firegen.landscape_batch(22, [(32, 32)] * 2, per_cell_wind=True)
+    sim = fs.FireSim.from_batch(batch, firegen.Params(), seed=0)
+    env_ser = torch.zeros((4, 2, 3), dtype=torch.float32, device="cuda")
+    with pytest.raises(fs.SimError):   # per-cell handle takes only a per-cell series
+        sim.set_wind_series(env_series=env_ser)
+    with pytest.raises(ValueError):
+        sim.set_wind_series(cell_series=torch.zeros((4, 3, 7), dtype=torch.float32, device="cuda"))
+    cell = torch.zeros((4, 3, batch.n_cells), dtype=torch.float32, device="cuda")
+    with pytest.raises(fs.SimError):
+        fs._check(fs.lib().sim_set_wind_series(sim.handle, fs._ptr(env_ser), fs._ptr(cell), 4), sim.handle)
+    sim.set_wind_series(cell_series=cell)
+    sim.step(4)
+    torch.cuda.synchronize()

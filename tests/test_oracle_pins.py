@@ -408,3 +408,61 @@ def test_directional_sanity():
     b.elev[:] = np.tile(((n - 1 - ii) * 3.0).astype(np.float32).ravel(), R)
     north = scar(b)
     assert (north * ii).sum() / north.sum() < n // 2 - 1.0
+
+
+# ------------------------------------------------------ time-varying wind --
+def _with_env_wind(b, wind):
+    import dataclasses
+    return dataclasses.replace(b, wind_env=np.ascontiguousarray(wind, np.float32))
+
+
+def test_wind_series_constant_equals_static():
+    """A series repeating the static wind gives the static run, per env and
+    per cell."""
+    prm = firegen.Params(veg=tuple(firegen.veg_table(np.random.default_rng(4))))
+    b = firegen.landscape_batch(8, [(40, 40), (24, 56)])
+    a = oracle.Sim(b, prm, seed=3)
+    a.step(30)
+    c = oracle.Sim(b, prm, seed=3)
+    c.step(30, wind_env_series=np.repeat(b.wind_env[None], 30, axis=0))
+    assert np.array_equal(a.states, c.states)
+    bc = firegen.landscape_batch(8, [(40, 40), (24, 56)], per_cell_wind=True)
+    a = oracle.Sim(bc, prm, seed=3)
+    a.step(30)
+    c = oracle.Sim(bc, prm, seed=3)
+    c.step(30, wind_cell_series=np.repeat(bc.wind_cell[None], 30, axis=0))
+    assert np.array_equal(a.states, c.states)
+
+
+def test_wind_series_is_indexed_by_absolute_step():
+    """Wind A for steps 0..k-1 and B from step k equals k static steps under A
+    followed by static steps under B from step k (also when the series run is
+    itself split), and a per-cell series that broadcasts each env's wind
+    equals the per-env series."""
+    prm = firegen.Params(p_base=0.7, veg=tuple(firegen.veg_table(np.random.default_rng(5))))
+    b = firegen.landscape_batch(9, [(48, 48), (30, 50), (40, 20)])
+    A = firegen.wind_components(np.array([9.0, 2.0, 6.0]), np.array([0.0, 2.0, 4.0]))
+    B = firegen.wind_components(np.array([3.0, 8.0, 6.0]), np.array([3.0, 1.0, 4.5]))
+    k, T = 7, 20
+    ser = np.concatenate([np.repeat(A[None], k, 0), np.repeat(B[None], T - k, 0)])
+    ref = oracle.Sim(_with_env_wind(b, A), prm, seed=11)
+    ref.step(k)
+    ref2 = oracle.Sim(_with_env_wind(b, B), prm, seed=11)
+    ref2.states[:] = ref.states
+    ref2.t = k
+    ref2.step(T - k)
+    only_a = oracle.Sim(_with_env_wind(b, A), prm, seed=11)
+    only_a.step(T)
+    assert not np.array_equal(only_a.states, ref2.states)  # the switch matters
+    s = oracle.Sim(b, prm, seed=11)
+    s.step(12, wind_env_series=ser)
+    s.step(T - 12, wind_env_series=ser)
+    assert np.array_equal(s.states, ref2.states)
+    cell = np.empty((T, 3, b.n_cells), np.float32)
+    for e in range(b.n_env):
+        cell[:, :, b.env_slice(e)] = ser[:, e, :, None]
+    c = oracle.Sim(b, prm, seed=11)
+    c.step(T, wind_cell_series=cell)
+    assert np.array_equal(c.states, ref2.states)
+    with pytest.raises(ValueError):
+        oracle.Sim(b, prm).step(T + 1, wind_env_series=ser)
