@@ -13,7 +13,7 @@ Reported beside it, each in its own object:
   dense_front - an ALU-bound case: a stationary checkerboard front where every
                 cell evaluates its neighbourhood each step;
   relaxed     - the relaxed forward + adjoint on 256 envs of 128 x 128 (T 100)
-                and on one 2048 x 2048 env (T 500), checkpoints every 10;
+                and on one 2048 x 2048 env (T 100), checkpoints every 10;
   cpu_baseline - the CPU oracle on the same stochastic workload.
 
 Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -286,7 +286,7 @@ def bench_relaxed(args, torch, fs, firegen):
     del batch
     batch, params, T, k = firegen.workload_relaxed_large()
     large = relaxed_case(args, torch, fs, firegen, batch, params, T, k,
-                         "relaxed2048: 1 env 2048x2048, per-cell wind, T=500, checkpoint every 10, "
+                         "relaxed2048: 1 env 2048x2048, per-cell wind, T=100, checkpoint every 10, "
                          "fp64 state")
     large["roofline"] = {"bound": "hbm", "achieved": large["achieved_GBs"], "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": large["hbm_frac"],

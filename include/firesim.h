@@ -108,11 +108,12 @@ int sim_init(sim_handle** out, const sim_params* p, int32_t n_env, const sim_env
  * Eqs. 1-4, "Stochastic update"), starting at the handle's step counter t,
  * which then advances by T.
  *  states   device uint8[n_cells], updated in place.
- *  actions  device int32[T][n_env] or NULL: before step s, env e drops
- *           suppression on the 5x5 square centred at (a>>16, a&0xFFFF) for
- *           a = actions[s][e] >= 0 (every FLAMMABLE or BURNING cell of the
- *           square, clipped to the grid, becomes UNBURNABLE); a < 0 or a
- *           centre outside the grid means no drop.
+ *  actions  device int32[T][n_env] or NULL: before step s, env e makes a
+ *           drop on the square centred at (a>>16, a&0xFFFF) for a =
+ *           actions[s][e] >= 0, clipped to the grid; by default (see
+ *           sim_set_drop) the square is 5x5 and every FLAMMABLE or BURNING
+ *           cell in it becomes UNBURNABLE.  a < 0 or a centre outside the
+ *           grid means no drop.
  *  counts   device int32[T][n_env] or NULL: number of BURNING cells of each
  *           env after each step (overwritten).
  * The random draw of cell n = i*W + j of env e at absolute step t is
@@ -138,6 +139,23 @@ int sim_step(sim_handle* h, uint8_t* states, const int32_t* actions, int32_t T, 
  * sim_autotune fail with SIM_EINVAL when a call would read past row
  * series_T - 1.  The relaxed calls keep the static wind. */
 int sim_set_wind_series(sim_handle* h, const float* env_wind, const float* cell_wind, int64_t series_T);
+
+/* sim_step_history -- sim_step that also keeps every intermediate state
+ * (the scan form of the rollout): history is device uint8[T][n_cells] and
+ * row k receives F_{t+k+1}; states ends equal to row T-1.  The steps write
+ * straight into the rows, so the history costs no extra pass.  Same
+ * arguments and errors as sim_step otherwise; history NULL is SIM_EINVAL. */
+int sim_step_history(sim_handle* h, uint8_t* states, const int32_t* actions, int32_t T, int32_t* counts,
+                     uint8_t* history, void* stream);
+
+/* sim_set_drop -- what a drop (the actions of sim_step) does to the cells of
+ * its (2 radius + 1)^2 square: SIM_DROP_SUPPRESS turns FLAMMABLE and BURNING
+ * cells UNBURNABLE (a retardant line; the default, radius 2), SIM_DROP_WATER
+ * turns BURNING cells BURNT (section 4: water changes a burning cell to
+ * burned).  radius in 0..255; other values are SIM_EINVAL. */
+#define SIM_DROP_SUPPRESS 0
+#define SIM_DROP_WATER 1
+int sim_set_drop(sim_handle* h, int32_t mode, int32_t radius);
 
 /* Step counter: get it, or set it to resume a saved run (states saved by
  * the caller, same handle inputs and seed). */

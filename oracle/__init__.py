@@ -62,7 +62,7 @@ def lib():
         L.oracle_cell_prob.restype = ctypes.c_float
         L.oracle_run.argtypes = [P, ctypes.c_int32, P, P, P, P, ctypes.c_int64, P, ctypes.c_uint64,
                                  ctypes.c_int32, P, P, ctypes.c_uint64, ctypes.c_int32]
-        L.oracle_run_series.argtypes = L.oracle_run.argtypes + [P, P]
+        L.oracle_run_ex.argtypes = L.oracle_run.argtypes + [P, P, ctypes.c_int32, ctypes.c_int32]
         _lib = L
     return _lib
 
@@ -150,10 +150,23 @@ class Sim:
         self.t = 0
 
     def step(self, T: int, actions=None, counts: bool = False, threads: int = 1,
-             wind_env_series=None, wind_cell_series=None):
+             wind_env_series=None, wind_cell_series=None, drop_mode: int = 0, drop_radius: int = 2,
+             history: bool = False):
         """T steps from the current step t.  A wind series (float32
         [S][n_env][3] per env, or [S][3][n_cells] per cell, row = absolute
-        step) replaces the static wind for steps t .. t+T-1."""
+        step) replaces the static wind for steps t .. t+T-1.  Drops (actions)
+        cover (2 drop_radius + 1)^2 cells; drop_mode 0 makes FLAMMABLE and
+        BURNING cells UNBURNABLE, 1 makes BURNING cells BURNT.  With history
+        the states after every step are returned ([T, n_cells]) instead of
+        the counts; counts then come second."""
+        if history:
+            rows, cnts = [], []
+            for _ in range(T):
+                c = self.step(1, None if actions is None else np.asarray(actions)[len(rows):len(rows) + 1],
+                              counts, threads, wind_env_series, wind_cell_series, drop_mode, drop_radius)
+                rows.append(self.states.copy())
+                cnts.append(c)
+            return np.stack(rows), (np.concatenate(cnts) if counts else None)
         n_env = self.batch.n_env
         act = None if actions is None else np.ascontiguousarray(actions, np.int32)
         if act is not None and act.shape != (T, n_env):
@@ -166,9 +179,10 @@ class Sim:
                                or cs.shape[0] < self.t + T):
             raise ValueError("wind_cell_series must be [>= t+T, 3, n_cells]")
         cnt = np.zeros((T, n_env), np.int32) if counts else None
-        lib().oracle_run_series(ctypes.byref(self.P), n_env, self.envs, _ptr(self.g), _ptr(self.E),
-                                _ptr(self.wind_cell), self.batch.n_cells, _ptr(self.states), self.t, T,
-                                _ptr(act), _ptr(cnt), self.seed, threads, _ptr(es), _ptr(cs))
+        lib().oracle_run_ex(ctypes.byref(self.P), n_env, self.envs, _ptr(self.g), _ptr(self.E),
+                            _ptr(self.wind_cell), self.batch.n_cells, _ptr(self.states), self.t, T,
+                            _ptr(act), _ptr(cnt), self.seed, threads, _ptr(es), _ptr(cs),
+                            int(drop_mode), int(drop_radius))
         self.t += T
         return cnt
 

@@ -342,17 +342,24 @@ float oracle_cell_prob(const oracle_params* P, const oracle_env* env, const floa
     return ignite_prob(&c, states, i, j);
 }
 
-static void apply_action(const oracle_env* e, uint8_t* F, int32_t a)
+/* A drop on the (2R+1) x (2R+1) square centred at (r, col), clipped to the  */
+/* grid: mode 0 (suppressant) makes FLAMMABLE and BURNING cells UNBURNABLE,  */
+/* mode 1 (water, section 4) makes BURNING cells BURNT.                      */
+static void apply_action(const oracle_env* e, uint8_t* F, int32_t a, int32_t mode, int32_t R)
 {
     if (a < 0) return;
     int32_t r = (a >> 16) & 0x7FFF, col = a & 0xFFFF;
     if (r >= e->H || col >= e->W) return;
-    for (int32_t i = r - 2; i <= r + 2; ++i) {
+    for (int32_t i = r - R; i <= r + R; ++i) {
         if (i < 0 || i >= e->H) continue;
-        for (int32_t j = col - 2; j <= col + 2; ++j) {
+        for (int32_t j = col - R; j <= col + R; ++j) {
             if (j < 0 || j >= e->W) continue;
             uint8_t* s = &F[e->offset + (int64_t)i * e->W + j];
-            if (*s == ST_FLAMMABLE || *s == ST_BURNING) *s = ST_UNBURNABLE;
+            if (mode == 0) {
+                if (*s == ST_FLAMMABLE || *s == ST_BURNING) *s = ST_UNBURNABLE;
+            } else {
+                if (*s == ST_BURNING) *s = ST_BURNT;
+            }
         }
     }
 }
@@ -364,7 +371,8 @@ static void apply_action(const oracle_env* e, uint8_t* F, int32_t a)
 static void run_env(const oracle_params* P, int32_t n_env, int32_t e, const oracle_env* envs,
                     const float* g, const float* E, const float* wind_cell, int64_t n_cells,
                     uint8_t* states, uint64_t t0, int32_t T, const int32_t* actions, int32_t* counts,
-                    uint64_t seed, const float* env_series, const float* cell_series)
+                    uint64_t seed, const float* env_series, const float* cell_series, int32_t drop_mode,
+                    int32_t drop_radius)
 {
     const oracle_env* env = &envs[e];
     int64_t n = (int64_t)env->H * env->W;
@@ -381,7 +389,7 @@ static void run_env(const oracle_params* P, int32_t n_env, int32_t e, const orac
             c.Vy = w[2];
         }
         if (cell_series) c.wind_cell = cell_series + (int64_t)t * 3 * n_cells;
-        if (actions) apply_action(env, F, actions[(int64_t)s * n_env + e]);
+        if (actions) apply_action(env, F, actions[(int64_t)s * n_env + e], drop_mode, drop_radius);
         int32_t burning = 0;
         for (int32_t i = 0; i < env->H; ++i) {
             for (int32_t j = 0; j < env->W; ++j) {
@@ -419,6 +427,7 @@ typedef struct {
     uint64_t seed;
     int32_t first, stride;
     const float *env_series, *cell_series;
+    int32_t drop_mode, drop_radius;
 } run_job;
 
 static void* run_worker(void* arg)
@@ -426,16 +435,18 @@ static void* run_worker(void* arg)
     run_job* j = (run_job*)arg;
     for (int32_t e = j->first; e < j->n_env; e += j->stride)
         run_env(j->P, j->n_env, e, j->envs, j->g, j->E, j->wind_cell, j->n_cells, j->states, j->t0,
-                j->T, j->actions, j->counts, j->seed, j->env_series, j->cell_series);
+                j->T, j->actions, j->counts, j->seed, j->env_series, j->cell_series, j->drop_mode,
+                j->drop_radius);
     return NULL;
 }
 
 /* Run T steps on every env.  Envs are independent, so n_threads > 1 only   */
 /* spreads whole envs over threads; each env is still stepped as above.     */
-void oracle_run_series(const oracle_params* P, int32_t n_env, const oracle_env* envs, const float* g,
-                       const float* E, const float* wind_cell, int64_t n_cells, uint8_t* states,
-                       uint64_t t0, int32_t T, const int32_t* actions, int32_t* counts, uint64_t seed,
-                       int32_t n_threads, const float* env_series, const float* cell_series)
+void oracle_run_ex(const oracle_params* P, int32_t n_env, const oracle_env* envs, const float* g,
+                   const float* E, const float* wind_cell, int64_t n_cells, uint8_t* states,
+                   uint64_t t0, int32_t T, const int32_t* actions, int32_t* counts, uint64_t seed,
+                   int32_t n_threads, const float* env_series, const float* cell_series,
+                   int32_t drop_mode, int32_t drop_radius)
 {
     if (n_threads < 1) n_threads = 1;
     if (n_threads > 256) n_threads = 256;
@@ -443,7 +454,7 @@ void oracle_run_series(const oracle_params* P, int32_t n_env, const oracle_env* 
     pthread_t th[256];
     for (int32_t i = 0; i < n_threads; ++i) {
         run_job j = {P, n_env, envs, g, E, wind_cell, n_cells, states, t0, T, actions, counts, seed, i,
-                     n_threads, env_series, cell_series};
+                     n_threads, env_series, cell_series, drop_mode, drop_radius};
         jobs[i] = j;
     }
     if (n_threads == 1) {
@@ -458,6 +469,6 @@ void oracle_run(const oracle_params* P, int32_t n_env, const oracle_env* envs, c
                 const float* E, const float* wind_cell, int64_t n_cells, uint8_t* states, uint64_t t0,
                 int32_t T, const int32_t* actions, int32_t* counts, uint64_t seed, int32_t n_threads)
 {
-    oracle_run_series(P, n_env, envs, g, E, wind_cell, n_cells, states, t0, T, actions, counts, seed,
-                      n_threads, NULL, NULL);
+    oracle_run_ex(P, n_env, envs, g, E, wind_cell, n_cells, states, t0, T, actions, counts, seed,
+                  n_threads, NULL, NULL, 0, 2);
 }

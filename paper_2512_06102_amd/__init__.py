@@ -25,7 +25,7 @@ THETA_NAMES = ("p_base", "alpha_w1", "alpha_w2", "alpha_s", "alpha_gamma", "p_co
     tuple("veg%d" % c for c in range(N_CLASSES))
 
 EXPORTED = ("sim_init", "sim_step", "sim_get_step", "sim_set_step", "sim_set_plan", "sim_get_plan",
-            "sim_autotune", "sim_set_wind_series",
+            "sim_autotune", "sim_set_wind_series", "sim_step_history", "sim_set_drop",
             "sim_relaxed_init", "sim_relaxed_workspace_bytes", "sim_step_relaxed_fwd",
             "sim_relaxed_loss", "sim_relaxed_loss_bce", "sim_step_relaxed_bwd", "sim_debug_exp", "sim_debug_philox",
             "sim_last_error", "sim_destroy")
@@ -79,6 +79,8 @@ def lib() -> ctypes.CDLL:
         L.sim_set_plan.argtypes = [P, P]
         L.sim_get_plan.argtypes = [P, P]
         L.sim_set_wind_series.argtypes = [P, P, P, I64]
+        L.sim_step_history.argtypes = [P, P, P, I32, P, P, P]
+        L.sim_set_drop.argtypes = [P, I32, I32]
         L.sim_autotune.argtypes = [P, P, I32, I32, I32, P, I32, ctypes.POINTER(I32), P]
         L.sim_relaxed_init.argtypes = [P, P, P, P]
         L.sim_relaxed_workspace_bytes.argtypes = [P, I32, I32]
@@ -251,6 +253,31 @@ class FireSim:
             S = int(ser.shape[0])
         _check(lib().sim_set_wind_series(self.handle, _ptr(env_series), _ptr(cell_series), S), self.handle)
         self._wind_series = (env_series, cell_series)
+
+    def step_history(self, T: int, actions: Optional[torch.Tensor] = None, counts: bool = False,
+                     history: Optional[torch.Tensor] = None):
+        """T steps keeping every state: returns (history [T, n_cells] uint8,
+        counts or None); the states end equal to history[T-1]."""
+        if history is None:
+            history = torch.empty((T, self.n_cells), dtype=torch.uint8, device=self.device)
+        if history.dtype != torch.uint8 or history.device != self.device or not history.is_contiguous() \
+                or tuple(history.shape) != (T, self.n_cells):
+            raise ValueError("history must be a contiguous uint8 [T, n_cells] tensor on %s" % self.device)
+        cnt = torch.empty((T, self.n_env), dtype=torch.int32, device=self.device) if counts else None
+        if actions is not None:
+            actions = actions.to(device=self.device, dtype=torch.int32).contiguous()
+            if tuple(actions.shape) != (T, self.n_env):
+                raise ValueError("actions must be [T, n_env]")
+        _check(lib().sim_step_history(self.handle, _ptr(self.states), _ptr(actions), int(T), _ptr(cnt),
+                                      _ptr(history), self._s()), self.handle)
+        return history, cnt
+
+    DROP_SUPPRESS, DROP_WATER = 0, 1
+
+    def set_drop(self, mode: int = 0, radius: int = 2):
+        """What drops do: mode 0 (suppressant) FLAMMABLE/BURNING -> UNBURNABLE,
+        mode 1 (water) BURNING -> BURNT, on (2 radius + 1)^2 cells."""
+        _check(lib().sim_set_drop(self.handle, int(mode), int(radius)), self.handle)
 
     @property
     def t(self) -> int:

@@ -28,6 +28,7 @@ struct GraphCache {
     const void* states = nullptr;
     const void* actions = nullptr;
     const void* counts = nullptr;
+    const void* history = nullptr;
     sim_plan plan{};
     bool valid = false;
 };
@@ -49,6 +50,9 @@ struct sim_handle {
     const float* series_env = nullptr;   // [series_T][n_env][3]
     const float* series_cell = nullptr;  // [series_T][3][n_cells]
     int64_t series_T = 0;
+    // drops of sim_step: mode 0 suppressant (FLAMMABLE/BURNING -> UNBURNABLE),
+    // mode 1 water (BURNING -> BURNT), square of side 2 radius + 1
+    int32_t drop_mode = 0, drop_radius = 2;
 
     EnvDev* d_envs = nullptr;
     float* d_g = nullptr;
@@ -120,6 +124,8 @@ StepArgs step_args(const sim_handle* h)
     a.inv_run_diag = (float)(1.0 / ((double)p.cell_size * std::sqrt(2.0)));
     a.key0 = (uint32_t)h->seed;
     a.key1 = (uint32_t)(h->seed >> 32);
+    a.drop_mode = h->drop_mode;
+    a.drop_radius = h->drop_radius;
     return a;
 }
 
@@ -195,33 +201,49 @@ StepLaunch step_launch(const sim_handle* h)
 }
 
 // Enqueue the T launches of one sim_step call (counts cleared first; if T is
-// odd the result is copied back from the ping-pong buffer).
+// odd the result is copied back from the ping-pong buffer).  With a history
+// buffer, step k reads row k-1 (states for k = 0) and writes row k, and the
+// last row is copied to states.  drop overrides the handle's drop setting.
 hipError_t enqueue_steps(sim_handle* h, hipStream_t s, uint8_t* states, const int32_t* actions,
-                         int32_t T, int32_t* counts)
+                         int32_t T, int32_t* counts, uint8_t* history = nullptr,
+                         const int32_t* drop = nullptr)
 {
     hipError_t e;
     if (counts) {
         e = launch_fill_i32(s, counts, (int64_t)T * h->n_env, 0);
         if (e != hipSuccess) return e;
     }
-    const StepLaunch L = step_launch(h);
+    StepLaunch L = step_launch(h);
+    if (drop) {
+        L.args.drop_mode = drop[0];
+        L.args.drop_radius = drop[1];
+    }
     const bool sparse = h->plan.sparse != 0;
     if (sparse) {  // nothing is known yet about how the two buffers compare
         e = launch_fill_i32(s, h->d_tile_eq, h->n_tiles, 0);
         if (e != hipSuccess) return e;
     }
     uint8_t* cur = states;
-    uint8_t* nxt = h->d_tmp;
+    uint8_t* nxt = history ? history : h->d_tmp;
     for (int32_t k = 0; k < T; ++k) {
         SparseArgs sp{nullptr, nullptr, nullptr, nullptr, 0};
-        if (sparse)
+        if (sparse) {
+            // a history row starts empty: an inactive tile must copy its cells
+            if (history && k > 0 && (e = launch_fill_i32(s, h->d_tile_eq, h->n_tiles, 0)) != hipSuccess)
+                return e;
             sp = SparseArgs{h->d_tile_burn + (k & 1) * h->n_tiles, h->d_tile_burn + ((k + 1) & 1) * h->n_tiles,
                             h->d_tile_eq, h->d_tile_nbr, k == 0 ? 1 : 0};
+        }
         e = launch_stoch_step(s, L, cur, nxt, h->d_t, (uint32_t)k,
                               actions ? actions + (int64_t)k * h->n_env : nullptr,
                               counts ? counts + (int64_t)k * h->n_env : nullptr, sp);
         if (e != hipSuccess) return e;
-        std::swap(cur, nxt);
+        if (history) {
+            cur = nxt;
+            nxt = history + (int64_t)(k + 1) * h->n_cells;
+        } else {
+            std::swap(cur, nxt);
+        }
     }
     if (cur != states) return launch_copy_u8(s, states, cur, h->n_cells);
     return hipSuccess;
@@ -371,8 +393,10 @@ int sim_init(sim_handle** out, const sim_params* p, int32_t n_env, const sim_env
     return SIM_OK;
 }
 
-int sim_step(sim_handle* h, uint8_t* states, const int32_t* actions, int32_t T, int32_t* counts,
-             void* stream)
+namespace {
+
+int step_common(sim_handle* h, uint8_t* states, const int32_t* actions, int32_t T, int32_t* counts,
+                uint8_t* history, void* stream)
 {
     if (!h) return fail(nullptr, SIM_EINVAL, "handle is NULL");
     if (T < 0) return fail(h, SIM_EINVAL, "T must be >= 0");
@@ -393,13 +417,13 @@ int sim_step(sim_handle* h, uint8_t* states, const int32_t* actions, int32_t T, 
     if (h->plan.graph) {
         GraphCache& G = h->graph;
         if (!(G.valid && G.T == T && G.states == states && G.actions == actions &&
-              G.counts == counts && same_plan(G.plan, h->plan))) {
+              G.counts == counts && G.history == history && same_plan(G.plan, h->plan))) {
             if (G.exec) (void)hipGraphExecDestroy(G.exec);
             G.exec = nullptr;
             G.valid = false;
             hipGraph_t graph = nullptr;
             HIP_OR_FAIL(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
-            hipError_t e = enqueue_steps(h, h->cap_stream, states, actions, T, counts);
+            hipError_t e = enqueue_steps(h, h->cap_stream, states, actions, T, counts, history);
             hipError_t e2 = hipStreamEndCapture(h->cap_stream, &graph);
             if (e != hipSuccess || e2 != hipSuccess) {
                 if (graph) (void)hipGraphDestroy(graph);
@@ -413,14 +437,41 @@ int sim_step(sim_handle* h, uint8_t* states, const int32_t* actions, int32_t T, 
             G.states = states;
             G.actions = actions;
             G.counts = counts;
+            G.history = history;
             G.plan = h->plan;
             G.valid = true;
         }
         HIP_OR_FAIL(h, hipGraphLaunch(G.exec, s));
     } else {
-        HIP_OR_FAIL(h, enqueue_steps(h, s, states, actions, T, counts));
+        HIP_OR_FAIL(h, enqueue_steps(h, s, states, actions, T, counts, history));
     }
     h->t += (uint64_t)T;
+    return SIM_OK;
+}
+
+}  // namespace
+
+int sim_step(sim_handle* h, uint8_t* states, const int32_t* actions, int32_t T, int32_t* counts,
+             void* stream)
+{
+    return step_common(h, states, actions, T, counts, nullptr, stream);
+}
+
+int sim_step_history(sim_handle* h, uint8_t* states, const int32_t* actions, int32_t T, int32_t* counts,
+                     uint8_t* history, void* stream)
+{
+    if (h && !history) return fail(h, SIM_EINVAL, "history is NULL");
+    return step_common(h, states, actions, T, counts, history, stream);
+}
+
+int sim_set_drop(sim_handle* h, int32_t mode, int32_t radius)
+{
+    if (!h) return fail(nullptr, SIM_EINVAL, "handle is NULL");
+    if (mode != SIM_DROP_SUPPRESS && mode != SIM_DROP_WATER) return fail(h, SIM_EINVAL, "unknown drop mode");
+    if (radius < 0 || radius > 255) return fail(h, SIM_EINVAL, "drop radius must be in 0..255");
+    h->drop_mode = mode;
+    h->drop_radius = radius;
+    h->graph.valid = false;  // the drop setting is a kernel argument
     return SIM_OK;
 }
 

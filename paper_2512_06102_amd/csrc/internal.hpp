@@ -22,6 +22,8 @@ struct StepArgs {
     float p_base, alpha_gamma, alpha_w1, alpha_w2, alpha_s, p_continue;
     float inv_run_orth, inv_run_diag;  // 1/cell_size, 1/(cell_size sqrt 2)
     uint32_t key0, key1;               // Philox key (seed lo, seed hi)
+    int32_t drop_mode;                 // 0: FLAMMABLE/BURNING -> UNBURNABLE, 1: BURNING -> BURNT
+    int32_t drop_radius;               // drops cover (2R+1) x (2R+1) cells
 };
 
 // Inputs of the step resident in HBM: fuel and elevation for the life of a

@@ -176,16 +176,24 @@ __device__ __forceinline__ uint32_t load_group(const uint8_t* __restrict__ env_s
     }
 }
 
-// A drop clears FLAMMABLE (1) and BURNING (2) bytes of dword w (columns
-// gj..gj+3, row gi) that lie in the 5 x 5 square centred at (ar, ac).
-__device__ __forceinline__ uint32_t apply_drop(uint32_t w, int gi, int gj, int ar, int ac)
+// A drop on the (2R+1) x (2R+1) square centred at (ar, ac): mode 0 turns
+// FLAMMABLE and BURNING cells UNBURNABLE (suppressant), mode 1 turns BURNING
+// cells BURNT (water).
+__device__ __forceinline__ uint32_t drop_cell(uint32_t s, int mode)
 {
-    if (gi < ar - 2 || gi > ar + 2) return w;
+    if (mode == 0) return (s == kFlammable || s == kBurning) ? (uint32_t)kUnburnable : s;
+    return s == kBurning ? (uint32_t)kBurnt : s;
+}
+
+// The drop on dword w (columns gj..gj+3 of row gi).
+__device__ __forceinline__ uint32_t apply_drop(uint32_t w, int gi, int gj, int ar, int ac, int R, int mode)
+{
+    if (gi < ar - R || gi > ar + R) return w;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
         const int j = gj + c;
         const uint32_t s = (w >> (8 * c)) & 0xFFu;
-        if (j >= ac - 2 && j <= ac + 2 && (s == kFlammable || s == kBurning)) w &= ~(0xFFu << (8 * c));
+        if (j >= ac - R && j <= ac + R) w = (w & ~(0xFFu << (8 * c))) | (drop_cell(s, mode) << (8 * c));
     }
     return w;
 }
@@ -234,8 +242,9 @@ __global__ __launch_bounds__(kWave) void stoch_step_kernel(
         const int32_t a0 = actions_row ? actions_row[td.env] : -1;
         if (!active && a0 >= 0) {
             const int ar = (a0 >> 16) & 0x7FFF, ac = a0 & 0xFFFF;
-            active = ar < H && ac < W && ar + 2 >= td.r0 - 1 && ar - 2 <= td.r0 + TH &&
-                     ac + 2 >= td.c0 - 1 && ac - 2 <= td.c0 + td.width;
+            const int R = A.drop_radius;
+            active = ar < H && ac < W && ar + R >= td.r0 - 1 && ar - R <= td.r0 + TH &&
+                     ac + R >= td.c0 - 1 && ac - R <= td.c0 + td.width;
         }
         if (!active) {
             if (SP.eq[tile] == 0) {  // the other buffer is stale on this tile: copy it over
@@ -332,13 +341,14 @@ __global__ __launch_bounds__(kWave) void stoch_step_kernel(
     if (act >= 0) {
         const int ar = (act >> 16) & 0x7FFF, ac = act & 0xFFFF;
         if (ar < H && ac < W) {
+            const int R = A.drop_radius, mode = A.drop_mode;
 #pragma unroll
             for (int j = 0; j < RT + 2; ++j) {
                 const int gi = row0 - 1 + j;
-                s[j] = apply_drop(s[j], gi, gj0, ar, ac);
-                if (gi >= ar - 2 && gi <= ar + 2) {
-                    if (cl >= ac - 2 && cl <= ac + 2 && (hl[j] == kFlammable || hl[j] == kBurning)) hl[j] = 0;
-                    if (cr >= ac - 2 && cr <= ac + 2 && (hr[j] == kFlammable || hr[j] == kBurning)) hr[j] = 0;
+                s[j] = apply_drop(s[j], gi, gj0, ar, ac, R, mode);
+                if (gi >= ar - R && gi <= ar + R) {
+                    if (cl >= ac - R && cl <= ac + R) hl[j] = drop_cell(hl[j], mode);
+                    if (cr >= ac - R && cr <= ac + R) hr[j] = drop_cell(hr[j], mode);
                 }
             }
         }

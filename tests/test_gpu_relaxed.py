@@ -239,26 +239,26 @@ def _window(batch, e, r0, r1, c0, c1):
 
 
 def test_relaxed2048_launch_config():
-    """One 2048 x 2048 env with per-cell wind (the benchmark's large relaxed
-    workload) in the benchmark's launch configuration.
+    """One 2048 x 2048 env with per-cell wind, T = 100, checkpoints every 10
+    (the benchmark's large relaxed workload, same launch configuration).
 
-    T = 64: U_T and B_T on windows around the ignitions and at random
-    centres against the fp64 oracle run on the window alone (a cell's state
+    U_T and B_T on windows around the ignitions, at random centres and at a
+    corner against the fp64 oracle run on the window alone (a cell's state
     after T steps depends only on cells within Chebyshev distance T, so cells
-    at least T from every cut edge are exact).  T = 500: properties that hold
-    at any size (U non-increasing from U_0, U + B <= 1, unburnable cells at
-    zero, the gradient unchanged by the checkpoint interval, and a central
-    difference of the loss along the gradient)."""
-    batch, params, T_full, k = firegen.workload_relaxed_large()
+    at least T from every cut edge are exact); then properties that hold at
+    any size: U non-increasing from U_0, U + B <= 1, unburnable cells at zero,
+    the gradient unchanged by the checkpoint interval, and a central
+    difference of the loss along the gradient."""
+    batch, params, T, k = firegen.workload_relaxed_large()
     H, W = int(batch.H[0]), int(batch.W[0])
-    T, M = 64, 72
+    M = T + 8
     params = params.replace(p_base=params.p_base * 1.2, alpha_s=params.alpha_s * 1.2)
-    Y = np.zeros(batch.n_cells, np.uint8)
-    U, B, _, _ = _gpu_loss_grad(batch, params, Y, T, k)
-    U, B = U.reshape(H, W), B.reshape(H, W)
+    Y = _target(batch, params, 60, 2)
+    U, B, loss, g = _gpu_loss_grad(batch, params, Y, T, k)
+    U2, B2 = U.reshape(H, W), B.reshape(H, W)
     rng = np.random.default_rng(17)
-    centres = [(int(r[1]), int(r[2])) for r in batch.ignitions[:4]]
-    centres += [(int(rng.integers(H)), int(rng.integers(W))) for _ in range(2)] + [(3, W - 5)]
+    centres = [(int(r[1]), int(r[2])) for r in batch.ignitions[:3]]
+    centres += [(int(rng.integers(H)), int(rng.integers(W))), (3, W - 5)]
     for ci, cj in centres:
         r0, r1, c0, c1 = max(0, ci - M), min(H, ci + M + 1), max(0, cj - M), min(W, cj + M + 1)
         win = _window(batch, 0, r0, r1, c0, c1)
@@ -268,19 +268,18 @@ def test_relaxed2048_launch_config():
         a0, a1 = (T if r0 > 0 else 0), (r1 - r0) - (T if r1 < H else 0)
         b0, b1 = (T if c0 > 0 else 0), (c1 - c0) - (T if c1 < W else 0)
         assert a1 > a0 and b1 > b0
-        gu = U[r0:r1, c0:c1][a0:a1, b0:b1]
-        gb = B[r0:r1, c0:c1][a0:a1, b0:b1]
+        gu = U2[r0:r1, c0:c1][a0:a1, b0:b1]
+        gb = B2[r0:r1, c0:c1][a0:a1, b0:b1]
         assert np.max(np.abs(gu - Us[-1][a0:a1, b0:b1])) <= 1e-5, (ci, cj)
         assert np.max(np.abs(gb - Bs[-1][a0:a1, b0:b1])) <= 1e-5, (ci, cj)
 
-    Yf = _target(batch, params, 60, 2)
-    U, B, loss, g = _gpu_loss_grad(batch, params, Yf, T_full, k)
     U0, _, burnable = relaxed64.initial_state(batch, 0)
     U0 = U0.ravel()
     assert np.all(U <= U0 + 1e-15) and np.all(U + B <= 1 + 1e-12)
     assert np.all(U[~burnable.ravel()] == 0) and np.all(B[~burnable.ravel()] == 0)
     assert 0.0 < float(loss[0]) < 1.0
-    _, _, _, g25 = _gpu_loss_grad(batch, params, Yf, T_full, 25)
+    assert np.all(np.isfinite(g))
+    _, _, _, g25 = _gpu_loss_grad(batch, params, Y, T, 25)
     assert np.allclose(g, g25, rtol=1e-6, atol=1e-9 * np.max(np.abs(g)))
     # directional derivative along the normalised gradient (fp64 state, h 1e-3)
     theta = _theta32(params)
@@ -292,6 +291,6 @@ def test_relaxed2048_launch_config():
         th = theta + sgn * h * d
         p = params.replace(p_base=th[0], alpha_w1=th[1], alpha_w2=th[2], alpha_s=th[3],
                            alpha_gamma=th[4], p_continue=th[5], veg=tuple(th[6:]))
-        Ls.append(float(_gpu_loss_grad(batch, p, Yf, T_full, k)[2][0]))
+        Ls.append(float(_gpu_loss_grad(batch, p, Y, T, k)[2][0]))
     fd = (Ls[0] - Ls[1]) / (2 * h)
     assert abs(fd - float(g @ d)) <= 2e-2 * abs(float(g @ d)), (fd, float(g @ d))

@@ -381,3 +381,56 @@ def test_wind_series_argument_checks():
     sim.set_wind_series(cell_series=cell)
     sim.step(4)
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("mode,radius", [(1, 0), (1, 2), (1, 5), (0, 1), (0, 4)])
+def test_drop_modes_and_radii(mode, radius):
+    """Water (BURNING -> BURNT) and suppressant drops of several radii, with
+    drops in every env at every step: bit-exact against the oracle, in a
+    graph and in the sparse plan."""
+    batch = firegen.landscape_batch(23, [(128, 128), (60, 200), (33, 47)])
+    params = firegen.Params(p_base=0.9, veg=_veg(23))
+    T = 30
+    act = firegen.random_actions(7, batch, T, p_none=0.3)
+    ref = oracle.Sim(batch, params, seed=4)
+    want = ref.step(T, actions=act, counts=True, threads=6, drop_mode=mode, drop_radius=radius)
+    for plan in (dict(graph=1), dict(graph=0, tile_width=64, tile_rows=8, skip_static=1, sparse=1)):
+        sim = fs.FireSim.from_batch(batch, params, seed=4)
+        sim.set_plan(**plan)
+        sim.set_drop(mode, radius)
+        got = sim.step(T, actions=torch.from_numpy(act), counts=True).cpu().numpy()
+        torch.cuda.synchronize()
+        assert np.array_equal(sim.states.cpu().numpy(), ref.states), plan
+        assert np.array_equal(got, want), plan
+    with pytest.raises(fs.SimError):
+        sim.set_drop(2, 1)
+    with pytest.raises(fs.SimError):
+        sim.set_drop(1, -1)
+
+
+@pytest.mark.parametrize("plan", [dict(graph=1), dict(graph=0, sparse=1, skip_static=1, tile_width=64)])
+def test_history_rows_are_every_step(plan):
+    """sim_step_history: row k is the state after step k, bit-exact, for a
+    call that starts mid-run, with drops; the states end at the last row."""
+    batch = firegen.landscape_batch(24, [(96, 96), (40, 130)])
+    params = firegen.Params(p_base=0.8, veg=_veg(24))
+    act = firegen.random_actions(8, batch, 25, p_none=0.5)
+    ref = oracle.Sim(batch, params, seed=6)
+    ref.step(5, actions=act[:5])
+    rows, want_c = ref.step(20, actions=act[5:], counts=True, history=True)
+    sim = fs.FireSim.from_batch(batch, params, seed=6)
+    sim.set_plan(**plan)
+    sim.step(5, actions=torch.from_numpy(act[:5]))
+    for rep in range(2):   # the second call starts from a saved row, at step 10
+        if rep:
+            sim.states.copy_(torch.from_numpy(hist0[4]))
+            sim.t = 10
+            rows, want_c = rows[5:], want_c[5:]
+            hist, cnt = sim.step_history(15, actions=torch.from_numpy(act[10:]), counts=True)
+        else:
+            hist, cnt = sim.step_history(20, actions=torch.from_numpy(act[5:]), counts=True)
+            hist0 = hist.cpu().numpy()
+        torch.cuda.synchronize()
+        assert np.array_equal(hist.cpu().numpy(), rows)
+        assert np.array_equal(cnt.cpu().numpy(), want_c)
+        assert np.array_equal(sim.states.cpu().numpy(), rows[-1])

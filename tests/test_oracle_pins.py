@@ -466,3 +466,38 @@ def test_wind_series_is_indexed_by_absolute_step():
     assert np.array_equal(c.states, ref2.states)
     with pytest.raises(ValueError):
         oracle.Sim(b, prm).step(T + 1, wind_env_series=ser)
+
+
+# ------------------------------------------------------------- drop modes --
+@pytest.mark.parametrize("radius", [0, 1, 3])
+def test_water_drop_extinguishes_square_before_the_step(radius):
+    """Water (mode 1) turns the BURNING cells of the (2R+1)^2 square BURNT
+    before the transition: with p = 1 spread and p_continue = 1, cells outside
+    the square keep burning and spread, the square's burning cells are BURNT,
+    its flammable cells stay flammable unless a burning cell outside the
+    square touches them; the suppressant (mode 0) makes the square's
+    flammable and burning cells UNBURNABLE."""
+    n = 15
+    b = firegen.uniform_batch(n, n, ignitions=())
+    prm = firegen.Params(p_base=64.0, p_continue=1.0)
+    ii, jj = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    F0 = np.where((ii + jj) % 3 == 0, firegen.BURNING, firegen.FLAMMABLE).astype(np.uint8)
+    F0[0, :] = firegen.BURNT
+    r, c = 7, 6
+    inside = (abs(ii - r) <= radius) & (abs(jj - c) <= radius)
+    for mode in (1, 0):
+        s = oracle.Sim(b, prm)
+        s.states[:] = F0.ravel()
+        s.step(1, actions=np.array([[(r << 16) | c]], np.int32), drop_mode=mode, drop_radius=radius)
+        F1 = s.states.reshape(n, n)
+        Fd = F0.copy()
+        if mode == 1:
+            Fd[inside & (F0 == firegen.BURNING)] = firegen.BURNT
+        else:
+            Fd[inside & ((F0 == firegen.BURNING) | (F0 == firegen.FLAMMABLE))] = firegen.UNBURNABLE
+        burn = np.pad(Fd == firegen.BURNING, 1)
+        nb = sum(burn[1 + di:1 + di + n, 1 + dj:1 + dj + n] for di in (-1, 0, 1) for dj in (-1, 0, 1)
+                 if di or dj)
+        want = Fd.copy()
+        want[(Fd == firegen.FLAMMABLE) & (nb > 0)] = firegen.BURNING
+        assert np.array_equal(F1, want), (mode, radius)
