@@ -157,6 +157,68 @@ int sim_step_history(sim_handle* h, uint8_t* states, const int32_t* actions, int
 #define SIM_DROP_WATER 1
 int sim_set_drop(sim_handle* h, int32_t mode, int32_t radius);
 
+/* ---- Reinforcement-learning layer (section 4, the air-tanker scenario) ----
+ * One agent per env flies over the grid, sees an egocentric window of the
+ * fire, and can open a valve to drop water, which turns the BURNING cells
+ * of a square footprint BURNT.  A step costs burn_penalty per BURNING cell
+ * after it; the step that leaves no BURNING cell earns extinguish_bonus and
+ * ends the episode, as does reaching max_steps.  Episodes start from one
+ * random ignition and a random agent position (sim_rl_reset). */
+typedef struct {
+    int32_t obs_radius;      /* observation window (2R+1)^2, R in 0..31 */
+    int32_t drop_radius;     /* water footprint (2r+1)^2, r in 0..255 */
+    int32_t water_capacity;  /* drops per episode, >= 0 */
+    int32_t max_steps;       /* episode length, >= 1 */
+    float burn_penalty;      /* reward -= burn_penalty * (BURNING cells) */
+    float extinguish_bonus;  /* reward += bonus on the step that puts the fire out */
+} sim_rl_config;
+
+/* Per-env agent state, device memory, 32 bytes. */
+typedef struct {
+    int32_t row, col;    /* position */
+    int32_t water;       /* drops left */
+    int32_t steps;       /* steps taken this episode */
+    int32_t done;        /* 1 once the episode is over; the agent then stays idle */
+    int32_t last_count;  /* BURNING cells after the last step */
+    int32_t pad[2];
+} sim_rl_agent;
+
+/* Observation codes: the four cell states, and 4 for cells beyond the grid. */
+#define SIM_OBS_OUTSIDE 4
+
+/* sim_rl_reset -- start new episodes in the envs with reset_mask[e] != 0
+ * (device int32[n_env]; NULL resets every env).  Each such env's states
+ * become FLAMMABLE (UNBURNABLE where the land cover is unburnable), one
+ * ignition is drawn uniformly over the grid (the first of 8 draws that lands
+ * on a burnable cell; none burns if all 8 miss), the agent is placed
+ * uniformly at random with water_capacity drops, steps = done = 0.  The
+ * draws are Philox4x32-10 with the handle's key and counter (env_id,
+ * episode lo, episode hi, 0x80000000 | attempt): row = (word0 * H) >> 32,
+ * col = (word1 * W) >> 32 for the ignition, words 2 and 3 of attempt 0 for
+ * the agent.  obs (device uint8[n_env][(2R+1)^2], row-major window centred
+ * on the agent) is written for every env; reset envs get done = 0 in
+ * done_out (device int32[n_env] or NULL). */
+int sim_rl_reset(sim_handle* h, const sim_rl_config* cfg, uint8_t* states, sim_rl_agent* agents,
+                 const int32_t* reset_mask, uint64_t episode, uint8_t* obs, int32_t* done_out, void* stream);
+
+/* sim_rl_step -- one RL step of every env.
+ *  actions  device int32[n_env]: bits 0-3 move (0 stay, 1..8 one cell in
+ *           direction k = move-1 of the paper's eight directions, k = 0
+ *           east, counter-clockwise; clipped to the grid), bit 4 opens the
+ *           valve: one drop of water at the agent's new position if water is
+ *           left.  Values outside 0..31 or moves above 8 act as 0.
+ *  Then one stochastic step (sim_step semantics, drops in water mode of
+ *  radius drop_radius), the handle's step counter advancing by 1.
+ *  reward   device float[n_env]: -burn_penalty * count (+ extinguish_bonus
+ *           when count == 0), count = BURNING cells after the step, in fp32;
+ *           0 for envs whose episode was already over.
+ *  done     device int32[n_env]: episode over after this step.
+ *  obs      as in sim_rl_reset, after the step.
+ * Envs whose episode is over still step (their fire keeps its course) until
+ * they are reset. */
+int sim_rl_step(sim_handle* h, const sim_rl_config* cfg, uint8_t* states, sim_rl_agent* agents,
+                const int32_t* actions, uint8_t* obs, float* reward, int32_t* done, void* stream);
+
 /* Step counter: get it, or set it to resume a saved run (states saved by
  * the caller, same handle inputs and seed). */
 int sim_get_step(const sim_handle* h, uint64_t* t);

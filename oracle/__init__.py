@@ -11,6 +11,9 @@ with the HIP implementation.
   adjoint in float64 numpy.
 * `enumerate_exact.py`: exact Markov-chain marginals of the stochastic
   process on tiny grids, from the fp64 closed form of Eq. 4.
+* `rl.py`: the reinforcement-learning layer of section 4 (air-tanker agent,
+  water drops, reward, egocentric observations, random resets) in plain
+  Python over the stochastic-step oracle.
 """
 from __future__ import annotations
 

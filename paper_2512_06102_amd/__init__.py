@@ -26,6 +26,7 @@ THETA_NAMES = ("p_base", "alpha_w1", "alpha_w2", "alpha_s", "alpha_gamma", "p_co
 
 EXPORTED = ("sim_init", "sim_step", "sim_get_step", "sim_set_step", "sim_set_plan", "sim_get_plan",
             "sim_autotune", "sim_set_wind_series", "sim_step_history", "sim_set_drop",
+            "sim_rl_reset", "sim_rl_step",
             "sim_relaxed_init", "sim_relaxed_workspace_bytes", "sim_step_relaxed_fwd",
             "sim_relaxed_loss", "sim_relaxed_loss_bce", "sim_step_relaxed_bwd", "sim_debug_exp", "sim_debug_philox",
             "sim_last_error", "sim_destroy")
@@ -81,6 +82,8 @@ def lib() -> ctypes.CDLL:
         L.sim_set_wind_series.argtypes = [P, P, P, I64]
         L.sim_step_history.argtypes = [P, P, P, I32, P, P, P]
         L.sim_set_drop.argtypes = [P, I32, I32]
+        L.sim_rl_reset.argtypes = [P, P, P, P, P, U64, P, P, P]
+        L.sim_rl_step.argtypes = [P, P, P, P, P, P, P, P, P]
         L.sim_autotune.argtypes = [P, P, I32, I32, I32, P, I32, ctypes.POINTER(I32), P]
         L.sim_relaxed_init.argtypes = [P, P, P, P]
         L.sim_relaxed_workspace_bytes.argtypes = [P, I32, I32]
@@ -363,6 +366,54 @@ class FireSim:
                                           int(T), int(ckpt_every), _form(form), _ptr(ws), ws.numel(),
                                           _ptr(grad), self._s()), self.handle)
         return grad
+
+
+class SimRlConfig(ctypes.Structure):
+    _fields_ = [("obs_radius", ctypes.c_int32), ("drop_radius", ctypes.c_int32),
+                ("water_capacity", ctypes.c_int32), ("max_steps", ctypes.c_int32),
+                ("burn_penalty", ctypes.c_float), ("extinguish_bonus", ctypes.c_float)]
+
+
+class RLEnv:
+    """The air-tanker scenario over a FireSim: one agent per env, egocentric
+    observations, water drops (BURNING -> BURNT), reward -burn_penalty x
+    burning cells and +extinguish_bonus when the fire is out.  Every part of
+    reset and step runs in the library's kernels on the simulator's stream.
+
+    Actions: int32 [n_env], bits 0-3 move (0 stay, 1..8 direction k = move-1,
+    k = 0 east, counter-clockwise), bit 4 opens the valve.  Agents: int32
+    [n_env, 8] (row, col, water, steps, done, last_count, pad, pad)."""
+
+    def __init__(self, sim: "FireSim", obs_radius: int = 2, drop_radius: int = 1, water_capacity: int = 10,
+                 max_steps: int = 100, burn_penalty: float = 0.1, extinguish_bonus: float = 10.0):
+        self.sim = sim
+        self.cfg = SimRlConfig(obs_radius, drop_radius, water_capacity, max_steps, burn_penalty,
+                               extinguish_bonus)
+        dev = sim.device
+        side = 2 * obs_radius + 1
+        self.agents = torch.zeros((sim.n_env, 8), dtype=torch.int32, device=dev)
+        self.obs = torch.empty((sim.n_env, side * side), dtype=torch.uint8, device=dev)
+        self.reward = torch.zeros(sim.n_env, dtype=torch.float32, device=dev)
+        self.done = torch.zeros(sim.n_env, dtype=torch.int32, device=dev)
+
+    def reset(self, episode: int, mask: Optional[torch.Tensor] = None):
+        if mask is not None:
+            mask = mask.to(device=self.sim.device, dtype=torch.int32).contiguous()
+            if tuple(mask.shape) != (self.sim.n_env,):
+                raise ValueError("mask must be [n_env]")
+        _check(lib().sim_rl_reset(self.sim.handle, ctypes.byref(self.cfg), _ptr(self.sim.states),
+                                  _ptr(self.agents), _ptr(mask), int(episode), _ptr(self.obs),
+                                  _ptr(self.done), self.sim._s()), self.sim.handle)
+        return self.obs, self.done
+
+    def step(self, actions: torch.Tensor):
+        actions = actions.to(device=self.sim.device, dtype=torch.int32).contiguous()
+        if tuple(actions.shape) != (self.sim.n_env,):
+            raise ValueError("actions must be [n_env]")
+        _check(lib().sim_rl_step(self.sim.handle, ctypes.byref(self.cfg), _ptr(self.sim.states),
+                                 _ptr(self.agents), _ptr(actions), _ptr(self.obs), _ptr(self.reward),
+                                 _ptr(self.done), self.sim._s()), self.sim.handle)
+        return self.obs, self.reward, self.done
 
 
 class RelaxedCalibrationLoss(torch.autograd.Function):

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "../../include/firesim.h"
+#include "rl.hpp"
 #include "internal.hpp"
 #include "relaxed.hpp"
 
@@ -53,6 +54,9 @@ struct sim_handle {
     // drops of sim_step: mode 0 suppressant (FLAMMABLE/BURNING -> UNBURNABLE),
     // mode 1 water (BURNING -> BURNT), square of side 2 radius + 1
     int32_t drop_mode = 0, drop_radius = 2;
+    // reinforcement-learning layer: drop row and burning counts of one step
+    int32_t* d_rl_drop = nullptr;
+    int32_t* d_rl_counts = nullptr;
 
     EnvDev* d_envs = nullptr;
     float* d_g = nullptr;
@@ -102,7 +106,8 @@ int fail(sim_handle* h, int code, const char* fmt, ...)
 void free_all(sim_handle* h)
 {
     void* ptrs[] = {h->d_envs, h->d_g, h->d_E, h->d_cls, h->d_den, h->d_wind, h->d_init_states,
-                    h->d_tmp, h->d_t, h->d_tiles, h->d_tile_nbr, h->d_tile_burn, h->d_tile_eq};
+                    h->d_tmp, h->d_t, h->d_tiles, h->d_tile_nbr, h->d_tile_burn, h->d_tile_eq,
+                    h->d_rl_drop, h->d_rl_counts};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (h->graph.exec) (void)hipGraphExecDestroy(h->graph.exec);
@@ -462,6 +467,73 @@ int sim_step_history(sim_handle* h, uint8_t* states, const int32_t* actions, int
 {
     if (h && !history) return fail(h, SIM_EINVAL, "history is NULL");
     return step_common(h, states, actions, T, counts, history, stream);
+}
+
+static_assert(sizeof(sim_rl_agent) == sizeof(RlAgent), "agent layout");
+
+namespace {
+
+int rl_check(sim_handle* h, const sim_rl_config* cfg, const void* states, const void* agents, const void* obs)
+{
+    if (!h) return fail(nullptr, SIM_EINVAL, "handle is NULL");
+    if (!cfg || !states || !agents || !obs) return fail(h, SIM_EINVAL, "cfg, states, agents and obs are required");
+    if (cfg->obs_radius < 0 || cfg->obs_radius > 31) return fail(h, SIM_EINVAL, "obs_radius must be in 0..31");
+    if (cfg->drop_radius < 0 || cfg->drop_radius > 255) return fail(h, SIM_EINVAL, "drop_radius must be in 0..255");
+    if (cfg->water_capacity < 0) return fail(h, SIM_EINVAL, "water_capacity must be >= 0");
+    if (cfg->max_steps < 1) return fail(h, SIM_EINVAL, "max_steps must be >= 1");
+    if (!h->d_rl_drop) {
+        if (hipMalloc(&h->d_rl_drop, (size_t)h->n_env * sizeof(int32_t)) != hipSuccess ||
+            hipMalloc(&h->d_rl_counts, (size_t)h->n_env * sizeof(int32_t)) != hipSuccess)
+            return fail(h, SIM_ENOMEM, "RL buffers allocation failed");
+    }
+    return SIM_OK;
+}
+
+RlConfigDev rl_dev(const sim_rl_config* cfg)
+{
+    return RlConfigDev{cfg->obs_radius, cfg->max_steps, cfg->burn_penalty, cfg->extinguish_bonus};
+}
+
+}  // namespace
+
+int sim_rl_reset(sim_handle* h, const sim_rl_config* cfg, uint8_t* states, sim_rl_agent* agents,
+                 const int32_t* reset_mask, uint64_t episode, uint8_t* obs, int32_t* done_out, void* stream)
+{
+    int rc = rl_check(h, cfg, states, agents, obs);
+    if (rc != SIM_OK) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    RlAgent* ag = reinterpret_cast<RlAgent*>(agents);
+    HIP_OR_FAIL(h, launch_rl_reset(s, h->d_envs, h->n_env, h->d_cls, h->params.unburnable_mask, states, ag,
+                                   reset_mask, (uint32_t)h->seed, (uint32_t)(h->seed >> 32), episode,
+                                   cfg->water_capacity));
+    HIP_OR_FAIL(h, launch_rl_obs(s, h->d_envs, h->n_env, states, ag, nullptr, rl_dev(cfg), obs, nullptr,
+                                 done_out));
+    return SIM_OK;
+}
+
+int sim_rl_step(sim_handle* h, const sim_rl_config* cfg, uint8_t* states, sim_rl_agent* agents,
+                const int32_t* actions, uint8_t* obs, float* reward, int32_t* done, void* stream)
+{
+    int rc = rl_check(h, cfg, states, agents, obs);
+    if (rc != SIM_OK) return rc;
+    if (!actions || !reward || !done) return fail(h, SIM_EINVAL, "actions, reward and done are required");
+    if (h->t + 1 > 0xFFFFFFFFull) return fail(h, SIM_ESTATE, "step counter would pass 2^32");
+    if ((h->series_env || h->series_cell) && h->t + 1 > (uint64_t)h->series_T)
+        return fail(h, SIM_EINVAL, "the wind series does not cover step %llu", (unsigned long long)h->t);
+    hipStream_t s = (hipStream_t)stream;
+    if (h->tiles_rt != h->plan.tile_rows || h->tiles_tw != h->plan.tile_width) {
+        if ((rc = build_tiles(h, h->plan.tile_rows, h->plan.tile_width)) != SIM_OK) return rc;
+        h->graph.valid = false;
+    }
+    RlAgent* ag = reinterpret_cast<RlAgent*>(agents);
+    const int32_t water[2] = {SIM_DROP_WATER, cfg->drop_radius};
+    HIP_OR_FAIL(h, launch_set_u32(s, h->d_t, (uint32_t)h->t));
+    HIP_OR_FAIL(h, launch_rl_act(s, h->d_envs, h->n_env, ag, actions, h->d_rl_drop));
+    HIP_OR_FAIL(h, enqueue_steps(h, s, states, h->d_rl_drop, 1, h->d_rl_counts, nullptr, water));
+    HIP_OR_FAIL(h, launch_rl_obs(s, h->d_envs, h->n_env, states, ag, h->d_rl_counts, rl_dev(cfg), obs, reward,
+                                 done));
+    h->t += 1;
+    return SIM_OK;
 }
 
 int sim_set_drop(sim_handle* h, int32_t mode, int32_t radius)
