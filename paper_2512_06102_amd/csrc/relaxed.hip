@@ -79,6 +79,42 @@ __device__ __forceinline__ float one_minus_exp_neg(float y)
     return 1.0f - hexp(-y);
 }
 
+// q = 1 - e^{-y} as above and the survival e^{-y}: 1 - q below y = 1/16
+// (where e^{-y} > 0.94, so the subtraction loses nothing), else from the
+// one exponential.
+__device__ __forceinline__ float2 q_and_survival(float y)
+{
+    const float qs = y * (1.0f - y * (0.5f - y * ((float)(1.0 / 6.0) - y * ((float)(1.0 / 24.0) - y * (float)(1.0 / 120.0)))));
+    const float el = hexp(-y);
+    return y < 0.0625f ? make_float2(qs, 1.0f - qs) : make_float2(1.0f - el, el);
+}
+
+// Sums of 17 values over the 64 lanes of a wave, written to out[0..16].
+// Recursive halving: at the exchange with lane ^ 32 the lower half keeps the
+// sums of values 0-7 and the upper half those of 8-15, and so on down to one
+// value per lane at lane ^ 4; lanes ^ 2 and ^ 1 finish it.  Lane l then
+// holds value 8 b5 + 4 b4 + 2 b3 + b2 (bits of l).  Value 16 is summed on
+// its own.  17 + 6 exchanges instead of 17 x 6.
+__device__ __forceinline__ void wave_sum17(const double (&a)[17], int lane, double* out)
+{
+    double b8[8], b4[4], b2[2];
+    const bool h5 = lane & 32, h4 = lane & 16, h3 = lane & 8, h2 = lane & 4;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) b8[j] = (h5 ? a[8 + j] : a[j]) + __shfl_xor(h5 ? a[j] : a[8 + j], 32);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) b4[j] = (h4 ? b8[4 + j] : b8[j]) + __shfl_xor(h4 ? b8[j] : b8[4 + j], 16);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) b2[j] = (h3 ? b4[2 + j] : b4[j]) + __shfl_xor(h3 ? b4[j] : b4[2 + j], 8);
+    double b1 = (h2 ? b2[1] : b2[0]) + __shfl_xor(h2 ? b2[0] : b2[1], 4);
+    b1 += __shfl_xor(b1, 2);
+    b1 += __shfl_xor(b1, 1);
+    double last = a[16];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) last += __shfl_xor(last, off);
+    if ((lane & 3) == 0) out[((lane >> 5) & 1) * 8 + ((lane >> 4) & 1) * 4 + ((lane >> 3) & 1) * 2 + ((lane >> 2) & 1)] = b1;
+    if (lane == 0) out[16] = last;
+}
+
 constexpr int TW = kRelaxTW, TH = kRelaxTH;  // forward tile
 constexpr int BW = kRelaxBW, BH = kRelaxBH;  // adjoint tile
 
@@ -275,8 +311,9 @@ __global__ __launch_bounds__(256) void relaxed_bwd_kernel(
                 ph[k] = A.p_base * sg[s] * ex[k];
                 if constexpr (FORM == 0) {
                     const float y = gam * ph[k];
-                    q[k] = one_minus_exp_neg(y);
-                    em[k] = hexp(-y);
+                    const float2 qe = q_and_survival(y);
+                    q[k] = qe.x;
+                    em[k] = qe.y;
                 }
             }
         }
@@ -368,17 +405,7 @@ __global__ __launch_bounds__(256) void relaxed_bwd_kernel(
     }
 
     // workgroup reduction of the 17 partial sums, then one fp64 stripe
-#pragma unroll
-    for (int j = 0; j < 17; ++j) {
-        double x = acc[j];
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
-        acc[j] = x;
-    }
-    if ((tid & 63) == 0) {
-#pragma unroll
-        for (int j = 0; j < 17; ++j) sred[tid >> 6][j] = acc[j];
-    }
+    wave_sum17(acc, tid & 63, sred[tid >> 6]);
     __syncthreads();
     if (tid < 17) {
         const double total = sred[0][tid] + sred[1][tid] + sred[2][tid] + sred[3][tid];
