@@ -229,7 +229,14 @@ int sim_set_step(sim_handle* h, uint64_t t);
  *               0 = default (4)
  *  tile_width   widest tile in cells (64, 128 or 256; narrower envs use the
  *               largest width not above W rounded up), 0 = default (256)
- *  temporal     steps fused per tile load (1 = one step per launch), 0 = default
+ *  temporal     steps per launch (1, 2, 4 or 8; 0 = default 1).  Above 1 each
+ *               256-lane workgroup loads a tile_width x 32 tile of states
+ *               with a halo of `temporal` cells into LDS, advances it that
+ *               many steps there and stores the tile; fuel and elevation are
+ *               read only at front cells.  Needs W % 4 == 0 in every env,
+ *               tile_width 64 or 128 and sparse 0 (else SIM_EINVAL);
+ *               tile_rows and skip_static are then unused.  sim_step_history
+ *               runs such plans one step per launch.
  *  skip_static  1: only cells with a burning neighbour read fuel and
  *               elevation; 0: every cell reads its 10 bytes every step
  *  sparse       1: after the first step of a call, a tile with no burning
@@ -245,7 +252,9 @@ int sim_set_plan(sim_handle* h, const sim_plan* plan);
 int sim_get_plan(const sim_handle* h, sim_plan* plan);
 
 /* Autotuner: times every candidate plan (tile_rows 1/2/4/8 x tile_width
- * 64/256, with skip_static 0 and, if allow_skip, 1; sparse = allow_sparse)
+ * 64/256, with skip_static 0 and, if allow_skip, 1; sparse = allow_sparse;
+ * and, if allow_skip and every env has W % 4 == 0, temporal 2/4/8 x
+ * tile_width 64/128)
  * for T_probe steps of this batch starting from `states` (device, read only)
  * at the handle's step counter, and makes the fastest the handle's plan
  * (graph flag kept).

@@ -314,7 +314,7 @@ class FireSim:
         for i in range(n.value):
             p = res[i].plan
             out.append(({"tile_rows": p.tile_rows, "tile_width": p.tile_width,
-                         "skip_static": p.skip_static, "sparse": p.sparse},
+                         "skip_static": p.skip_static, "sparse": p.sparse, "temporal": p.temporal},
                         float(res[i].ms_per_step)))
         return out
 

@@ -143,14 +143,17 @@ int tile_width_for(int W, int max_width)
 
 // Tile list: env-major, then row band, then column band; with each tile's 8
 // neighbouring tiles (same env) for the sparse plan.
+// rt > 0: one-step tiles (one wave64: 256 / width lane rows of rt rows, width
+// narrowed for narrow envs); rt < 0: temporal-blocking tiles of max_width x
+// kTbTileRows for every env.
 int build_tiles(sim_handle* h, int rt, int max_width)
 {
     std::vector<TileDesc> tiles;
     std::vector<int32_t> nbr;
     for (int32_t e = 0; e < h->n_env; ++e) {
         const int H = h->envs[e].H, W = h->envs[e].W;
-        const int width = tile_width_for(W, max_width);
-        const int th = (256 / width) * rt;  // one wave64 per tile: 256 / width lane rows of rt rows
+        const int width = rt < 0 ? max_width : tile_width_for(W, max_width);
+        const int th = rt < 0 ? kTbTileRows : (256 / width) * rt;
         const int nr = (H + th - 1) / th, nc = (W + width - 1) / width;
         const int32_t first = (int32_t)tiles.size();
         for (int i = 0; i < nr; ++i)
@@ -181,6 +184,17 @@ int build_tiles(sim_handle* h, int rt, int max_width)
     h->tiles_rt = rt;
     h->tiles_tw = max_width;
     return SIM_OK;
+}
+
+int tiles_key(const sim_handle* h) { return h->plan.temporal > 1 ? -1 : h->plan.tile_rows; }
+
+// Rebuild the tile list if the plan changed its geometry.
+int ensure_tiles(sim_handle* h)
+{
+    if (h->tiles_rt == tiles_key(h) && h->tiles_tw == h->plan.tile_width) return SIM_OK;
+    const int rc = build_tiles(h, tiles_key(h), h->plan.tile_width);
+    h->graph.valid = false;
+    return rc;
 }
 
 StepLaunch step_launch(const sim_handle* h)
@@ -230,6 +244,26 @@ hipError_t enqueue_steps(sim_handle* h, hipStream_t s, uint8_t* states, const in
     }
     uint8_t* cur = states;
     uint8_t* nxt = history ? history : h->d_tmp;
+    if (h->plan.temporal > 1) {
+        // temporal blocking: K steps per launch (one per launch with a history)
+        const int K = h->plan.temporal;
+        for (int32_t k = 0; k < T;) {
+            const int32_t ks = history ? 1 : std::min<int32_t>(K, T - k);
+            e = launch_stoch_tb(s, L, K, h->plan.tile_width, cur, nxt, h->d_t, (uint32_t)k, ks,
+                                actions ? actions + (int64_t)k * h->n_env : nullptr,
+                                counts ? counts + (int64_t)k * h->n_env : nullptr);
+            if (e != hipSuccess) return e;
+            k += ks;
+            if (history) {
+                cur = nxt;
+                nxt = history + (int64_t)k * h->n_cells;
+            } else {
+                std::swap(cur, nxt);
+            }
+        }
+        if (cur != states) return launch_copy_u8(s, states, cur, h->n_cells);
+        return hipSuccess;
+    }
     for (int32_t k = 0; k < T; ++k) {
         SparseArgs sp{nullptr, nullptr, nullptr, nullptr, 0};
         if (sparse) {
@@ -269,7 +303,14 @@ int validate_plan(sim_handle* h, sim_plan& p)
         return fail(h, SIM_EINVAL, "tile_rows must be 1, 2, 4 or 8");
     if (!(p.tile_width == 64 || p.tile_width == 128 || p.tile_width == 256))
         return fail(h, SIM_EINVAL, "tile_width must be 64, 128 or 256");
-    if (p.temporal != 1) return fail(h, SIM_EINVAL, "temporal must be 1");
+    if (!(p.temporal == 1 || p.temporal == 2 || p.temporal == 4 || p.temporal == 8))
+        return fail(h, SIM_EINVAL, "temporal must be 1, 2, 4 or 8");
+    if (p.temporal > 1) {
+        if (!h->aligned) return fail(h, SIM_EINVAL, "temporal blocking needs W %% 4 == 0 in every env");
+        if (p.sparse) return fail(h, SIM_EINVAL, "temporal blocking and the sparse plan do not combine");
+        if (p.tile_width != 64 && p.tile_width != 128)
+            return fail(h, SIM_EINVAL, "temporal blocking takes tile_width 64 or 128");
+    }
     if (p.skip_static != 0 && p.skip_static != 1) return fail(h, SIM_EINVAL, "skip_static must be 0 or 1");
     if (p.sparse != 0 && p.sparse != 1) return fail(h, SIM_EINVAL, "sparse must be 0 or 1");
     if (p.graph != 0 && p.graph != 1) return fail(h, SIM_EINVAL, "graph must be 0 or 1");
@@ -389,7 +430,7 @@ int sim_init(sim_handle** out, const sim_params* p, int32_t n_env, const sim_env
         fail(h, SIM_EHIP, "initialisation kernels failed: %s", hipGetErrorString(e));
         return bail(SIM_EHIP);
     }
-    if ((rc = build_tiles(h, h->plan.tile_rows, h->plan.tile_width)) != SIM_OK) return bail(rc);
+    if ((rc = build_tiles(h, tiles_key(h), h->plan.tile_width)) != SIM_OK) return bail(rc);
     if (hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess) {
         fail(h, SIM_EHIP, "stream creation failed");
         return bail(SIM_EHIP);
@@ -413,10 +454,9 @@ int step_common(sim_handle* h, uint8_t* states, const int32_t* actions, int32_t 
         return fail(h, SIM_EINVAL, "the wind series covers steps 0..%lld, the call needs up to step %llu",
                     (long long)h->series_T - 1, (unsigned long long)(h->t + T - 1));
     hipStream_t s = (hipStream_t)stream;
-    if (h->tiles_rt != h->plan.tile_rows || h->tiles_tw != h->plan.tile_width) {
-        const int rc = build_tiles(h, h->plan.tile_rows, h->plan.tile_width);
+    {
+        const int rc = ensure_tiles(h);
         if (rc != SIM_OK) return rc;
-        h->graph.valid = false;
     }
     HIP_OR_FAIL(h, launch_set_u32(s, h->d_t, (uint32_t)h->t));
     if (h->plan.graph) {
@@ -521,10 +561,7 @@ int sim_rl_step(sim_handle* h, const sim_rl_config* cfg, uint8_t* states, sim_rl
     if ((h->series_env || h->series_cell) && h->t + 1 > (uint64_t)h->series_T)
         return fail(h, SIM_EINVAL, "the wind series does not cover step %llu", (unsigned long long)h->t);
     hipStream_t s = (hipStream_t)stream;
-    if (h->tiles_rt != h->plan.tile_rows || h->tiles_tw != h->plan.tile_width) {
-        if ((rc = build_tiles(h, h->plan.tile_rows, h->plan.tile_width)) != SIM_OK) return rc;
-        h->graph.valid = false;
-    }
+    if ((rc = ensure_tiles(h)) != SIM_OK) return rc;
     RlAgent* ag = reinterpret_cast<RlAgent*>(agents);
     const int32_t water[2] = {SIM_DROP_WATER, cfg->drop_radius};
     HIP_OR_FAIL(h, launch_set_u32(s, h->d_t, (uint32_t)h->t));
@@ -614,12 +651,18 @@ int sim_autotune(sim_handle* h, const uint8_t* states, int32_t T_probe, int32_t 
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
         rc = fail(h, SIM_EHIP, "event creation failed");
     }
-    for (int skip = 0; rc == SIM_OK && skip <= (allow_skip ? 1 : 0); ++skip)
+    std::vector<sim_plan> cands;
+    for (int skip = 0; skip <= (allow_skip ? 1 : 0); ++skip)
         for (int width : {64, 256})
-            for (int rows : {1, 2, 4, 8}) {
+            for (int rows : {1, 2, 4, 8}) cands.push_back(sim_plan{rows, width, 1, skip, allow_sparse ? 1 : 0, 0});
+    if (allow_skip && h->aligned)  // temporal blocking reads fuel and elevation only at fronts, like skip
+        for (int width : {64, 128})
+            for (int k : {2, 4, 8}) cands.push_back(sim_plan{4, width, k, 1, 0, 0});
+    for (const sim_plan& cand : cands) {
+        {
                 if (rc != SIM_OK) break;
-                h->plan = sim_plan{rows, width, 1, skip, allow_sparse ? 1 : 0, 0};
-                if ((rc = build_tiles(h, rows, width)) != SIM_OK) break;
+                h->plan = cand;
+                if ((rc = ensure_tiles(h)) != SIM_OK) break;
                 hipError_t e = hipSuccess;
                 float best = 0.0f;
                 for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {  // first pass warms up
@@ -636,7 +679,8 @@ int sim_autotune(sim_handle* h, const uint8_t* states, int32_t T_probe, int32_t 
                     break;
                 }
                 tried.push_back(sim_tune_result{h->plan, best / (float)T_probe});
-            }
+        }
+    }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     (void)hipFree(work);
@@ -648,7 +692,7 @@ int sim_autotune(sim_handle* h, const uint8_t* states, int32_t T_probe, int32_t 
         h->plan.graph = saved.graph;
     }
     h->graph.valid = false;
-    const int built = build_tiles(h, h->plan.tile_rows, h->plan.tile_width);
+    const int built = ensure_tiles(h);
     if (rc == SIM_OK) rc = built;
     const int n = std::min<int>((int)tried.size(), max_results);
     for (int i = 0; i < n; ++i) results[i] = tried[i];

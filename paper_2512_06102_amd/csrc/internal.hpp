@@ -92,6 +92,13 @@ struct SparseArgs {
 hipError_t launch_stoch_step(hipStream_t s, const StepLaunch& L, const uint8_t* src,
                              uint8_t* dst, const uint32_t* t_base, uint32_t step,
                              const int32_t* actions_row, int32_t* counts_row, const SparseArgs& sp);
+// ksteps (<= K, K in {2, 4, 8}) steps from src to dst in one launch over
+// tiles of tile_width (64 or 128) x 32 cells; actions and counts point at the
+// rows of step step0 (or are NULL).  Requires W % 4 == 0 in every env.
+constexpr int kTbTileRows = 32;
+hipError_t launch_stoch_tb(hipStream_t s, const StepLaunch& L, int K, int tile_width, const uint8_t* src,
+                           uint8_t* dst, const uint32_t* t_base, uint32_t step0, int32_t ksteps,
+                           const int32_t* actions, int32_t* counts);
 hipError_t launch_set_u32(hipStream_t s, uint32_t* p, uint32_t v);
 
 hipError_t launch_debug_exp(hipStream_t s, const float* x, float* y, int64_t n);

@@ -590,6 +590,260 @@ __global__ void debug_philox_kernel(const uint32_t* ctr, const uint32_t* key, ui
     }
 }
 
+// ---------------------------------------------------------------------------
+// Temporal blocking: `ksteps` (<= K) steps per launch.  A 256-lane workgroup
+// loads the state of its tile (TWD dwords x kTbRows rows of one env) with a
+// halo of K rows and HX dwords (>= K cells) into LDS once, advances the whole
+// region ksteps times in LDS, and stores only the tile.  After s steps the
+// cells within s of the region border are stale (their neighbours were not
+// loaded); each step computes the dwords that are still valid, so the tile
+// itself is exact after K steps.  Draws, drops, counts and the arithmetic are
+// those of the one-step kernel (same counters, same operation order), so the
+// results are bit-identical; fuel and elevation are read only where a front
+// cell needs them.  Envs must have W % 4 == 0.
+constexpr int kTbRows = kTbTileRows;
+constexpr int kTbListCap = 1024;  // listed front cells per tile and step
+
+template <bool WIND_CELL, int TWD, int K>
+__global__ __launch_bounds__(256) void stoch_tb_kernel(
+    const TileDesc* __restrict__ tiles, int32_t n_tiles, int32_t tiles_per_xcd,
+    const EnvDev* __restrict__ envs, StaticFields F0, StepArgs A, const uint8_t* __restrict__ src,
+    uint8_t* __restrict__ dst, const uint32_t* __restrict__ t_base, uint32_t step0, int32_t ksteps,
+    const int32_t* __restrict__ actions, int32_t* __restrict__ counts, int32_t n_env)
+{
+    constexpr int HX = (K + 3) / 4;        // halo in dwords
+    constexpr int RWD = TWD + 2 * HX;      // region width in dwords
+    constexpr int RW = 4 * RWD;            // ... in cells
+    constexpr int RH = kTbRows + 2 * K;    // region rows
+    constexpr int G = 256 / RWD;           // row strips: lane (g, cd) walks strip g of column cd
+    __shared__ uint32_t buf[2][RH * RWD];
+    __shared__ float lds_ew[2][8];
+    // Row activity, rotating over three slots (written during step j, read
+    // during step j + 1, cleared during step j + 2): bit r of burn_rows says
+    // row r may hold a burning cell; bit r of diff_rows says the two buffers
+    // may differ on row r.  A row with no burning cell within one row cannot
+    // change, so it is skipped (copied if the buffers differ).
+    __shared__ unsigned long long burn_rows[3], diff_rows[3];
+    // Front cells of the step, listed so that their neighbour loads are
+    // issued by all lanes together: row | column dword << 6 | cell << 12 |
+    // burning-neighbour mask << 14, with the cell's uniform.  A full list
+    // leaves further cells to their lane.
+    __shared__ uint32_t list_key[kTbListCap];
+    __shared__ float list_u[kTbListCap];
+    __shared__ int32_t n_list[3];
+
+    const int b = blockIdx.x;
+    const int tile = (b & 7) * tiles_per_xcd + (b >> 3);
+    if (tile >= n_tiles) return;
+    const TileDesc td = tiles[tile];
+    const EnvDev ed = envs[td.env];
+    const int H = ed.H, W = ed.W, Wd = W >> 2;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int r0 = td.r0 - K, d0 = (td.c0 >> 2) - HX;  // region origin (row, dword column)
+    const int64_t base = ed.offset;
+    const uint32_t* src32 = reinterpret_cast<const uint32_t*>(src + base);
+    uint32_t* dst32 = reinterpret_cast<uint32_t*>(dst + base);
+    const uint2 key = make_uint2(A.key0, A.key1);
+    const int cd = tid % RWD, grp = tid / RWD;  // this lane's column and row strip
+    const int gj = 4 * (d0 + cd);
+    const bool col_in = gj >= 0 && gj < W;
+    const bool col_tile = cd >= HX && cd < HX + TWD;
+
+    if (tid < 3) {
+        burn_rows[tid] = 0ull;
+        diff_rows[tid] = tid == 0 ? ~0ull : 0ull;  // the second buffer holds nothing yet
+        n_list[tid] = 0;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < RH * RWD; idx += 256) {
+        const int gi = r0 + idx / RWD, gd = d0 + idx % RWD;
+        const uint32_t w = (gi >= 0 && gi < H && gd >= 0 && gd < Wd) ? src32[(int64_t)gi * Wd + gd] : 0u;
+        buf[0][idx] = w;
+        if (burning_flags(w)) atomicOr(&burn_rows[0], 1ull << (idx / RWD));
+    }
+
+    for (int j = 0; j < ksteps; ++j) {
+        const uint32_t t = *t_base + step0 + (uint32_t)j;
+        StaticFields F = F0;
+        if (F0.wind_stride != 0) F.wind = F0.wind + (int64_t)t * F0.wind_stride;
+        uint32_t* cur = buf[j & 1];
+        uint32_t* nxt = buf[(j + 1) & 1];
+        float* ew = lds_ew[j & 1];  // double-buffered: the previous step may still read the other
+        if constexpr (!WIND_CELL) {
+            if (tid < 8) {
+                float V = ed.V, Vx = ed.Vx, Vy = ed.Vy;
+                if (F.env_wind) {
+                    const float* w = F.env_wind + ((int64_t)t * F.n_env + td.env) * 3;
+                    V = w[0];
+                    Vx = w[1];
+                    Vy = w[2];
+                }
+                ew[tid] = wind_exponent(tid, A.alpha_w1, A.alpha_w2, V, Vx, Vy);
+            }
+        }
+        const int32_t act = actions ? actions[(int64_t)j * n_env + td.env] : -1;
+        const int sc = j % 3, sn = (j + 1) % 3, sz = (j + 2) % 3;
+        __syncthreads();  // region loaded / previous step complete; wind exponents visible
+        unsigned long long bmask = burn_rows[sc], dmask = diff_rows[sc];
+        if (tid == 0) {
+            burn_rows[sz] = 0ull;
+            diff_rows[sz] = 0ull;
+            n_list[sn] = 0;  // the counter of the next step (last read two steps ago)
+        }
+        if (act >= 0) {
+            const int ar = (act >> 16) & 0x7FFF, ac = act & 0xFFFF;
+            if (ar < H && ac < W) {
+                // rows the drop may change differ from the other buffer afterwards
+                for (int r = max(ar - A.drop_radius - r0, 0); r <= min(ar + A.drop_radius - r0, RH - 1); ++r)
+                    dmask |= 1ull << r;
+                // the dwords of the square inside the region
+                const int R = A.drop_radius;
+                const int ya = max(ar - R - r0, 0), yb = min(ar + R - r0, RH - 1);
+                const int xa = max(ac - R - 4 * d0, 0), xb = min(ac + R - 4 * d0, RW - 1);
+                if (ya <= yb && xa <= xb) {
+                    const int da = xa >> 2, nw = (xb >> 2) - da + 1;
+                    for (int q = tid; q < (yb - ya + 1) * nw; q += 256) {
+                        const int rr = ya + q / nw, cdq = da + q % nw;
+                        cur[rr * RWD + cdq] =
+                            apply_drop(cur[rr * RWD + cdq], r0 + rr, 4 * (d0 + cdq), ar, ac, R, A.drop_mode);
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        // dwords still valid after this step: rows [s, RH - s), cells [s, RW - s), s = j + 1
+        const int s1 = j + 1;
+        const int row_lo = s1, nrows = RH - 2 * s1;
+        const int per = (nrows + G - 1) / G;
+        const int ra = row_lo + grp * per, rb = min(ra + per, row_lo + nrows);
+        const unsigned long long active = bmask | (bmask << 1) | (bmask >> 1);
+        unsigned long long my_burn = 0ull, my_diff = 0ull;
+        int cnt = 0;
+        if (grp < G && cd >= (s1 >> 2) && cd <= ((RW - s1 - 1) >> 2) && ra < rb) {
+            const bool hasl = cd > 0, hasr = cd < RWD - 1;
+            auto window = [&](int rr, uint32_t& own) {
+                const uint32_t* r = cur + rr * RWD;
+                own = r[cd];
+                return row_window(hasl ? r[cd - 1] : 0u, own, hasr ? r[cd + 1] : 0u);
+            };
+            uint32_t own_up, own = 0u, own_dn, up6 = 0u, md6 = 0u;
+            bool have = false;  // up6 / md6 / own hold rows rr - 1 and rr
+            for (int rr = ra; rr < rb; ++rr) {
+                if (!((active >> rr) & 1ull)) {  // no burning cell within one row: unchanged
+                    if ((dmask >> rr) & 1ull) nxt[rr * RWD + cd] = cur[rr * RWD + cd];
+                    have = false;
+                    continue;
+                }
+                if (!have) {
+                    up6 = window(rr - 1, own_up);
+                    md6 = window(rr, own);
+                }
+                const uint32_t dn6 = window(rr + 1, own_dn);
+                const uint32_t ud = up6 | dn6;
+                const uint32_t near = (ud | (ud >> 1) | (ud >> 2) | md6 | (md6 >> 2)) & 0xFu;
+                const uint32_t burn = pack4(burning_flags(own));
+                const uint32_t front = pack4(flammable_flags(own)) & near;
+                uint32_t out = own;
+                const int gi = r0 + rr;
+                if ((burn | front) && col_in && gi >= 0 && gi < H) {
+                    const int64_t n0 = (int64_t)gi * W + gj;
+                    const uint4 w = group_words<true>(n0, t, ed.env_id, key);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        const float u = word_to_uniform(compu(w, c));
+                        uint32_t next;
+                        if ((burn >> c) & 1u) {
+                            next = u < A.p_continue ? kBurning : kBurnt;
+                        } else if ((front >> c) & 1u) {
+                            const uint32_t nbk = direction_mask(up6, md6, dn6, c);
+                            const int slot = atomicAdd(&n_list[sc], 1);
+                            if (slot < kTbListCap) {  // decided below, with the other listed cells
+                                list_key[slot] = (uint32_t)rr | ((uint32_t)cd << 6) | ((uint32_t)c << 12) | (nbk << 14);
+                                list_u[slot] = u;
+                                continue;
+                            }
+                            next = u < ignite_prob<WIND_CELL>(nbk, base + n0 + c, W, F, A, ew) ? kBurning
+                                                                                                : kFlammable;
+                        } else {
+                            continue;
+                        }
+                        out = (out & ~(0xFFu << (8 * c))) | (next << (8 * c));
+                    }
+                }
+                nxt[rr * RWD + cd] = out;
+                const uint32_t bo = burning_flags(out);
+                if (bo) my_burn |= 1ull << rr;
+                if (out != own) my_diff |= 1ull << rr;  // every valid dword of the row is rewritten
+                if (col_tile && rr >= K && rr < K + kTbRows && gi < H) cnt += __popc(pack4(bo));
+                up6 = md6;
+                md6 = dn6;
+                own = own_dn;
+                have = true;
+            }
+        }
+        __syncthreads();  // list complete, non-listed cells written
+        {
+            const int n = min(n_list[sc], kTbListCap);
+            uint8_t* nxt8 = reinterpret_cast<uint8_t*>(nxt);
+            for (int q = tid; q < n; q += 256) {
+                const uint32_t e = list_key[q];
+                const int rr = e & 63, cdq = (e >> 6) & 63, c = (e >> 12) & 3;
+                const uint32_t nbk = e >> 14;
+                const int gi = r0 + rr, gjc = 4 * (d0 + cdq) + c;
+                if (list_u[q] < ignite_prob<WIND_CELL>(nbk, base + (int64_t)gi * W + gjc, W, F, A, ew)) {
+                    nxt8[(rr * RWD + cdq) * 4 + c] = kBurning;
+                    my_burn |= 1ull << rr;
+                    my_diff |= 1ull << rr;
+                    if (cdq >= HX && cdq < HX + TWD && rr >= K && rr < K + kTbRows && gi < H) ++cnt;
+                }
+            }
+        }
+        // row masks of the next step, OR-reduced over the wave first
+#pragma unroll
+        for (int o2 = 32; o2 > 0; o2 >>= 1) {
+            my_burn |= __shfl_xor(my_burn, o2);
+            my_diff |= __shfl_xor(my_diff, o2);
+        }
+        if (lane == 0) {
+            if (my_burn) atomicOr(&burn_rows[sn], my_burn);
+            if (my_diff) atomicOr(&diff_rows[sn], my_diff);
+        }
+        if (counts) {
+#pragma unroll
+            for (int o2 = 32; o2 > 0; o2 >>= 1) cnt += __shfl_xor(cnt, o2);
+            if (lane == 0 && cnt) atomicAdd(counts + (int64_t)j * n_env + td.env, cnt);
+        }
+    }
+    __syncthreads();
+    const uint32_t* fin = buf[ksteps & 1];
+    for (int idx = tid; idx < kTbRows * TWD; idx += 256) {
+        const int rr = K + idx / TWD, cdo = HX + idx % TWD;
+        const int gi = r0 + rr, gd = d0 + cdo;
+        if (gi < H && gd < Wd) dst32[(int64_t)gi * Wd + gd] = fin[rr * RWD + cdo];
+    }
+}
+
+template <bool WC, int TWD, int K>
+hipError_t launch_tb(hipStream_t s, const StepLaunch& L, const uint8_t* src, uint8_t* dst, const uint32_t* t_base,
+                     uint32_t step0, int32_t ksteps, const int32_t* act, int32_t* cnt)
+{
+    const int32_t per_xcd = (L.n_tiles + 7) / 8;
+    hipLaunchKernelGGL((stoch_tb_kernel<WC, TWD, K>), dim3(8 * per_xcd), dim3(256), 0, s, L.tiles, L.n_tiles,
+                       per_xcd, L.envs, L.fields, L.args, src, dst, t_base, step0, ksteps, act, cnt, L.n_env);
+    return hipGetLastError();
+}
+
+template <bool WC, int TWD>
+hipError_t launch_tb_k(hipStream_t s, const StepLaunch& L, int K, const uint8_t* src, uint8_t* dst,
+                       const uint32_t* t_base, uint32_t step0, int32_t ksteps, const int32_t* act, int32_t* cnt)
+{
+    switch (K) {
+    case 2: return launch_tb<WC, TWD, 2>(s, L, src, dst, t_base, step0, ksteps, act, cnt);
+    case 4: return launch_tb<WC, TWD, 4>(s, L, src, dst, t_base, step0, ksteps, act, cnt);
+    default: return launch_tb<WC, TWD, 8>(s, L, src, dst, t_base, step0, ksteps, act, cnt);
+    }
+}
+
 int grid_for(int64_t n, int block)
 {
     int64_t g = (n + block - 1) / block;
@@ -646,6 +900,18 @@ hipError_t launch_stoch_step(hipStream_t s, const StepLaunch& L, const uint8_t* 
     return L.skip_static
                ? launch_rt<false, false, true>(s, L, src, dst, t_base, step, actions_row, counts_row, sp)
                : launch_rt<false, false, false>(s, L, src, dst, t_base, step, actions_row, counts_row, sp);
+}
+
+hipError_t launch_stoch_tb(hipStream_t s, const StepLaunch& L, int K, int tile_width, const uint8_t* src,
+                           uint8_t* dst, const uint32_t* t_base, uint32_t step0, int32_t ksteps,
+                           const int32_t* actions, int32_t* counts)
+{
+    const bool wc = L.fields.wind != nullptr;
+    if (tile_width == 64)
+        return wc ? launch_tb_k<true, 16>(s, L, K, src, dst, t_base, step0, ksteps, actions, counts)
+                  : launch_tb_k<false, 16>(s, L, K, src, dst, t_base, step0, ksteps, actions, counts);
+    return wc ? launch_tb_k<true, 32>(s, L, K, src, dst, t_base, step0, ksteps, actions, counts)
+              : launch_tb_k<false, 32>(s, L, K, src, dst, t_base, step0, ksteps, actions, counts);
 }
 
 hipError_t launch_init_cells(hipStream_t s, int64_t n, const uint8_t* cls, const float* den,

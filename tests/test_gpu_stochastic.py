@@ -308,11 +308,13 @@ def test_autotune_keeps_state_and_results():
     res = sim.autotune(T_probe=4)
     torch.cuda.synchronize()
     assert torch.equal(sim.states, before) and sim.t == 7
-    assert len(res) == 16 and all(res[i][1] <= res[i + 1][1] for i in range(15))
+    # 16 one-step plans + 6 temporal-blocking plans (every width is a multiple of 4)
+    assert len(res) == 22 and all(res[i][1] <= res[i + 1][1] for i in range(21))
+    assert sum(r[0]["temporal"] > 1 for r in res) == 6
     best = res[0][0]
     plan = sim.plan()
-    assert (plan["tile_rows"], plan["tile_width"], plan["skip_static"]) == \
-        (best["tile_rows"], best["tile_width"], best["skip_static"])
+    keys = ("tile_width", "temporal") if best["temporal"] > 1 else ("tile_rows", "tile_width", "skip_static")
+    assert all(plan[k] == best[k] for k in keys), (plan, best)
     sim.step(13)
     ref = oracle.Sim(batch, params, seed=21)
     ref.step(20, threads=8)
@@ -434,3 +436,73 @@ def test_history_rows_are_every_step(plan):
         assert np.array_equal(hist.cpu().numpy(), rows)
         assert np.array_equal(cnt.cpu().numpy(), want_c)
         assert np.array_equal(sim.states.cpu().numpy(), rows[-1])
+
+
+@pytest.mark.parametrize("temporal", [2, 4, 8])
+@pytest.mark.parametrize("tile_width", [64, 128])
+def test_temporal_blocking(temporal, tile_width):
+    """Several steps per launch with the state tile in LDS: bit-exact against
+    the oracle with drops, counts, a T that is not a multiple of the depth,
+    split calls, graph replay and envs narrower, wider and shorter than a
+    tile."""
+    batch = firegen.landscape_batch(51, [(128, 128), (64, 200), (36, 52), (300, 20), (8, 8), (97, 132)])
+    params = firegen.Params(p_base=0.85, veg=_veg(51))
+    T = 23
+    act = firegen.random_actions(12, batch, T, p_none=0.4)
+    ref = oracle.Sim(batch, params, seed=17)
+    want = ref.step(T, actions=act, counts=True, threads=6)
+    for graph in (1, 0):
+        sim = fs.FireSim.from_batch(batch, params, seed=17)
+        sim.set_plan(tile_width=tile_width, temporal=temporal, graph=graph)
+        c1 = sim.step(9, actions=torch.from_numpy(act[:9]), counts=True).cpu().numpy()
+        c2 = sim.step(T - 9, actions=torch.from_numpy(act[9:]), counts=True).cpu().numpy()
+        torch.cuda.synchronize()
+        assert np.array_equal(sim.states.cpu().numpy(), ref.states), graph
+        assert np.array_equal(np.concatenate([c1, c2]), want), graph
+        assert sim.plan()["temporal"] == temporal
+
+
+@pytest.mark.parametrize("per_cell", [False, True])
+def test_temporal_blocking_with_wind_series_water_and_history(per_cell):
+    batch = firegen.landscape_batch(52, [(128, 128), (60, 200)], per_cell_wind=per_cell)
+    params = firegen.Params(p_base=0.9, veg=_veg(52))
+    T = 19
+    ser = firegen.wind_series(6, batch, T, per_cell=per_cell, speed_step=1.0, turn_step=0.3)
+    kw = {"wind_cell_series" if per_cell else "wind_env_series": ser}
+    act = firegen.random_actions(13, batch, T, p_none=0.3)
+    ref = oracle.Sim(batch, params, seed=5)
+    rows, want = ref.step(T, actions=act, counts=True, threads=6, drop_mode=1, drop_radius=3, history=True,
+                          **kw)
+    sim = fs.FireSim.from_batch(batch, params, seed=5)
+    sim.set_plan(tile_width=128, temporal=8, graph=1)
+    sim.set_drop(1, 3)
+    dev = torch.from_numpy(ser).cuda()
+    sim.set_wind_series(cell_series=dev) if per_cell else sim.set_wind_series(env_series=dev)
+    got = sim.step(T, actions=torch.from_numpy(act), counts=True).cpu().numpy()
+    torch.cuda.synchronize()
+    assert np.array_equal(sim.states.cpu().numpy(), ref.states)
+    assert np.array_equal(got, want)
+    sim2 = fs.FireSim.from_batch(batch, params, seed=5)
+    sim2.set_plan(tile_width=64, temporal=4)
+    sim2.set_drop(1, 3)
+    sim2.set_wind_series(cell_series=dev) if per_cell else sim2.set_wind_series(env_series=dev)
+    hist, cnt = sim2.step_history(T, actions=torch.from_numpy(act), counts=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(hist.cpu().numpy(), rows)
+    assert np.array_equal(cnt.cpu().numpy(), want)
+
+
+def test_temporal_blocking_rejections():
+    ragged = firegen.landscape_batch(53, [(40, 42)])
+    sim = fs.FireSim.from_batch(ragged, firegen.Params(), seed=0)
+    with pytest.raises(fs.SimError):
+        sim.set_plan(temporal=4, tile_width=64)
+    batch = firegen.landscape_batch(54, [(64, 64)])
+    sim = fs.FireSim.from_batch(batch, firegen.Params(), seed=0)
+    for kw in (dict(temporal=3, tile_width=64), dict(temporal=4, tile_width=256),
+               dict(temporal=4, tile_width=64, sparse=1)):
+        with pytest.raises(fs.SimError):
+            sim.set_plan(**kw)
+    sim.set_plan(temporal=2, tile_width=64)
+    sim.step(3)
+    torch.cuda.synchronize()
