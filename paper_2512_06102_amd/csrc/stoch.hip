@@ -164,7 +164,7 @@ __device__ __forceinline__ uint32_t load_group(const uint8_t* __restrict__ env_s
                                                int W)
 {
     if (gi < 0 || gi >= H || gj >= W) return 0u;
-    const uint8_t* p = env_src + (int64_t)gi * W + gj;
+    const uint8_t* p = env_src + (uint32_t)(gi * W + gj);  // envs hold < 2^30 cells
     if constexpr (ALIGNED) {
         return *reinterpret_cast<const uint32_t*>(p);
     } else {
@@ -273,15 +273,27 @@ __global__ __launch_bounds__(kWave) void stoch_step_kernel(
     // -- 1. loads: RT own dwords plus the one above and below; halo bytes at
     //       the segment ends; fuel and elevation of own cells (dense plan)
     uint32_t s[RT + 2], hl[RT + 2], hr[RT + 2];
+    if constexpr (ALIGNED) {
+        // branch-free: every lane loads from a clamped in-grid address and
+        // zeroes what lies off the grid (W % 4 == 0, so W >= 4)
+        const int gjc = min(gj0, W - 4);
 #pragma unroll
-    for (int j = 0; j < RT + 2; ++j) s[j] = load_group<ALIGNED>(env_src, row0 - 1 + j, gj0, H, W);
+        for (int j = 0; j < RT + 2; ++j) {
+            const int gi = row0 - 1 + j, gic = min(max(gi, 0), H - 1);
+            const uint32_t w = *reinterpret_cast<const uint32_t*>(env_src + (uint32_t)(gic * W + gjc));
+            s[j] = (gi >= 0 && gi < H && gj0 < W) ? w : 0u;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < RT + 2; ++j) s[j] = load_group<ALIGNED>(env_src, row0 - 1 + j, gj0, H, W);
+    }
     const int cl = td.c0 - 1, cr = td.c0 + td.width;
 #pragma unroll
     for (int j = 0; j < RT + 2; ++j) {
         const int gi = row0 - 1 + j;
         const bool row_in = gi >= 0 && gi < H;
-        hl[j] = (tx == 0 && row_in && cl >= 0) ? (uint32_t)env_src[(int64_t)gi * W + cl] : 0u;
-        hr[j] = (tx == GX - 1 && row_in && cr < W) ? (uint32_t)env_src[(int64_t)gi * W + cr] : 0u;
+        hl[j] = (tx == 0 && row_in && cl >= 0) ? (uint32_t)env_src[(uint32_t)(gi * W + cl)] : 0u;
+        hr[j] = (tx == GX - 1 && row_in && cr < W) ? (uint32_t)env_src[(uint32_t)(gi * W + cr)] : 0u;
     }
     float4 gv[RT], ev[RT];
 #pragma unroll
@@ -290,15 +302,20 @@ __global__ __launch_bounds__(kWave) void stoch_step_kernel(
         ev[m] = gv[m];
         if constexpr (!SKIP) {
             const int gi = row0 + m;
-            if (gi < H && gj0 < W) {
+            if (ALIGNED || (gi < H && gj0 < W)) {
                 const int64_t c0 = base + (int64_t)gi * W + gj0;
                 if constexpr (ALIGNED) {
-                    gv[m] = *reinterpret_cast<const float4*>(F.g + c0);
-                    ev[m] = *reinterpret_cast<const float4*>(F.E + c0);
+                    // uniform env bases plus 32-bit byte offsets (envs hold < 2^30
+                    // cells), clamped into the grid so that no lane branches
+                    const uint32_t bo = 4u * (uint32_t)(min(gi, H - 1) * W + min(gj0, W - 4));
+                    gv[m] = *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(F.g + base) + bo);
+                    ev[m] = *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(F.E + base) + bo);
                     if constexpr (WIND_CELL) {
-                        keep_loaded(*reinterpret_cast<const float4*>(F.wind + c0));
-                        keep_loaded(*reinterpret_cast<const float4*>(F.wind + F.n_cells + c0));
-                        keep_loaded(*reinterpret_cast<const float4*>(F.wind + 2 * F.n_cells + c0));
+                        keep_loaded(*reinterpret_cast<const float4*>(reinterpret_cast<const char*>(F.wind + base) + bo));
+                        keep_loaded(*reinterpret_cast<const float4*>(
+                            reinterpret_cast<const char*>(F.wind + F.n_cells + base) + bo));
+                        keep_loaded(*reinterpret_cast<const float4*>(
+                            reinterpret_cast<const char*>(F.wind + 2 * F.n_cells + base) + bo));
                     }
                 } else {
                     float tg[4] = {0.f, 0.f, 0.f, 0.f}, te[4] = {0.f, 0.f, 0.f, 0.f};
@@ -483,7 +500,7 @@ __global__ __launch_bounds__(kWave) void stoch_step_kernel(
                 }
             }
         }
-        uint8_t* o = dst + base + (int64_t)gi * W + gj0;
+        uint8_t* o = (dst + base) + (uint32_t)(gi * W + gj0);
         if constexpr (ALIGNED) {
             *reinterpret_cast<uint32_t*>(o) = out;
         } else {
