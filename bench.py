@@ -250,6 +250,67 @@ def bench_dense_front(args, torch, fs, firegen, st):
                          "hbm_GBs_at_10B": round(STOCH_BYTES_PER_CELL * cells / (launch_ms / 1e3) / 1e9, 1)}}
 
 
+def bench_paper_config(args, torch, fs, firegen):
+    """The paper's vectorised-throughput setting: 64 envs of 64 x 64, 200
+    steps, timed with the dense plan and with the autotuner's choice."""
+    import numpy as np
+
+    batch = firegen.landscape_batch(7, [(64, 64)] * 64)
+    params = firegen.Params(veg=tuple(float(v) for v in firegen.veg_table(np.random.default_rng(7))))
+    sim = fs.FireSim.from_batch(batch, params, seed=0)
+    init = sim.states.clone()
+    stream = torch.cuda.current_stream()
+    T = 200
+    out = {"workload": "64 envs x 64x64, 200 steps (the paper's vmap throughput setting)"}
+    sim.set_plan(tile_rows=4, tile_width=256, temporal=1, skip_static=0, sparse=0, graph=1)
+    ms, _ = timed_runs(torch, stream, sim, init, T, args.steps, 2)
+    out["dense"] = {"ms_per_200_steps": round(ms, 4), "env_steps_per_s": 64 * T / (ms / 1e3)}
+    sim.states.copy_(init)
+    sim.t = 0
+    sim.autotune(T_probe=T, allow_skip=True, allow_sparse=True)
+    best = sim.plan()
+    keys = ("tile_rows", "tile_width", "temporal", "skip_static", "sparse")
+    sim.set_plan(**{k: best[k] for k in keys}, graph=1)
+    ms, _ = timed_runs(torch, stream, sim, init, T, args.steps, 2)
+    out["autotuned"] = {"plan": {k: best[k] for k in keys}, "ms_per_200_steps": round(ms, 4),
+                        "env_steps_per_s": 64 * T / (ms / 1e3)}
+    out["unit"] = "env-steps/s"
+    out["note"] = ("context only: the paper quotes its peak on an NVIDIA A100 in a garbled form; "
+                   "its literal reading is 2.5^16 = 2.3e6 env-steps/s")
+    log("[bench] paper setting 64 x 64^2: dense %.3f ms, autotuned %s %.3f ms per 200 steps"
+        % (out["dense"]["ms_per_200_steps"], out["autotuned"]["plan"], ms))
+    return out
+
+
+def bench_rl(args, torch, fs, firegen):
+    """RL air-tanker layer: 65536 envs of 20 x 20, 100 steps of random actions
+    (agent move + water drop + fire step + reward + 5 x 5 observation)."""
+    n = 65536
+    batch = firegen.uniform_batch(20, 20, n_env=n, ignitions=())
+    params = firegen.Params(p_base=0.45)
+    sim = fs.FireSim.from_batch(batch, params, seed=0)
+    sim.set_plan(tile_rows=4, tile_width=64, graph=0)
+    env = fs.RLEnv(sim, obs_radius=2, drop_radius=1, water_capacity=20, max_steps=1000)
+    steps = 100
+    g = torch.Generator(device="cuda").manual_seed(0)
+    acts = torch.randint(0, 32, (steps, n), dtype=torch.int32, device="cuda", generator=g)
+    env.reset(episode=0)
+    for i in range(5):
+        env.step(acts[i])
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    env.reset(episode=1)
+    with StepTimer(torch, stream) as tm:
+        for i in range(steps):
+            env.step(acts[i])
+    ms = tm.ms()
+    rate = n * steps / (ms / 1e3)
+    log("[bench] rl: %.3f ms per step of %d envs, %.3e env-steps/s" % (ms / steps, n, rate))
+    return {"workload": "65536 envs x 20x20, 100 RL steps, random moves and valve, 5x5 observations",
+            "value": rate, "unit": "env-steps/s", "ms_per_step": round(ms / steps, 4),
+            "cell_updates_per_s": rate * 400}
+
+
 def relaxed_case(args, torch, fs, firegen, batch, params, T, k, label):
     sim = fs.FireSim.from_batch(batch, params, seed=0)
     sim.step(T)   # target scar: a stochastic run at the known parameters
@@ -315,6 +376,7 @@ def main():
     ap.add_argument("--no-relaxed", action="store_true")
     ap.add_argument("--no-variants", action="store_true", help="skip the front-skipping plans")
     ap.add_argument("--no-dense-front", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the paper-setting and RL objects")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (HBM counter calibration)")
@@ -337,6 +399,8 @@ def main():
     variants = None if args.no_variants else bench_variants(args, torch, fs, st)
     dense = None if args.no_dense_front else bench_dense_front(args, torch, fs, firegen, st)
     st.pop("sim")
+    paper = None if args.no_extra else bench_paper_config(args, torch, fs, firegen)
+    rl = None if args.no_extra else bench_rl(args, torch, fs, firegen)
     relaxed = None if args.no_relaxed else bench_relaxed(args, torch, fs, firegen)
     if args.copy_calibration:
         a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
@@ -355,6 +419,7 @@ def main():
                       "n_env": int(batch.n_env), "H": 256, "W": 256, "T": st["T"], "plan": st["plan"],
                       "burning_cell_steps": st["burning"]},
            "roofline": st["roof"], "variants": variants, "dense_front": dense, "relaxed": relaxed,
+           "paper_setting": paper, "rl": rl,
            "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
 

@@ -227,8 +227,9 @@ int sim_set_step(sim_handle* h, uint64_t t);
 /* Launch plan of sim_step (results never depend on it).
  *  tile_rows    rows of 4-cell groups each lane owns in its tile (1, 2, 4 or 8),
  *               0 = default (4)
- *  tile_width   widest tile in cells (64, 128 or 256; narrower envs use the
- *               largest width not above W rounded up), 0 = default (256)
+ *  tile_width   widest tile in cells (64, 128 or 256), 0 = default (256);
+ *               an env of width W gets the smallest of 16, 32, 64, 128, 256
+ *               that covers W, capped at tile_width
  *  temporal     steps per launch (1, 2, 4 or 8; 0 = default 1).  Above 1 each
  *               256-lane workgroup loads a tile_width x 32 tile of states
  *               with a halo of `temporal` cells into LDS, advances it that

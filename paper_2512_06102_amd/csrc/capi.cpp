@@ -137,7 +137,7 @@ StepArgs step_args(const sim_handle* h)
 // Widest tile width (64, 128, 256) not above max_width that W needs.
 int tile_width_for(int W, int max_width)
 {
-    const int w = W > 128 ? 256 : (W > 64 ? 128 : 64);
+    const int w = W > 128 ? 256 : (W > 64 ? 128 : (W > 32 ? 64 : (W > 16 ? 32 : 16)));
     return w < max_width ? w : max_width;
 }
 

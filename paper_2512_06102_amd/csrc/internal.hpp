@@ -41,8 +41,8 @@ struct StaticFields {
 };
 
 // One workgroup tile of the stochastic step: env, first row, first column and
-// tile width in cells (64, 128 or 256).  Its height is (1024 / width) *
-// rows_per_thread.
+// tile width in cells (16, 32, 64, 128 or 256; narrow envs get narrow tiles).
+// Its height is (256 / width) * rows_per_thread.
 struct TileDesc {
     int32_t env, r0, c0, width;
 };

@@ -217,7 +217,7 @@ __global__ __launch_bounds__(kWave) void stoch_step_kernel(
     const TileDesc td = tiles[tile];
     const EnvDev ed = envs[td.env];
     const int H = ed.H, W = ed.W;
-    const int gx_log = td.width == 256 ? 6 : (td.width == 128 ? 5 : 4);
+    const int gx_log = td.width == 256 ? 6 : (td.width == 128 ? 5 : (td.width == 64 ? 4 : (td.width == 32 ? 3 : 2)));
     const int GX = 1 << gx_log;  // lanes per row segment
     const int lane = threadIdx.x;
     const int tx = lane & (GX - 1), ty = lane >> gx_log;

@@ -506,3 +506,18 @@ def test_temporal_blocking_rejections():
     sim.set_plan(temporal=2, tile_width=64)
     sim.step(3)
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("plan", [dict(graph=1), dict(tile_rows=1, skip_static=1, sparse=1, graph=0),
+                                  dict(tile_rows=8, tile_width=64)])
+def test_narrow_envs_use_narrow_tiles(plan):
+    """Envs of width <= 32 run on 16- and 32-column tiles (4 or 8 lanes per
+    row segment): bit-exact with drops, including the RL scenario's 20 x 20."""
+    sizes = [(20, 20)] * 5 + [(12, 28), (32, 32), (16, 48), (40, 16), (9, 4), (33, 36)]
+    batch = firegen.landscape_batch(61, sizes)
+    params = firegen.Params(p_base=0.9, veg=_veg(61))
+    T = 25
+    act = firegen.random_actions(14, batch, T, p_none=0.5)
+    sim, ref, got, want = _run_both(batch, params, T, seed=3, actions=act, plan=plan)
+    assert np.array_equal(sim.states.cpu().numpy(), ref.states)
+    assert np.array_equal(got, want)
