@@ -66,6 +66,7 @@ class Params:
     p_continue: float = 0.5
     veg: Sequence[float] = tuple([0.0] * N_CLASSES)
     cell_size: float = 30.0
+    slope_mode: int = 0  # 0: S = rise / run; 1: S = atan(rise / run) (radians)
 
     def replace(self, **kw) -> "Params":
         return dataclasses.replace(self, **kw)

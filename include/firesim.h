@@ -58,12 +58,19 @@ enum { SIM_UNBURNABLE = 0, SIM_FLAMMABLE = 1, SIM_BURNING = 2, SIM_BURNT = 3 };
  *  veg[c]       mu_veg of land-cover class c, in [-1, 1]
  *  cell_size    cell edge in metres (slope = rise / run, run = cell_size or
  *               cell_size * sqrt(2) on diagonals)
- *  unburnable_mask  bit c set: class c holds no fuel (starts UNBURNABLE) */
+ *  unburnable_mask  bit c set: class c holds no fuel (starts UNBURNABLE)
+ *  slope_mode   SIM_SLOPE_RATIO: S of Eq. 2 is rise / run; SIM_SLOPE_ANGLE:
+ *               S is the slope angle atan(rise / run) in radians (the paper
+ *               says only that S is the slope toward the neighbour, positive
+ *               uphill); other values are SIM_EINVAL */
+#define SIM_SLOPE_RATIO 0
+#define SIM_SLOPE_ANGLE 1
 typedef struct {
     float p_base, alpha_gamma, alpha_w1, alpha_w2, alpha_s, p_continue;
     float veg[SIM_N_CLASSES];
     float cell_size;
     uint32_t unburnable_mask;
+    uint32_t slope_mode;
 } sim_params;
 
 /* One env of the batch.  (V, Vx, Vy) is its wind: speed V (m/s) and
@@ -344,6 +351,8 @@ int sim_step_relaxed_bwd(sim_handle* h, const sim_params* p, const double* gU_T,
  * tests of the building blocks).  x, y: device float[n]; ctr: device
  * uint32[n][4], key: device uint32[n][2], out: device uint32[n][4]. */
 int sim_debug_exp(const float* x, float* y, int64_t n, void* stream);
+/* The device arctangent of the slope-angle variant, elementwise. */
+int sim_debug_atan(const float* x, float* y, int64_t n, void* stream);
 int sim_debug_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int64_t n,
                      void* stream);
 

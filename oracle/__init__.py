@@ -31,7 +31,7 @@ class OracleParams(ctypes.Structure):
     _fields_ = [("p_base", ctypes.c_float), ("alpha_gamma", ctypes.c_float),
                 ("alpha_w1", ctypes.c_float), ("alpha_w2", ctypes.c_float),
                 ("alpha_s", ctypes.c_float), ("p_continue", ctypes.c_float),
-                ("cell_size", ctypes.c_float)]
+                ("cell_size", ctypes.c_float), ("slope_mode", ctypes.c_int32)]
 
 
 class OracleEnv(ctypes.Structure):
@@ -56,6 +56,7 @@ def lib():
         L.oracle_exp_c_batch.argtypes = [P, P, ctypes.c_int64]
         L.oracle_exp_c_sweep.argtypes = [ctypes.c_float, ctypes.c_float, ctypes.c_int,
                                          ctypes.c_int, P]
+        L.oracle_atan_c_batch.argtypes = [P, P, ctypes.c_int64]
         L.oracle_exp_c_sweep.restype = ctypes.c_double
         L.oracle_fuel.argtypes = [ctypes.c_int64, P, P, P, P]
         L.oracle_init_states.argtypes = [ctypes.c_int32, P, P, ctypes.c_uint32, P, ctypes.c_int32, P]
@@ -91,6 +92,13 @@ def philox_blocks(ctr, key):
     return out
 
 
+def atan_c(x):
+    x = np.ascontiguousarray(x, np.float32)
+    y = np.empty_like(x)
+    lib().oracle_atan_c_batch(_ptr(x), _ptr(y), x.size)
+    return y
+
+
 def exp_c(x):
     x = np.ascontiguousarray(x, np.float32)
     y = np.empty_like(x)
@@ -106,7 +114,7 @@ def exp_c_sweep(amag: float, bmag: float, negative: bool, threads: int = 8):
 
 def params_struct(p) -> OracleParams:
     return OracleParams(p.p_base, p.alpha_gamma, p.alpha_w1, p.alpha_w2, p.alpha_s,
-                        p.p_continue, p.cell_size)
+                        p.p_continue, p.cell_size, int(getattr(p, "slope_mode", 0)))
 
 
 def envs_struct(batch):

@@ -142,6 +142,49 @@ void oracle_exp_c_batch(const float* x, float* y, int64_t n)
     for (int64_t i = 0; i < n; ++i) y[i] = oracle_exp_c(x[i]);
 }
 
+/* ------------------------------------------------------------------------- */
+/* atan_c: the arctangent of the slope-angle variant (S = atan(rise / run)),  */
+/* in fp32 from the mathematics: atan is odd; for |x| > 1 use                 */
+/* atan(x) = pi/2 - atan(1/x); above tan(pi/8) use                            */
+/* atan(a) = pi/4 + atan((a - 1) / (a + 1)); on the remaining |t| <= tan(pi/8) */
+/* the Taylor series t - t^3/3 + ... - t^19/19 (Horner in t^2, coefficients   */
+/* rounded to fp32, separate multiply and add).  Divisions are IEEE.          */
+/* ------------------------------------------------------------------------- */
+float oracle_atan_c(float x)
+{
+    const float tan_pi8 = (float)0.41421356237309504880;
+    const float pi4 = (float)0.78539816339744830962, pi2 = (float)1.57079632679489661923;
+    if (x != x) return x;
+    const int neg = x < 0.0f;
+    float a = neg ? -x : x;
+    const int inv = a > 1.0f;
+    if (inv) a = 1.0f / a;
+    float base = 0.0f, t = a;
+    if (a > tan_pi8) {
+        t = (a - 1.0f) / (a + 1.0f);
+        base = pi4;
+    }
+    const float t2 = t * t;
+    float p = (float)(-1.0 / 19.0);
+    p = p * t2 + (float)(1.0 / 17.0);
+    p = p * t2 + (float)(-1.0 / 15.0);
+    p = p * t2 + (float)(1.0 / 13.0);
+    p = p * t2 + (float)(-1.0 / 11.0);
+    p = p * t2 + (float)(1.0 / 9.0);
+    p = p * t2 + (float)(-1.0 / 7.0);
+    p = p * t2 + (float)(1.0 / 5.0);
+    p = p * t2 + (float)(-1.0 / 3.0);
+    p = p * t2 + 1.0f;
+    float r = base + t * p;
+    if (inv) r = pi2 - r;
+    return neg ? -r : r;
+}
+
+void oracle_atan_c_batch(const float* x, float* y, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i) y[i] = oracle_atan_c(x[i]);
+}
+
 /* Error of exp_c against the fp64 exp, in units of the fp32 ulp of the true  */
 /* value, over every fp32 in [lo, hi]; multi-threaded over bit-pattern        */
 /* ranges.  Returns the max error; *worst receives its argument.              */
@@ -209,6 +252,7 @@ typedef struct {
     float alpha_s;     /* Eq. 2                                         */
     float p_continue;  /* stochastic update: burning stays burning      */
     float cell_size;   /* metres per cell edge (slope denominator)      */
+    int32_t slope_mode; /* 0: S = rise / run; 1: S = atan(rise / run)   */
 } oracle_params;
 
 typedef struct {
@@ -310,7 +354,9 @@ static float phi_uk(const step_ctx* c, int64_t u, int64_t v, int k)
     /* exponent of kappa_wind: alpha_w1 V + alpha_w2 V (cos(phi_k - Theta) - 1) */
     float wind_exp = P->alpha_w1 * V + P->alpha_w2 * ((c->cx[k] * Vx + c->sy[k] * Vy) - V);
     /* exponent of kappa_slope: alpha_s S(u, k), S = rise over run toward v   */
+    /* (or its angle, in radians)                                             */
     float slope = (c->E[v] - c->E[u]) * c->invd[k];
+    if (P->slope_mode) slope = oracle_atan_c(slope);
     float x = wind_exp + P->alpha_s * slope;
     return (P->p_base * c->g[u]) * oracle_exp_c(x);
 }

@@ -81,7 +81,7 @@ def scatter_to_source(C: np.ndarray, k: int) -> np.ndarray:
 class Env64:
     """One env's static inputs in float64 arrays of shape [H, W]."""
 
-    def __init__(self, cls, den, elev, wind, cell_size):
+    def __init__(self, cls, den, elev, wind, cell_size, slope_mode=0):
         self.cls = np.asarray(cls).astype(np.int64)
         self.den = np.asarray(den, np.float64)
         self.E = np.asarray(elev, np.float64)
@@ -94,10 +94,11 @@ class Env64:
         else:  # [3, H, W]
             self.V, self.Vx, self.Vy = w[0], w[1], w[2]
         self.cs = float(cell_size)
+        self.slope_mode = int(slope_mode)  # 0: S = rise / run; 1: S = atan(rise / run)
         self.valid = [shift_from_source(np.ones((H, W)), k) > 0 for k in range(8)]
 
 
-def from_batch(batch, e, cell_size) -> Env64:
+def from_batch(batch, e, cell_size, slope_mode=0) -> Env64:
     H, W = int(batch.H[e]), int(batch.W[e])
     sl = batch.env_slice(e)
     if batch.wind_cell is not None:
@@ -105,7 +106,7 @@ def from_batch(batch, e, cell_size) -> Env64:
     else:
         wind = batch.wind_env[e]
     return Env64(batch.cls[sl].reshape(H, W), batch.den[sl].reshape(H, W),
-                 batch.elev[sl].reshape(H, W), wind, cell_size)
+                 batch.elev[sl].reshape(H, W), wind, cell_size, slope_mode)
 
 
 def edge_terms(env: Env64, theta: np.ndarray) -> dict:
@@ -130,6 +131,8 @@ def edge_terms(env: Env64, theta: np.ndarray) -> dict:
         # V cos(ang_k - Theta) - V, with V cos Theta = Vx, V sin Theta = Vy
         cosdev = (ca * Vx + sa * Vy) - V
         S = (env.E - Eu) / dist
+        if env.slope_mode:
+            S = np.arctan(S)  # the slope angle (radians)
         kappa_wind = np.exp(a_w1 * V) * np.exp(a_w2 * cosdev)
         kappa_slope = np.exp(a_s * S)
         kappa = kappa_wind * kappa_slope
@@ -315,7 +318,7 @@ def adjoint(env: Env64, theta, Us, Bs, terms, gU_T, gB_T=None, form="product") -
 
 
 def loss_and_grad(batch, theta, T, Y_list, env_ids=None, cell_size=30.0, form="product",
-                  loss="iou", **loss_kw) -> tuple:
+                  loss="iou", slope_mode=0, **loss_kw) -> tuple:
     """Mean loss over the given envs after T relaxed steps, its gradient,
     and the final (U_T, B_T) per env."""
     theta = np.asarray(theta, np.float64)
@@ -325,7 +328,7 @@ def loss_and_grad(batch, theta, T, Y_list, env_ids=None, cell_size=30.0, form="p
     grad = np.zeros(N_THETA)
     finals = []
     for idx, e in enumerate(env_ids):
-        env = from_batch(batch, e, cell_size)
+        env = from_batch(batch, e, cell_size, slope_mode)
         U0, B0, burnable = initial_state(batch, e)
         Us, Bs, terms = forward(env, theta, U0, B0, T, form)
         Le, gU = loss_fn(loss, Us[-1], Y_list[idx], burnable, **loss_kw)
@@ -336,13 +339,13 @@ def loss_and_grad(batch, theta, T, Y_list, env_ids=None, cell_size=30.0, form="p
 
 
 def loss_only(batch, theta, T, Y_list, env_ids=None, cell_size=30.0, form="product", loss="iou",
-              **loss_kw) -> float:
+              slope_mode=0, **loss_kw) -> float:
     theta = np.asarray(theta, np.float64)
     env_ids = list(range(batch.n_env) if env_ids is None else env_ids)
     n = len(env_ids)
     L = 0.0
     for idx, e in enumerate(env_ids):
-        env = from_batch(batch, e, cell_size)
+        env = from_batch(batch, e, cell_size, slope_mode)
         U0, B0, burnable = initial_state(batch, e)
         Us, Bs, _ = forward(env, theta, U0, B0, T, form)
         L += loss_fn(loss, Us[-1], Y_list[idx], burnable, **loss_kw)[0] / n

@@ -28,7 +28,7 @@ EXPORTED = ("sim_init", "sim_step", "sim_get_step", "sim_set_step", "sim_set_pla
             "sim_autotune", "sim_set_wind_series", "sim_step_history", "sim_set_drop",
             "sim_rl_reset", "sim_rl_step",
             "sim_relaxed_init", "sim_relaxed_workspace_bytes", "sim_step_relaxed_fwd",
-            "sim_relaxed_loss", "sim_relaxed_loss_bce", "sim_step_relaxed_bwd", "sim_debug_exp", "sim_debug_philox",
+            "sim_relaxed_loss", "sim_relaxed_loss_bce", "sim_step_relaxed_bwd", "sim_debug_exp", "sim_debug_atan", "sim_debug_philox",
             "sim_last_error", "sim_destroy")
 
 
@@ -37,7 +37,7 @@ class SimParams(ctypes.Structure):
                 ("alpha_w1", ctypes.c_float), ("alpha_w2", ctypes.c_float),
                 ("alpha_s", ctypes.c_float), ("p_continue", ctypes.c_float),
                 ("veg", ctypes.c_float * N_CLASSES), ("cell_size", ctypes.c_float),
-                ("unburnable_mask", ctypes.c_uint32)]
+                ("unburnable_mask", ctypes.c_uint32), ("slope_mode", ctypes.c_uint32)]
 
 
 class SimEnv(ctypes.Structure):
@@ -94,6 +94,7 @@ def lib() -> ctypes.CDLL:
         L.sim_relaxed_loss_bce.argtypes = [P, P, P, I32, D, D, P, P, D, P]
         L.sim_step_relaxed_bwd.argtypes = [P, P, P, P, I32, I32, I32, P, SZ, P, P]
         L.sim_debug_exp.argtypes = [P, P, I64, P]
+        L.sim_debug_atan.argtypes = [P, P, I64, P]
         L.sim_debug_philox.argtypes = [P, P, P, I64, P]
         L.sim_last_error.argtypes = [P]
         L.sim_last_error.restype = ctypes.c_char_p
@@ -132,6 +133,7 @@ def make_params(p) -> SimParams:
     for c in range(N_CLASSES):
         s.veg[c] = float(p.veg[c])
     s.unburnable_mask = int(from_mask) if from_mask is not None else 0
+    s.slope_mode = int(getattr(p, "slope_mode", 0))
     return s
 
 
@@ -144,6 +146,14 @@ def params_with_theta(base: SimParams, theta: Sequence[float]) -> SimParams:
     for c in range(N_CLASSES):
         s.veg[c] = float(theta[6 + c])
     return s
+
+
+def debug_atan(x: torch.Tensor) -> torch.Tensor:
+    """The slope-angle arctangent of the step applied to a float32 CUDA tensor."""
+    x = x.contiguous()
+    y = torch.empty_like(x)
+    _check(lib().sim_debug_atan(_ptr(x), _ptr(y), x.numel(), ctypes.c_void_p(_stream(x.device))))
+    return y
 
 
 def debug_exp(x: torch.Tensor) -> torch.Tensor:

@@ -131,6 +131,7 @@ StepArgs step_args(const sim_handle* h)
     a.key1 = (uint32_t)(h->seed >> 32);
     a.drop_mode = h->drop_mode;
     a.drop_radius = h->drop_radius;
+    a.slope_mode = (int32_t)p.slope_mode;
     return a;
 }
 
@@ -335,6 +336,8 @@ int sim_init(sim_handle** out, const sim_params* p, int32_t n_env, const sim_env
     if (n_ign < 0 || (n_ign > 0 && !ignitions)) return fail(nullptr, SIM_EINVAL, "bad ignition list");
     if (!(p->cell_size > 0.0f) || !std::isfinite(p->cell_size))
         return fail(nullptr, SIM_EINVAL, "cell_size must be positive");
+    if (p->slope_mode != SIM_SLOPE_RATIO && p->slope_mode != SIM_SLOPE_ANGLE)
+        return fail(nullptr, SIM_EINVAL, "slope_mode must be SIM_SLOPE_RATIO or SIM_SLOPE_ANGLE");
     if (n_cells < 1) return fail(nullptr, SIM_EINVAL, "n_cells must be >= 1");
     // envs: sizes and disjoint in-range cell ranges
     std::vector<std::pair<int64_t, int64_t>> ranges;
@@ -735,6 +738,8 @@ static int check_relaxed_params(sim_handle* h, const sim_params* p)
     if (!p) return fail(h, SIM_EINVAL, "params are NULL");
     if (p->cell_size != h->params.cell_size || p->unburnable_mask != h->params.unburnable_mask)
         return fail(h, SIM_EINVAL, "cell_size and unburnable_mask must match sim_init");
+    if (p->slope_mode != SIM_SLOPE_RATIO && p->slope_mode != SIM_SLOPE_ANGLE)
+        return fail(h, SIM_EINVAL, "slope_mode must be SIM_SLOPE_RATIO or SIM_SLOPE_ANGLE");
     return SIM_OK;
 }
 
@@ -804,6 +809,12 @@ int sim_step_relaxed_bwd(sim_handle* h, const sim_params* p, const double* gU_T,
                                     ckpt_every, workspace, grad, h->relaxed);
     if (e != hipSuccess) return fail(h, SIM_EHIP, "relaxed backward failed: %s", hipGetErrorString(e));
     return SIM_OK;
+}
+
+int sim_debug_atan(const float* x, float* y, int64_t n, void* stream)
+{
+    if (n < 0 || (n > 0 && (!x || !y))) return SIM_EINVAL;
+    return launch_debug_atan((hipStream_t)stream, x, y, n) == hipSuccess ? SIM_OK : SIM_EHIP;
 }
 
 int sim_debug_exp(const float* x, float* y, int64_t n, void* stream)

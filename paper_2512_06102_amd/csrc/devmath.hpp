@@ -68,6 +68,40 @@ __device__ __forceinline__ float exp_c(float x)
     return poly * two_n;
 }
 
+// arctan in fp32 for the slope-angle variant: odd; pi/2 - atan(1/x) above
+// 1; pi/4 + atan((a-1)/(a+1)) above tan(pi/8); then the Taylor series
+// t - t^3/3 + t^5/5 - ... - t^19/19 in t^2 by Horner's rule (|t| <= tan(pi/8),
+// truncation below 1e-8 relative).  IEEE divisions, no contraction.
+__device__ __forceinline__ float atan_c(float x)
+{
+    constexpr float kTanPi8 = (float)0.41421356237309504880;
+    constexpr float kPi4 = (float)0.78539816339744830962, kPi2 = (float)1.57079632679489661923;
+    if (x != x) return x;
+    const bool neg = x < 0.0f;
+    float a = neg ? -x : x;
+    const bool inv = a > 1.0f;
+    if (inv) a = 1.0f / a;
+    float base = 0.0f, t = a;
+    if (a > kTanPi8) {
+        t = (a - 1.0f) / (a + 1.0f);
+        base = kPi4;
+    }
+    const float t2 = t * t;
+    float poly = (float)(-1.0 / 19.0);
+    poly = poly * t2 + (float)(1.0 / 17.0);
+    poly = poly * t2 + (float)(-1.0 / 15.0);
+    poly = poly * t2 + (float)(1.0 / 13.0);
+    poly = poly * t2 + (float)(-1.0 / 11.0);
+    poly = poly * t2 + (float)(1.0 / 9.0);
+    poly = poly * t2 + (float)(-1.0 / 7.0);
+    poly = poly * t2 + (float)(1.0 / 5.0);
+    poly = poly * t2 + (float)(-1.0 / 3.0);
+    poly = poly * t2 + 1.0f;
+    float r = base + t * poly;
+    if (inv) r = kPi2 - r;
+    return neg ? -r : r;
+}
+
 // Neighbour direction k points from a source cell to its target; its angle
 // is k*pi/4 counter-clockwise from east and rows grow southward, so
 // (drow, dcol) = E(0,1) NE(-1,1) N(-1,0) NW(-1,-1) W(0,-1) SW(1,-1) S(1,0)

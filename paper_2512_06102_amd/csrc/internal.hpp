@@ -24,6 +24,7 @@ struct StepArgs {
     uint32_t key0, key1;               // Philox key (seed lo, seed hi)
     int32_t drop_mode;                 // 0: FLAMMABLE/BURNING -> UNBURNABLE, 1: BURNING -> BURNT
     int32_t drop_radius;               // drops cover (2R+1) x (2R+1) cells
+    int32_t slope_mode;                // 0: S = rise / run; 1: S = atan(rise / run)
 };
 
 // Inputs of the step resident in HBM: fuel and elevation for the life of a
@@ -102,6 +103,7 @@ hipError_t launch_stoch_tb(hipStream_t s, const StepLaunch& L, int K, int tile_w
 hipError_t launch_set_u32(hipStream_t s, uint32_t* p, uint32_t v);
 
 hipError_t launch_debug_exp(hipStream_t s, const float* x, float* y, int64_t n);
+hipError_t launch_debug_atan(hipStream_t s, const float* x, float* y, int64_t n);
 hipError_t launch_debug_philox(hipStream_t s, const uint32_t* ctr, const uint32_t* key,
                                uint32_t* out, int64_t n);
 

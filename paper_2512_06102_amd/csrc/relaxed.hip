@@ -47,7 +47,14 @@ namespace {
 struct RelaxedArgs {
     float p_base, alpha_gamma, alpha_w1, alpha_w2, alpha_s, p_continue;
     float inv_orth, inv_diag;
+    int32_t slope_mode;  // 0: S = rise / run; 1: S = atan(rise / run)
 };
+
+// S of Eq. 2 from the rise over the run (or its angle).
+__device__ __forceinline__ float slope_of(float rise_over_run, const RelaxedArgs& A)
+{
+    return A.slope_mode ? atanf(rise_over_run) : rise_over_run;
+}
 
 RelaxedArgs relaxed_args(const sim_params& p)
 {
@@ -60,6 +67,7 @@ RelaxedArgs relaxed_args(const sim_params& p)
     a.p_continue = p.p_continue;
     a.inv_orth = (float)(1.0 / (double)p.cell_size);
     a.inv_diag = (float)(1.0 / ((double)p.cell_size * 1.41421356237309504880));
+    a.slope_mode = (int32_t)p.slope_mode;
     return a;
 }
 
@@ -216,7 +224,7 @@ __global__ __launch_bounds__(256) void relaxed_fwd_kernel(
                 if (Bu == 0.0) continue;  // off-grid sources read 0
                 const int64_t u = v - (int64_t)kDRow[k] * W - kDCol[k];
                 const float x = source_wind<WC>(k, ew, wind, n_cells, u, A) +
-                                A.alpha_s * ((Ev - sE[s]) * ((k & 1) ? A.inv_diag : A.inv_orth));
+                                A.alpha_s * slope_of((Ev - sE[s]) * ((k & 1) ? A.inv_diag : A.inv_orth), A);
                 const float phi = A.p_base * sg[s] * hexp(x);
                 if constexpr (FORM == 0)
                     prod = prod * (1.0 - (double)one_minus_exp_neg(gam * phi) * Bu);
@@ -306,7 +314,7 @@ __global__ __launch_bounds__(256) void relaxed_bwd_kernel(
             if (ui >= 0 && ui < H && uj >= 0 && uj < W && (Pbar != 0.0 || Bs[k] != 0.0)) {
                 const int64_t u = v - (int64_t)kDRow[k] * W - kDCol[k];
                 const float x = source_wind<WC>(k, ew, wind, n_cells, u, A) +
-                                A.alpha_s * ((Ev - sE[s]) * ((k & 1) ? A.inv_diag : A.inv_orth));
+                                A.alpha_s * slope_of((Ev - sE[s]) * ((k & 1) ? A.inv_diag : A.inv_orth), A);
                 ex[k] = hexp(x);
                 ph[k] = A.p_base * sg[s] * ex[k];
                 if constexpr (FORM == 0) {
@@ -371,7 +379,7 @@ __global__ __launch_bounds__(256) void relaxed_bwd_kernel(
                 acc[0] += phibar * gu * (double)ex[k];
                 acc[1] += xbar * (double)V;
                 acc[2] += xbar * (double)((kCos[k] * Vx + kSin[k] * Vy) - V);
-                acc[3] += xbar * ((double)(Ev - sE[s]) * (double)((k & 1) ? A.inv_diag : A.inv_orth));
+                acc[3] += xbar * (double)slope_of((Ev - sE[s]) * ((k & 1) ? A.inv_diag : A.inv_orth), A);
             }
         }
         if (interior) {

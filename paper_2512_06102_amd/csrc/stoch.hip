@@ -106,7 +106,8 @@ __device__ __forceinline__ float ignite_prob(uint32_t nbk, int64_t v, int W, con
             wexp = wind_exponent(k, A.alpha_w1, A.alpha_w2, V_u[k], Vx_u[k], Vy_u[k]);
         else
             wexp = ew[k];
-        const float slope = (E_v - E_u[k]) * ((k & 1) ? A.inv_run_diag : A.inv_run_orth);
+        float slope = (E_v - E_u[k]) * ((k & 1) ? A.inv_run_diag : A.inv_run_orth);
+        if (A.slope_mode) slope = atan_c(slope);  // the slope angle in radians
         const float x = wexp + A.alpha_s * slope;
         lambda = lambda + (A.p_base * g_u[k]) * exp_c(x);
     }
@@ -594,6 +595,13 @@ __global__ void debug_exp_kernel(const float* x, float* y, int64_t n)
         y[i] = exp_c(x[i]);
 }
 
+__global__ void debug_atan_kernel(const float* x, float* y, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = atan_c(x[i]);
+}
+
 __global__ void debug_philox_kernel(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int64_t n)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -975,6 +983,13 @@ hipError_t launch_debug_exp(hipStream_t s, const float* x, float* y, int64_t n)
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(debug_exp_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, x, y, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_debug_atan(hipStream_t s, const float* x, float* y, int64_t n)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(debug_atan_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, x, y, n);
     return hipGetLastError();
 }
 

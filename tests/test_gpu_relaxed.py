@@ -294,3 +294,19 @@ def test_relaxed2048_launch_config():
         Ls.append(float(_gpu_loss_grad(batch, p, Y, T, k)[2][0]))
     fd = (Ls[0] - Ls[1]) / (2 * h)
     assert abs(fd - float(g @ d)) <= 2e-2 * abs(float(g @ d)), (fd, float(g @ d))
+
+
+@pytest.mark.parametrize("form", ["product", "exp"])
+def test_slope_angle_mode(form):
+    """S = atan(rise / run) in the relaxed forward and adjoint, on steep
+    terrain, against the fp64 oracle in the same mode."""
+    batch = firegen.landscape_batch(72, [(48, 40), (33, 64)], elev_max=1500.0, per_cell_wind=True)
+    params = _params(8, slope_mode=1)
+    T, k = 18, 5
+    Y = _target(batch, params, T, 11)
+    U, B, loss, grad = _gpu_loss_grad(batch, params, Y, T, k, form)
+    L64, g64, finals = _oracle(batch, params, Y, T, form, slope_mode=1)
+    for e in range(batch.n_env):
+        assert np.max(np.abs(batch.env_view(U, e) - finals[e][0])) <= 1e-5
+    assert abs(float(loss.astype(np.float64).mean()) - L64) <= 1e-5
+    _check_grad(grad, g64)

@@ -521,3 +521,39 @@ def test_narrow_envs_use_narrow_tiles(plan):
     sim, ref, got, want = _run_both(batch, params, T, seed=3, actions=act, plan=plan)
     assert np.array_equal(sim.states.cpu().numpy(), ref.states)
     assert np.array_equal(got, want)
+
+
+def test_atan_bit_exact():
+    """The device arctangent of the slope-angle variant equals the oracle's
+    on every third fp32 in (-2^24, 2^24) and on +-0, +-inf, NaN-free powers."""
+    top = int(np.float32(2.0 ** 24).view(np.uint32))
+    chunk = 1 << 26
+    for neg in (False, True):
+        for start in range(0, top, chunk):
+            bits = np.arange(start, min(start + chunk, top), 3, dtype=np.uint32)
+            if neg:
+                bits |= np.uint32(0x80000000)
+            x = bits.view(np.float32)
+            want = oracle.atan_c(x)
+            got = fs.debug_atan(torch.from_numpy(x).cuda()).cpu().numpy()
+            bad = np.flatnonzero(got.view(np.uint32) != want.view(np.uint32))
+            assert bad.size == 0, (x[bad[:5]], got[bad[:5]], want[bad[:5]])
+    x = np.array([0.0, -0.0, np.inf, -np.inf, 2.0 ** 100, -2.0 ** -100], np.float32)
+    assert np.array_equal(fs.debug_atan(torch.from_numpy(x).cuda()).cpu().numpy().view(np.uint32),
+                          oracle.atan_c(x).view(np.uint32))
+
+
+@pytest.mark.parametrize("per_cell_wind", [False, True])
+@pytest.mark.parametrize("plan", [dict(graph=1), dict(tile_width=128, temporal=4)])
+def test_slope_angle_mode(per_cell_wind, plan):
+    """S = atan(rise / run) on steep terrain (0-2000 m): bit-exact."""
+    batch = firegen.landscape_batch(71, [(128, 128), (64, 200), (36, 52)], elev_max=2000.0,
+                                    per_cell_wind=per_cell_wind)
+    params = firegen.Params(p_base=0.8, alpha_s=3.0, slope_mode=1, veg=_veg(71))
+    T = 30
+    sim, ref, got, want = _run_both(batch, params, T, seed=8, plan=plan)
+    assert np.array_equal(sim.states.cpu().numpy(), ref.states)
+    assert np.array_equal(got, want)
+    flat = oracle.Sim(batch, params.replace(slope_mode=0), seed=8)
+    flat.step(T, threads=6)
+    assert not np.array_equal(flat.states, ref.states)   # the mode matters here

@@ -501,3 +501,42 @@ def test_water_drop_extinguishes_square_before_the_step(radius):
         want = Fd.copy()
         want[(Fd == firegen.FLAMMABLE) & (nb > 0)] = firegen.BURNING
         assert np.array_equal(F1, want), (mode, radius)
+
+
+# ---------------------------------------------------- slope-angle variant --
+def _ulp32(v):
+    v = np.abs(v)
+    e = np.floor(np.log2(np.maximum(v, 2.0 ** -126)))
+    return 2.0 ** (e - 23)
+
+
+def test_atan_c_within_3ulp_and_odd():
+    """atan_c against fp64 atan on every 64th fp32 bit pattern of [0, 2^24]
+    plus powers of two up to 2^100, in units of the result's fp32 ulp; odd and
+    monotone; atan(+-inf) = +-pi/2."""
+    bits = np.arange(0, np.float32(2.0 ** 24).view(np.uint32), 64, dtype=np.uint32)
+    x = np.concatenate([bits.view(np.float32), (2.0 ** np.arange(-100, 101)).astype(np.float32)])
+    y = oracle.atan_c(x).astype(np.float64)
+    want = np.arctan(x.astype(np.float64))
+    err = np.abs(y - want) / _ulp32(want)
+    assert np.max(err[want != 0]) <= 3.0, (x[np.argmax(err)], np.max(err))
+    assert np.array_equal(oracle.atan_c(-x), -oracle.atan_c(x))
+    xs = np.sort(x)
+    assert np.all(np.diff(oracle.atan_c(xs).astype(np.float64)) >= 0)
+    inf = oracle.atan_c(np.array([np.inf, -np.inf], np.float32))
+    assert inf[0] == np.float32(math.pi / 2) and inf[1] == -np.float32(math.pi / 2)
+
+
+def test_slope_angle_mode():
+    """slope_mode 1: S is the slope angle atan(rise / run) in radians, so
+    spreading uphill by h over one cell gives exp(a_s atan(h / cs)) (Eq. 2),
+    diagonals with run cs sqrt(2); and downhill the mirror image."""
+    prm = firegen.Params(alpha_s=3.0, p_base=0.25, cell_size=30.0, slope_mode=1)
+    for h in (6.0, 45.0, -20.0, 300.0):
+        E = np.zeros((3, 3), np.float32)
+        E[1, 1] = h
+        for k, run in [(2, 30.0), (1, 30.0 * math.sqrt(2)), (4, 30.0)]:
+            b, st = _one_cell_batch([k], slope_rise=E)
+            p = oracle.Sim(b, prm).cell_prob(0, 1, 1, st)
+            want = 1.0 - math.exp(-0.25 * math.exp(3.0 * math.atan(h / run)))
+            assert abs(p - want) < 4e-7, (h, k, p, want)

@@ -196,3 +196,29 @@ def test_mass_invariants():
         assert np.all(Us[t + 1] <= Us[t] + 1e-15)
         assert np.all(Us[t + 1] + Bs[t + 1] <= 1 + 1e-12)
         assert np.all(Us[t + 1][~burnable] == 0) and np.all(Bs[t + 1][~burnable] == 0)
+
+
+@pytest.mark.parametrize("form", ["product", "exp"])
+def test_adjoint_matches_central_differences_slope_angle(form):
+    """The slope-angle variant (S = atan(rise / run)): the adjoint against
+    fp64 central differences, on steep terrain where atan departs from its
+    argument."""
+    b = firegen.landscape_batch(4, ((14, 18),), elev_max=400.0)
+    prm = _params(7)
+    T = 10
+    Y = _target(b, T, 5)
+    theta = relaxed64.theta_from_params(prm)
+    kw = dict(form=form, slope_mode=1)
+    L, grad, _ = relaxed64.loss_and_grad(b, theta, T, Y, **kw)
+    L0, _, _ = relaxed64.loss_and_grad(b, theta, T, Y, form=form)
+    assert L != L0   # the mode changes the model
+    fd = np.zeros_like(grad)
+    for i in range(theta.size):
+        h = 1e-6 * max(1.0, abs(theta[i]))
+        tp, tm = theta.copy(), theta.copy()
+        tp[i] += h
+        tm[i] -= h
+        fd[i] = (relaxed64.loss_only(b, tp, T, Y, **kw) - relaxed64.loss_only(b, tm, T, Y, **kw)) / (2 * h)
+    scale = np.max(np.abs(fd))
+    for i in range(theta.size):
+        assert abs(grad[i] - fd[i]) <= 1e-6 * scale + 1e-6 * abs(fd[i]), (relaxed64.THETA_NAMES[i], grad[i], fd[i])
