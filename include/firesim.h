@@ -144,7 +144,9 @@ int sim_step(sim_handle* h, uint8_t* states, const int32_t* actions, int32_t T, 
  * created with per-cell wind accepts only a per-cell series.  The memory is
  * the caller's and must stay valid while steps run.  sim_step and
  * sim_autotune fail with SIM_EINVAL when a call would read past row
- * series_T - 1.  The relaxed calls keep the static wind. */
+ * series_T - 1.  The relaxed calls use the same series: relaxed step t
+ * (counted from the relaxed initial state) takes row t, and a relaxed call
+ * with T > series_T is SIM_EINVAL. */
 int sim_set_wind_series(sim_handle* h, const float* env_wind, const float* cell_wind, int64_t series_T);
 
 /* sim_step_history -- sim_step that also keeps every intermediate state

@@ -81,7 +81,7 @@ def scatter_to_source(C: np.ndarray, k: int) -> np.ndarray:
 class Env64:
     """One env's static inputs in float64 arrays of shape [H, W]."""
 
-    def __init__(self, cls, den, elev, wind, cell_size, slope_mode=0):
+    def __init__(self, cls, den, elev, wind, cell_size, slope_mode=0, wind_series=None):
         self.cls = np.asarray(cls).astype(np.int64)
         self.den = np.asarray(den, np.float64)
         self.E = np.asarray(elev, np.float64)
@@ -95,18 +95,41 @@ class Env64:
             self.V, self.Vx, self.Vy = w[0], w[1], w[2]
         self.cs = float(cell_size)
         self.slope_mode = int(slope_mode)  # 0: S = rise / run; 1: S = atan(rise / run)
+        # time-varying wind: [S, 3] (per env) or [S, 3, H, W] (per cell), row t for step t
+        self.wind_series = None if wind_series is None else np.asarray(wind_series, np.float64)
         self.valid = [shift_from_source(np.ones((H, W)), k) > 0 for k in range(8)]
 
 
-def from_batch(batch, e, cell_size, slope_mode=0) -> Env64:
+def from_batch(batch, e, cell_size, slope_mode=0, wind_env_series=None, wind_cell_series=None) -> Env64:
     H, W = int(batch.H[e]), int(batch.W[e])
     sl = batch.env_slice(e)
     if batch.wind_cell is not None:
         wind = batch.wind_cell[:, sl].reshape(3, H, W)
     else:
         wind = batch.wind_env[e]
+    series = None
+    if wind_env_series is not None:
+        series = np.asarray(wind_env_series)[:, e, :]
+    elif wind_cell_series is not None:
+        series = np.asarray(wind_cell_series)[:, :, sl].reshape(-1, 3, H, W)
     return Env64(batch.cls[sl].reshape(H, W), batch.den[sl].reshape(H, W),
-                 batch.elev[sl].reshape(H, W), wind, cell_size, slope_mode)
+                 batch.elev[sl].reshape(H, W), wind, cell_size, slope_mode, series)
+
+
+def env_at_step(env: Env64, t: int) -> Env64:
+    """The env with the wind of step t of its series (itself without one)."""
+    if env.wind_series is None:
+        return env
+    out = Env64.__new__(Env64)
+    out.__dict__.update(env.__dict__)
+    w = env.wind_series[t]
+    H, W = env.cls.shape
+    if w.ndim == 1:
+        out.V, out.Vx, out.Vy = (np.full((H, W), w[i]) for i in range(3))
+    else:
+        out.V, out.Vx, out.Vy = w[0], w[1], w[2]
+    out.wind_series = None
+    return out
 
 
 def edge_terms(env: Env64, theta: np.ndarray) -> dict:
@@ -186,11 +209,17 @@ def initial_state(batch, e) -> tuple:
 
 
 def forward(env: Env64, theta, U0, B0, T, form="product") -> tuple:
-    """Return the lists U[0..T], B[0..T] and the edge terms."""
-    terms = edge_terms(env, theta)
+    """Return the lists U[0..T], B[0..T] and the edge terms (one dict, or a
+    list of per-step dicts when the wind varies with time)."""
+    if env.wind_series is None:
+        terms = edge_terms(env, theta)
+        per_step = [terms] * T
+    else:
+        per_step = [edge_terms(env_at_step(env, t), theta) for t in range(T)]
+        terms = per_step
     Us, Bs = [U0.astype(np.float64)], [B0.astype(np.float64)]
-    for _ in range(T):
-        U, B = step(Us[-1], Bs[-1], terms, theta[5], form)
+    for t in range(T):
+        U, B = step(Us[-1], Bs[-1], per_step[t], theta[5], form)
         Us.append(U)
         Bs.append(B)
     return Us, Bs, terms
@@ -250,19 +279,47 @@ def loss_fn(kind, U_T, Y, burnable, **kw):
     raise ValueError(kind)
 
 
+def _param_chain(env: Env64, theta, terms, phibar, gamma_bar) -> np.ndarray:
+    """Gradient from the adjoints of phi_k (per edge) and gamma (per cell)
+    through phi_k = p_base g(u) kappa_k and gamma = alpha_gamma g(v)."""
+    grad = np.zeros(N_THETA)
+    p_base, a_gamma = theta[0], theta[4]
+    phi_k = terms["phi"]
+    g = terms["g"]
+    gbar = np.zeros_like(g)       # adjoint of the fuel term g per cell
+    for k in range(8):
+        kappa = np.where(env.valid[k], terms["kappa"][k], 0.0)
+        grad[0] += float(np.sum(phibar[k] * terms["g_src"][k] * kappa))
+        xbar = phibar[k] * phi_k[k]                  # phi = p_base g_u exp(x)
+        grad[1] += float(np.sum(xbar * terms["V_src"][k]))
+        grad[2] += float(np.sum(xbar * terms["cosdev"][k]))
+        grad[3] += float(np.sum(xbar * np.where(env.valid[k], terms["S"][k], 0.0)))
+        gbar += scatter_to_source(phibar[k] * p_base * kappa, k)
+    grad[4] += float(np.sum(gamma_bar * g))
+    gbar += gamma_bar * a_gamma
+    contrib = gbar * (1.0 + env.den)             # g = (1 + veg[c]) (1 + den)
+    grad[6:17] += np.bincount(env.cls.ravel(), weights=contrib.ravel(), minlength=11)[:11]
+    return grad
+
+
 def adjoint(env: Env64, theta, Us, Bs, terms, gU_T, gB_T=None, form="product") -> np.ndarray:
     """Reverse-mode gradient of a scalar loss with dL/dU_T = gU_T (and dL/dB_T
-    = gB_T, default 0) with respect to THETA."""
+    = gB_T, default 0) with respect to THETA.  With per-step edge terms (a
+    wind series) the parameter chain is applied step by step."""
     T = len(Us) - 1
     p_c = theta[5]
-    q, phi_k = terms["q"], terms["phi"]
-    gamma = terms["gamma"]
+    per_step = isinstance(terms, list)
     gU = gU_T.astype(np.float64).copy()
     gB = np.zeros_like(gU) if gB_T is None else gB_T.astype(np.float64).copy()
-    phibar = [np.zeros_like(gU) for _ in range(8)]   # summed over time
+    phibar = [np.zeros_like(gU) for _ in range(8)]   # summed over time (static terms)
     gamma_bar = np.zeros_like(gU)
     grad = np.zeros(N_THETA)
     for t in range(T - 1, -1, -1):
+        tt = terms[t] if per_step else terms
+        q, phi_k, gamma = tt["q"], tt["phi"], tt["gamma"]
+        if per_step:
+            phibar = [np.zeros_like(gU) for _ in range(8)]
+            gamma_bar = np.zeros_like(gU)
         U, B = Us[t], Bs[t]
         Bsrc = [shift_from_source(B, k) for k in range(8)]
         gB_new = p_c * gB
@@ -297,28 +354,17 @@ def adjoint(env: Env64, theta, Us, Bs, terms, gU_T, gB_T=None, form="product") -
                 gB_new = gB_new + scatter_to_source(lbar * phi_k[k], k)
                 phibar[k] += lbar * Bsrc[k]
         grad[5] += float(np.sum(gB * B))  # B' = newly + p_c B
+        if per_step:
+            grad += _param_chain(env, theta, tt, phibar, gamma_bar)
         gU, gB = gU + nbar * P, gB_new
-    # through phi_k = p_base g(u) kappa_k and gamma = alpha_gamma g(v)
-    p_base, a_gamma = theta[0], theta[4]
-    g = terms["g"]
-    gbar = np.zeros_like(g)       # adjoint of the fuel term g per cell
-    for k in range(8):
-        kappa = np.where(env.valid[k], terms["kappa"][k], 0.0)
-        grad[0] += float(np.sum(phibar[k] * terms["g_src"][k] * kappa))
-        xbar = phibar[k] * phi_k[k]                  # phi = p_base g_u exp(x)
-        grad[1] += float(np.sum(xbar * terms["V_src"][k]))
-        grad[2] += float(np.sum(xbar * terms["cosdev"][k]))
-        grad[3] += float(np.sum(xbar * np.where(env.valid[k], terms["S"][k], 0.0)))
-        gbar += scatter_to_source(phibar[k] * p_base * kappa, k)
-    grad[4] += float(np.sum(gamma_bar * g))
-    gbar += gamma_bar * a_gamma
-    contrib = gbar * (1.0 + env.den)             # g = (1 + veg[c]) (1 + den)
-    grad[6:17] += np.bincount(env.cls.ravel(), weights=contrib.ravel(), minlength=11)[:11]
+    if not per_step:
+        grad += _param_chain(env, theta, terms, phibar, gamma_bar)
     return grad
 
 
 def loss_and_grad(batch, theta, T, Y_list, env_ids=None, cell_size=30.0, form="product",
-                  loss="iou", slope_mode=0, **loss_kw) -> tuple:
+                  loss="iou", slope_mode=0, wind_env_series=None, wind_cell_series=None,
+                  **loss_kw) -> tuple:
     """Mean loss over the given envs after T relaxed steps, its gradient,
     and the final (U_T, B_T) per env."""
     theta = np.asarray(theta, np.float64)
@@ -328,7 +374,7 @@ def loss_and_grad(batch, theta, T, Y_list, env_ids=None, cell_size=30.0, form="p
     grad = np.zeros(N_THETA)
     finals = []
     for idx, e in enumerate(env_ids):
-        env = from_batch(batch, e, cell_size, slope_mode)
+        env = from_batch(batch, e, cell_size, slope_mode, wind_env_series, wind_cell_series)
         U0, B0, burnable = initial_state(batch, e)
         Us, Bs, terms = forward(env, theta, U0, B0, T, form)
         Le, gU = loss_fn(loss, Us[-1], Y_list[idx], burnable, **loss_kw)
@@ -339,13 +385,13 @@ def loss_and_grad(batch, theta, T, Y_list, env_ids=None, cell_size=30.0, form="p
 
 
 def loss_only(batch, theta, T, Y_list, env_ids=None, cell_size=30.0, form="product", loss="iou",
-              slope_mode=0, **loss_kw) -> float:
+              slope_mode=0, wind_env_series=None, wind_cell_series=None, **loss_kw) -> float:
     theta = np.asarray(theta, np.float64)
     env_ids = list(range(batch.n_env) if env_ids is None else env_ids)
     n = len(env_ids)
     L = 0.0
     for idx, e in enumerate(env_ids):
-        env = from_batch(batch, e, cell_size, slope_mode)
+        env = from_batch(batch, e, cell_size, slope_mode, wind_env_series, wind_cell_series)
         U0, B0, burnable = initial_state(batch, e)
         Us, Bs, _ = forward(env, theta, U0, B0, T, form)
         L += loss_fn(loss, Us[-1], Y_list[idx], burnable, **loss_kw)[0] / n

@@ -730,6 +730,12 @@ static RelaxedInputs relaxed_inputs(const sim_handle* h, int32_t form = 0)
     in.E = h->d_E;
     in.wind = h->wind_cell ? h->d_wind : nullptr;
     in.n_cells = h->n_cells;
+    if (h->series_cell) {  // relaxed step t takes row t of the wind series
+        in.wind = h->series_cell;
+        in.wind_stride = 3 * h->n_cells;
+    } else if (h->series_env) {
+        in.env_wind = h->series_env;
+    }
     return in;
 }
 
@@ -751,6 +757,9 @@ int sim_step_relaxed_fwd(sim_handle* h, const sim_params* p, double* U, double* 
     int rc = check_relaxed_params(h, p);
     if (rc) return rc;
     if (form != SIM_FORM_PRODUCT && form != SIM_FORM_EXP) return fail(h, SIM_EINVAL, "unknown form");
+    if ((h->series_env || h->series_cell) && (int64_t)T > h->series_T)
+        return fail(h, SIM_EINVAL, "the wind series covers %lld steps, the relaxed run needs %d",
+                    (long long)h->series_T, T);
     if (!U || !B || T < 0 || ckpt_every < 1) return fail(h, SIM_EINVAL, "bad U/B/T/ckpt_every");
     if (T > 0 && (!workspace || workspace_bytes < relaxed_workspace_bytes(h->n_cells, T, ckpt_every)))
         return fail(h, SIM_EINVAL, "workspace too small (%zu < %zu)", workspace_bytes,
@@ -800,6 +809,9 @@ int sim_step_relaxed_bwd(sim_handle* h, const sim_params* p, const double* gU_T,
     int rc = check_relaxed_params(h, p);
     if (rc) return rc;
     if (form != SIM_FORM_PRODUCT && form != SIM_FORM_EXP) return fail(h, SIM_EINVAL, "unknown form");
+    if ((h->series_env || h->series_cell) && (int64_t)T > h->series_T)
+        return fail(h, SIM_EINVAL, "the wind series covers %lld steps, the relaxed run needs %d",
+                    (long long)h->series_T, T);
     if (!gU_T || !grad || T < 0 || ckpt_every < 1) return fail(h, SIM_EINVAL, "bad gU_T/grad/T/ckpt_every");
     if (T > 0 && (!workspace || workspace_bytes < relaxed_workspace_bytes(h->n_cells, T, ckpt_every)))
         return fail(h, SIM_EINVAL, "workspace too small");

@@ -50,6 +50,14 @@ struct RelaxedArgs {
     int32_t slope_mode;  // 0: S = rise / run; 1: S = atan(rise / run)
 };
 
+// The per-env wind of the current step: row env of a series row [n_env][3],
+// or the env's static wind.
+__device__ __forceinline__ float3 env_wind_of(const EnvDev& ed, const float* env_wind, int env)
+{
+    if (env_wind) return make_float3(env_wind[3 * env], env_wind[3 * env + 1], env_wind[3 * env + 2]);
+    return make_float3(ed.V, ed.Vx, ed.Vy);
+}
+
 // S of Eq. 2 from the rise over the run (or its angle).
 __device__ __forceinline__ float slope_of(float rise_over_run, const RelaxedArgs& A)
 {
@@ -186,7 +194,7 @@ __global__ __launch_bounds__(256) void relaxed_fwd_kernel(
     const RelaxedTile* __restrict__ tiles, const EnvDev* __restrict__ envs, const float* __restrict__ g,
     const float* __restrict__ E, const float* __restrict__ wind, int64_t n_cells, RelaxedArgs A,
     const double* __restrict__ U, const double* __restrict__ B, double* __restrict__ Uo,
-    double* __restrict__ Bo)
+    double* __restrict__ Bo, const float* __restrict__ env_wind)
 {
     constexpr int EW = TW + 2, EH = TH + 2;
     __shared__ double sB[EH * EW];
@@ -203,7 +211,10 @@ __global__ __launch_bounds__(256) void relaxed_fwd_kernel(
         sg[idx] = in ? g[v] : 0.0f;
         sE[idx] = in ? E[v] : 0.0f;
     }
-    if (!WC && tid < 8) ew[tid] = wind_exponent(tid, A.alpha_w1, A.alpha_w2, ed.V, ed.Vx, ed.Vy);
+    if (!WC && tid < 8) {
+        const float3 w = env_wind_of(ed, env_wind, td.env);
+        ew[tid] = wind_exponent(tid, A.alpha_w1, A.alpha_w2, w.x, w.y, w.z);
+    }
     __syncthreads();
     for (int idx = tid; idx < TW * TH; idx += 256) {
         const int rr = idx / TW, cc = idx % TW;
@@ -252,7 +263,8 @@ __global__ __launch_bounds__(256) void relaxed_bwd_kernel(
     const float* __restrict__ E, const float* __restrict__ wind, const uint8_t* __restrict__ cls,
     const float* __restrict__ den, int64_t n_cells, RelaxedArgs A, const double* __restrict__ U,
     const double* __restrict__ B, const double* __restrict__ gU1, const double* __restrict__ gB1,
-    double* __restrict__ gU0, double* __restrict__ gB0, double* __restrict__ stripes)
+    double* __restrict__ gU0, double* __restrict__ gB0, double* __restrict__ stripes,
+    const float* __restrict__ env_wind)
 {
     constexpr int XW = BW + 4, XH = BH + 4;  // two-cell halo: sources of the ring
     constexpr int EW = BW + 2, EH = BH + 2;  // one-cell ring: targets gathered by the tile
@@ -274,7 +286,8 @@ __global__ __launch_bounds__(256) void relaxed_bwd_kernel(
         sg[idx] = in ? g[v] : 0.0f;
         sE[idx] = in ? E[v] : 0.0f;
     }
-    if (!WC && tid < 8) ew[tid] = wind_exponent(tid, A.alpha_w1, A.alpha_w2, ed.V, ed.Vx, ed.Vy);
+    const float3 wenv = env_wind_of(ed, env_wind, td.env);  // this step's per-env wind
+    if (!WC && tid < 8) ew[tid] = wind_exponent(tid, A.alpha_w1, A.alpha_w2, wenv.x, wenv.y, wenv.z);
     __syncthreads();
 
     double acc[17];
@@ -371,9 +384,9 @@ __global__ __launch_bounds__(256) void relaxed_bwd_kernel(
                     Vx = wind[n_cells + u];
                     Vy = wind[2 * n_cells + u];
                 } else {
-                    V = ed.V;
-                    Vx = ed.Vx;
-                    Vy = ed.Vy;
+                    V = wenv.x;
+                    Vx = wenv.y;
+                    Vy = wenv.z;
                 }
                 const double xbar = phibar * phi;
                 acc[0] += phibar * gu * (double)ex[k];
@@ -625,12 +638,22 @@ hipError_t fuel(hipStream_t s, const RelaxedInputs& in, const sim_params& p, flo
     return hipGetLastError();
 }
 
+// The inputs of relaxed step t: a wind series (per env or per cell) moves to
+// its row t; static wind is returned as it is.
+RelaxedInputs at_step(const RelaxedInputs& in, int32_t t)
+{
+    RelaxedInputs r = in;
+    if (in.wind && in.wind_stride) r.wind = in.wind + (int64_t)t * in.wind_stride;
+    if (in.env_wind) r.env_wind = in.env_wind + (int64_t)t * in.n_env * 3;
+    return r;
+}
+
 template <bool WC, int FORM>
 void launch_fwd(hipStream_t s, const RelaxedInputs& in, const RelaxedArgs& A, const float* g,
                 const double* U, const double* B, double* Uo, double* Bo)
 {
     hipLaunchKernelGGL((relaxed_fwd_kernel<WC, FORM>), dim3(in.n_tiles), dim3(256), 0, s, in.tiles,
-                       in.envs, g, in.E, in.wind, in.n_cells, A, U, B, Uo, Bo);
+                       in.envs, g, in.E, in.wind, in.n_cells, A, U, B, Uo, Bo, in.env_wind);
 }
 
 hipError_t fwd_step(hipStream_t s, const RelaxedInputs& in, const RelaxedArgs& A, const float* g,
@@ -650,7 +673,7 @@ void launch_bwd(hipStream_t s, const RelaxedInputs& in, const RelaxedState& R, c
 {
     hipLaunchKernelGGL((relaxed_bwd_kernel<WC, FORM>), dim3(R.n_btiles), dim3(256), 0, s, R.d_btiles,
                        in.envs, g, in.E, in.wind, in.cls, in.den, in.n_cells, A, U, B, gU1, gB1, gU0,
-                       gB0, stripes);
+                       gB0, stripes, in.env_wind);
 }
 
 }  // namespace
@@ -752,7 +775,7 @@ hipError_t relaxed_forward(hipStream_t s, const RelaxedInputs& in, const sim_par
             e = copy_f64(s, slot, cu, n);
             if (e == hipSuccess) e = copy_f64(s, slot + n, cb, n);
         }
-        if (e == hipSuccess) e = fwd_step(s, in, A, g, cu, cb, nu, nb);
+        if (e == hipSuccess) e = fwd_step(s, at_step(in, t), A, g, cu, cb, nu, nb);
         std::swap(cu, nu);
         std::swap(cb, nb);
     }
@@ -836,17 +859,18 @@ hipError_t relaxed_backward(hipStream_t s, const RelaxedInputs& in, const sim_pa
             return j == 0 ? base + n : seg + (size_t)j * 2 * n + n;
         };
         for (int32_t j = 1; j < t1 - t0 && e == hipSuccess; ++j)
-            e = fwd_step(s, in, A, g, state_u(j - 1), state_b(j - 1), seg + (size_t)j * 2 * n,
-                         seg + (size_t)j * 2 * n + n);
+            e = fwd_step(s, at_step(in, t0 + j - 1), A, g, state_u(j - 1), state_b(j - 1),
+                         seg + (size_t)j * 2 * n, seg + (size_t)j * 2 * n + n);
         for (int32_t t = t1 - 1; t >= t0 && e == hipSuccess; --t) {
             const int32_t j = t - t0;
             const double *Ut = state_u(j), *Bt = state_b(j);
-            if (in.wind)
-                in.form ? launch_bwd<true, 1>(s, in, R, A, g, Ut, Bt, cu, cb, nu, nb, stripes)
-                        : launch_bwd<true, 0>(s, in, R, A, g, Ut, Bt, cu, cb, nu, nb, stripes);
+            const RelaxedInputs it = at_step(in, t);
+            if (it.wind)
+                it.form ? launch_bwd<true, 1>(s, it, R, A, g, Ut, Bt, cu, cb, nu, nb, stripes)
+                        : launch_bwd<true, 0>(s, it, R, A, g, Ut, Bt, cu, cb, nu, nb, stripes);
             else
-                in.form ? launch_bwd<false, 1>(s, in, R, A, g, Ut, Bt, cu, cb, nu, nb, stripes)
-                        : launch_bwd<false, 0>(s, in, R, A, g, Ut, Bt, cu, cb, nu, nb, stripes);
+                it.form ? launch_bwd<false, 1>(s, it, R, A, g, Ut, Bt, cu, cb, nu, nb, stripes)
+                        : launch_bwd<false, 0>(s, it, R, A, g, Ut, Bt, cu, cb, nu, nb, stripes);
             e = hipGetLastError();
             std::swap(cu, nu);
             std::swap(cb, nb);

@@ -44,9 +44,11 @@ struct RelaxedInputs {
     const uint8_t* cls;
     const float* den;
     const float* E;
-    const float* wind;  // [3][n_cells] or nullptr
+    const float* wind;  // [3][n_cells] (or a series of such planes, see wind_stride) or nullptr
     int64_t n_cells;
     int32_t form;       // 0: product form of p_ignite, 1: 1 - exp(-gamma sum B phi)
+    int64_t wind_stride = 0;          // floats between the per-cell wind planes of steps t, t+1
+    const float* env_wind = nullptr;  // per-env wind series [T][n_env][3] or nullptr
 };
 
 int relaxed_prepare(RelaxedState& R, const std::vector<sim_env>& envs);

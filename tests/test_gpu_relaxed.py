@@ -310,3 +310,38 @@ def test_slope_angle_mode(form):
         assert np.max(np.abs(batch.env_view(U, e) - finals[e][0])) <= 1e-5
     assert abs(float(loss.astype(np.float64).mean()) - L64) <= 1e-5
     _check_grad(grad, g64)
+
+
+@pytest.mark.parametrize("per_cell", [False, True])
+def test_wind_series(per_cell):
+    """The relaxed forward and adjoint with time-varying wind (row t of the
+    handle's series for relaxed step t) against the fp64 oracle; a run longer
+    than the series is rejected."""
+    batch = firegen.landscape_batch(73, [(40, 56), (33, 17)], per_cell_wind=per_cell, elev_max=80.0)
+    params = _params(10)
+    T, k = 16, 5
+    ser = firegen.wind_series(9, batch, T, per_cell=per_cell, speed_step=1.0, turn_step=0.3)
+    Y = _target(batch, params, T, 12)
+    sim = fs.FireSim.from_batch(batch, params, seed=0)
+    dev = torch.from_numpy(ser).cuda()
+    sim.set_wind_series(cell_series=dev) if per_cell else sim.set_wind_series(env_series=dev)
+    p = fs.make_params(params)
+    p.unburnable_mask = batch.unburnable_mask
+    U, B = sim.relaxed_init()
+    ws = sim.relaxed_workspace(T, k)
+    sim.relaxed_fwd(p, U, B, T, k, ws)
+    loss, gU = sim.relaxed_loss(U, torch.from_numpy(Y).cuda(), scale=1.0 / batch.n_env)
+    grad = sim.relaxed_bwd(p, gU, None, T, k, ws).cpu().numpy()
+    torch.cuda.synchronize()
+    kw = {"wind_cell_series" if per_cell else "wind_env_series": ser}
+    L64, g64, finals = _oracle(batch, params, Y, T, **kw)
+    Un = U.cpu().numpy()
+    for e in range(batch.n_env):
+        assert np.max(np.abs(batch.env_view(Un, e) - finals[e][0])) <= 1e-5
+    assert abs(float(loss.cpu().double().mean()) - L64) <= 1e-5
+    _check_grad(grad, g64)
+    ws2 = sim.relaxed_workspace(T + 1, k)
+    U, B = sim.relaxed_init()
+    with pytest.raises(fs.SimError):
+        sim.relaxed_fwd(p, U, B, T + 1, k, ws2)
+    torch.cuda.synchronize()
