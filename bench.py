@@ -14,6 +14,9 @@ Reported beside it, each in its own object:
                 cell evaluates its neighbourhood each step;
   relaxed     - the relaxed forward + adjoint on 256 envs of 128 x 128 (T 100)
                 and on one 2048 x 2048 env (T 100), checkpoints every 10;
+  paper_setting, rl, uneven - the paper's 64 x 64^2 vectorised setting, the
+                RL layer on 65536 envs of 20 x 20, and the 4096-env uneven
+                batch with drops;
   cpu_baseline - the CPU oracle on the same stochastic workload.
 
 Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -282,6 +285,53 @@ def bench_paper_config(args, torch, fs, firegen):
     return out
 
 
+def bench_uneven(args, torch, fs, firegen):
+    """The uneven batch: 4096 envs with sides in {64, 128, 256, 512}, 300
+    steps, one 5 x 5 suppression drop per env per step, in-kernel counts; the
+    dense plan and the autotuner's choice."""
+    batch, params, T, seed, act = firegen.workload_uneven()
+    sim = fs.FireSim.from_batch(batch, params, seed=seed)
+    acts = torch.from_numpy(act).cuda()
+    init = sim.states.clone()
+    stream = torch.cuda.current_stream()
+    cells = float(batch.n_cells)
+
+    def run(reps):
+        for _ in range(reps):
+            sim.states.copy_(init)
+            sim.t = 0
+            sim.step(T, actions=acts, counts=True)
+
+    out = {"workload": "4096 envs, sides in {64,128,256,512} (%d cells), 300 steps, one 5x5 drop per "
+                       "env per step, in-kernel counts" % int(cells), "unit": "cell-updates/s"}
+    sim.set_plan(tile_rows=4, tile_width=256, temporal=1, skip_static=0, sparse=0, graph=1)
+    run(1)
+    torch.cuda.synchronize()
+    with StepTimer(torch, stream) as tm:
+        run(2)
+    ms = tm.ms() / 2
+    rate = cells * T / (ms / 1e3)
+    out["dense"] = {"ms_per_pass": round(ms, 3), "value": rate,
+                    "hbm_GBs_at_10B": round(STOCH_BYTES_PER_CELL * rate / 1e9, 1),
+                    "hbm_frac_at_10B": round(STOCH_BYTES_PER_CELL * rate / 1e9 / HBM_PEAK_GBS, 4)}
+    sim.states.copy_(init)
+    sim.t = 0
+    sim.autotune(T_probe=50, allow_skip=True, allow_sparse=True)
+    best = sim.plan()
+    keys = ("tile_rows", "tile_width", "temporal", "skip_static", "sparse")
+    sim.set_plan(**{k: best[k] for k in keys}, graph=1)
+    run(1)
+    torch.cuda.synchronize()
+    with StepTimer(torch, stream) as tm:
+        run(2)
+    ms2 = tm.ms() / 2
+    out["autotuned"] = {"plan": {k: best[k] for k in keys}, "ms_per_pass": round(ms2, 3),
+                        "value": cells * T / (ms2 / 1e3)}
+    log("[bench] uneven: dense %.2f ms (%.3e cell-updates/s, %.0f GB/s at 10 B), autotuned %s %.2f ms"
+        % (ms, rate, STOCH_BYTES_PER_CELL * rate / 1e9, out["autotuned"]["plan"], ms2))
+    return out
+
+
 def bench_rl(args, torch, fs, firegen):
     """RL air-tanker layer: 65536 envs of 20 x 20, 100 steps of random actions
     (agent move + water drop + fire step + reward + 5 x 5 observation)."""
@@ -401,6 +451,7 @@ def main():
     st.pop("sim")
     paper = None if args.no_extra else bench_paper_config(args, torch, fs, firegen)
     rl = None if args.no_extra else bench_rl(args, torch, fs, firegen)
+    uneven = None if args.no_extra else bench_uneven(args, torch, fs, firegen)
     relaxed = None if args.no_relaxed else bench_relaxed(args, torch, fs, firegen)
     if args.copy_calibration:
         a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
@@ -419,7 +470,7 @@ def main():
                       "n_env": int(batch.n_env), "H": 256, "W": 256, "T": st["T"], "plan": st["plan"],
                       "burning_cell_steps": st["burning"]},
            "roofline": st["roof"], "variants": variants, "dense_front": dense, "relaxed": relaxed,
-           "paper_setting": paper, "rl": rl,
+           "paper_setting": paper, "rl": rl, "uneven": uneven,
            "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
 
