@@ -339,7 +339,7 @@ def bench_rl(args, torch, fs, firegen):
     batch = firegen.uniform_batch(20, 20, n_env=n, ignitions=())
     params = firegen.Params(p_base=0.45)
     sim = fs.FireSim.from_batch(batch, params, seed=0)
-    sim.set_plan(tile_rows=2, tile_width=64, skip_static=1, graph=0)
+    sim.set_plan(tile_rows=4, tile_width=64, graph=0)
     env = fs.RLEnv(sim, obs_radius=2, drop_radius=1, water_capacity=20, max_steps=1000)
     steps = 100
     g = torch.Generator(device="cuda").manual_seed(0)
