@@ -6,7 +6,11 @@
  * grids ("envs") on one GPU: the stochastic step (Eqs. 1-4 and the
  * "Stochastic update" paragraph) and a relaxed mean-field step with its
  * adjoint (the "Deterministic (raw-probabilities) update", Eqs. 5-10) for
- * gradient-based calibration.
+ * gradient-based calibration.  Around the step: time-varying wind
+ * (sim_set_wind_series), retardant or water drops (sim_set_drop), per-step
+ * history (sim_step_history), the air-tanker reinforcement-learning scenario
+ * of section 4 (sim_rl_reset / sim_rl_step), launch plans with temporal
+ * blocking and sparse tiles, and an autotuner (sim_set_plan, sim_autotune).
  *
  * Conventions
  *  - Every pointer marked "device" is memory the caller allocated on the

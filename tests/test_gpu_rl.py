@@ -21,6 +21,7 @@ def _agents_np(env):
     ([(20, 20)] * 96, dict(graph=0)),
     ([(20, 20)] * 40 + [(33, 17), (64, 64), (7, 9)], dict(graph=0, tile_width=64, tile_rows=2,
                                                            skip_static=1, sparse=1)),
+    ([(20, 20)] * 30 + [(64, 64), (32, 48)], dict(graph=0, tile_width=64, temporal=4)),
 ])
 def test_rl_episodes_match_oracle(sizes, plan):
     batch = firegen.landscape_batch(31, sizes)
