@@ -557,3 +557,23 @@ def test_slope_angle_mode(per_cell_wind, plan):
     flat = oracle.Sim(batch, params.replace(slope_mode=0), seed=8)
     flat.step(T, threads=6)
     assert not np.array_equal(flat.states, ref.states)   # the mode matters here
+
+
+@pytest.mark.parametrize("plan", [dict(graph=1), dict(tile_rows=1, tile_width=64, skip_static=1, sparse=1)])
+def test_maximum_side_lengths(plan):
+    """Envs at the largest side the ABI accepts (32767) in either direction,
+    with drops at the far edges: bit-exact."""
+    sizes = [(6, 32767), (32767, 5), (1, 32767), (32767, 1), (3, 32764)]
+    batch = firegen.landscape_batch(81, sizes, class_sigma=3.0)
+    for e, (H, W) in enumerate(sizes):   # ignite along the long axis too
+        far = (H - 1, W - 1)
+        batch.ignitions = np.concatenate([batch.ignitions, np.array([[e, far[0] // 2, far[1] // 2],
+                                                                     [e, far[0], far[1]]], np.int32)])
+    params = firegen.Params(p_base=1.5, veg=_veg(81))
+    T = 20
+    act = firegen.random_actions(15, batch, T, p_none=0.6)
+    act[5] = ((batch.H - 1) << 16) | (batch.W - 1)      # a drop on every far corner
+    sim, ref, got, want = _run_both(batch, params, T, seed=12, actions=act, plan=plan)
+    assert np.array_equal(sim.states.cpu().numpy(), ref.states)
+    assert np.array_equal(got, want)
+    assert want.sum() > 0
