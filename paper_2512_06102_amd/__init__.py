@@ -5,6 +5,19 @@ include/firesim.h).  Python only marshals arguments: PyTorch provides device
 memory and the current stream; every step of the model runs in the library's
 kernels.  Importing works without a GPU; creating a simulator needs the built
 library and a GPU, and fails loudly otherwise.
+
+    sim = FireSim.from_batch(batch, params, seed=0)    # batch: packed envs (firegen.Batch)
+    counts = sim.step(200, counts=True)                 # [200, n_env] burning cells
+    sim.autotune(T_probe=50)                            # pick the fastest launch plan
+    hist, _ = sim.step_history(20)                      # every state of 20 steps
+
+    U, B = sim.relaxed_init()                           # relaxed (mean-field) path
+    theta, losses = calibrate(sim, target_scar, T=100, theta0=theta0, loss="bce",
+                              loss_kw={"pool": 8})      # Adam through the adjoint
+
+    env = RLEnv(sim, obs_radius=2, water_capacity=10)   # air-tanker scenario
+    obs, done = env.reset(episode=0)
+    obs, reward, done = env.step(actions)               # int32 [n_env]: move | valve << 4
 """
 from __future__ import annotations
 
