@@ -18,12 +18,14 @@
 // gamma(v) = alpha_gamma g(v), g = (1 + veg[class]) (1 + den), to the 17
 // parameters.
 //
-// The forward works on 32 x 16 tiles, the adjoint on 32 x 8 tiles (256 lanes).
+// The forward works on 32 x 16 tiles, the adjoint on 32 x 13 tiles (256 lanes).
 // The adjoint's transpose stencil (Bbar(u) gathers from the targets around
 // u, and those need B two cells away) is done in one launch per step: the
-// tile stages B, g and E with a two-cell halo in LDS, phase 1 computes c_k
-// and the source-side fuel adjoint d_k for the tile plus a one-cell ring
-// into LDS, phase 2 gathers them for the tile's own cells.  Parameter
+// tile stages B, g and E (and per-cell wind) with a two-cell halo in LDS;
+// phase 1 evaluates every target of the tile plus a one-cell ring and adds
+// c_k and the source-side fuel adjoint d_k into LDS slots of the sources in
+// the tile (LDS atomics: the summation order of a slot is not fixed);
+// phase 2 finishes the tile's own cells.  Parameter
 // gradients are summed per lane, reduced per workgroup, and added to one of
 // 64 fp64 stripes with atomics; a last kernel sums the stripes.
 //
@@ -250,13 +252,35 @@ __global__ __launch_bounds__(256) void relaxed_fwd_kernel(
     }
 }
 
-// One adjoint step on a 32 x 8 tile: (U_t, B_t), (Ubar_{t+1}, Bbar_{t+1})
+// Atomic add to a double in LDS (ds_add_f64).
+__device__ __forceinline__ void lds_add(double* p, double v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Wind exponent of direction k at a staged source cell (per env, or from the
+// staged per-cell wind).
+template <bool WC>
+__device__ __forceinline__ float staged_wind(int k, const float* ew, const float* sW, int s, int nx,
+                                             const RelaxedArgs& A)
+{
+    if constexpr (WC)
+        return wind_exponent(k, A.alpha_w1, A.alpha_w2, sW[s], sW[nx + s], sW[2 * nx + s]);
+    else
+        return ew[k];
+}
+
+// One adjoint step on a 32 x 13 tile: (U_t, B_t), (Ubar_{t+1}, Bbar_{t+1})
 // -> (Ubar_t, Bbar_t), and the step's contribution to the parameter gradient.
 // Both forms reduce to per-edge phibar_k and per-target gammabar:
 //   FORM 0: ybar_k = Pbar B_k E_k exp(-y_k), phibar_k = ybar_k gamma,
 //           gammabar = sum_k ybar_k phi_k, c_k = Pbar q_k E_k;
 //   FORM 1: lambdabar = Pbar gamma (1 - P), phibar_k = lambdabar B_k,
 //           gammabar = Pbar lambda (1 - P), c_k = lambdabar phi_k.
+// The targets are the tile and its one-cell ring (34 x 15 = 510, two passes
+// of 256 lanes); each target adds c_k and the source-side fuel adjoint to
+// the LDS slots of its sources inside the tile, so per tile cell only two
+// doubles of LDS are needed and occupancy is set by registers.
 template <bool WC, int FORM>
 __global__ __launch_bounds__(256) void relaxed_bwd_kernel(
     const RelaxedTile* __restrict__ tiles, const EnvDev* __restrict__ envs, const float* __restrict__ g,
@@ -266,26 +290,32 @@ __global__ __launch_bounds__(256) void relaxed_bwd_kernel(
     double* __restrict__ gU0, double* __restrict__ gB0, double* __restrict__ stripes,
     const float* __restrict__ env_wind)
 {
-    constexpr int XW = BW + 4, XH = BH + 4;  // two-cell halo: sources of the ring
-    constexpr int EW = BW + 2, EH = BH + 2;  // one-cell ring: targets gathered by the tile
-    constexpr int NE = EW * EH;
-    __shared__ double sB[XH * XW];
-    __shared__ float sg[XH * XW], sE[XH * XW];
-    __shared__ double sC[8 * NE], sD[8 * NE];
-    __shared__ double sgt[BW * BH];
+    constexpr int XW = BW + 4, XH = BH + 4;  // staged: the targets' sources
+    constexpr int EW = BW + 2, EH = BH + 2;  // targets: the tile and its ring
+    constexpr int NX = XW * XH, NE = EW * EH, NT = BW * BH;
+    __shared__ double sB[NX];
+    __shared__ float sg[NX], sE[NX];
+    __shared__ float sW[WC ? 3 * NX : 1];      // per-cell wind V, Vx, Vy of the staged cells
+    __shared__ double sBbar[NT], sFbar[NT];  // per tile cell: sum_k c_k, fuel adjoint
     __shared__ float ew[8];
     __shared__ double sred[4][17];
     const RelaxedTile td = tiles[blockIdx.x];
     const EnvDev ed = envs[td.env];
     const int H = ed.H, W = ed.W, tid = threadIdx.x;
-    for (int idx = tid; idx < XH * XW; idx += 256) {
+    for (int idx = tid; idx < NX; idx += 256) {
         const int gi = td.r0 - 2 + idx / XW, gj = td.c0 - 2 + idx % XW;
         const bool in = gi >= 0 && gi < H && gj >= 0 && gj < W;
         const int64_t v = ed.offset + (int64_t)gi * W + gj;
         sB[idx] = in ? B[v] : 0.0;
         sg[idx] = in ? g[v] : 0.0f;
         sE[idx] = in ? E[v] : 0.0f;
+        if constexpr (WC) {
+            sW[idx] = in ? wind[v] : 0.0f;
+            sW[NX + idx] = in ? wind[n_cells + v] : 0.0f;
+            sW[2 * NX + idx] = in ? wind[2 * n_cells + v] : 0.0f;
+        }
     }
+    for (int idx = tid; idx < NT; idx += 256) sBbar[idx] = sFbar[idx] = 0.0;
     const float3 wenv = env_wind_of(ed, env_wind, td.env);  // this step's per-env wind
     if (!WC && tid < 8) ew[tid] = wind_exponent(tid, A.alpha_w1, A.alpha_w2, wenv.x, wenv.y, wenv.z);
     __syncthreads();
@@ -293,63 +323,62 @@ __global__ __launch_bounds__(256) void relaxed_bwd_kernel(
     double acc[17];
 #pragma unroll
     for (int j = 0; j < 17; ++j) acc[j] = 0.0;
+    double xbar_sin = 0.0;  // per-env wind: sum of xbar sin(k pi / 4)
     const double p_base = A.p_base, a_gamma = A.alpha_gamma;
 
-    // phase 1: every target of the tile and its one-cell ring
+    // phase 1: every target of the tile and its ring
     for (int idx = tid; idx < NE; idx += 256) {
         const int er = idx / EW, ec = idx % EW;
         const int gi = td.r0 - 1 + er, gj = td.c0 - 1 + ec;
-        const bool in = gi >= 0 && gi < H && gj >= 0 && gj < W;
-        if (!in) {
-#pragma unroll
-            for (int k = 0; k < 8; ++k) sC[k * NE + idx] = sD[k * NE + idx] = 0.0;
-            continue;
-        }
+        if (gi < 0 || gi >= H || gj < 0 || gj >= W) continue;
         const int64_t v = ed.offset + (int64_t)gi * W + gj;
-        const int a = er + 1, b = ec + 1;
+        const int a = er + 1, b = ec + 1;  // staged coordinates of v
         const double Uv = U[v];
         const double gU = gU1[v], gB = gB1[v];
         const double nbar = gB - gU;
         const double Pbar = nbar * Uv;
         const float gv = sg[a * XW + b], Ev = sE[a * XW + b];
         const float gam = A.alpha_gamma * gv;
-        float q[8], em[8], ex[8], ph[8];
-        double Bs[8];
+        float q[8], em[8], ex[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const int s = (a - kDRow[k]) * XW + (b - kDCol[k]);
             const int ui = gi - kDRow[k], uj = gj - kDCol[k];
-            Bs[k] = sB[s];
             q[k] = 0.0f;
             em[k] = 1.0f;
             ex[k] = 0.0f;
-            ph[k] = 0.0f;
-            if (ui >= 0 && ui < H && uj >= 0 && uj < W && (Pbar != 0.0 || Bs[k] != 0.0)) {
-                const int64_t u = v - (int64_t)kDRow[k] * W - kDCol[k];
-                const float x = source_wind<WC>(k, ew, wind, n_cells, u, A) +
+            if (ui >= 0 && ui < H && uj >= 0 && uj < W && (Pbar != 0.0 || sB[s] != 0.0)) {
+                const float x = staged_wind<WC>(k, ew, sW, s, NX, A) +
                                 A.alpha_s * slope_of((Ev - sE[s]) * ((k & 1) ? A.inv_diag : A.inv_orth), A);
                 ex[k] = hexp(x);
-                ph[k] = A.p_base * sg[s] * ex[k];
                 if constexpr (FORM == 0) {
-                    const float y = gam * ph[k];
-                    const float2 qe = q_and_survival(y);
+                    const float2 qe = q_and_survival(gam * (A.p_base * sg[s] * ex[k]));
                     q[k] = qe.x;
                     em[k] = qe.y;
                 }
             }
         }
-        // FORM 0: exclusive products from stored prefix and a running suffix
-        double pre[9];
+        // The later loops read B, g (and E) of the sources from LDS again
+        // instead of keeping them in registers across the loops.
+        asm volatile("" ::: "memory");
+        // FORM 0: exclusive products from stored prefixes and a running suffix
+        double pre[8];
         double P, gam_bar = 0.0, lbar = 0.0;
         if constexpr (FORM == 0) {
-            pre[0] = 1.0;
+            double run = 1.0;
 #pragma unroll
-            for (int k = 0; k < 8; ++k) pre[k + 1] = pre[k] * (1.0 - (double)q[k] * Bs[k]);
-            P = 1.0 - pre[8];
+            for (int k = 0; k < 8; ++k) {
+                pre[k] = run;
+                run = run * (1.0 - (double)q[k] * sB[(a - kDRow[k]) * XW + (b - kDCol[k])]);
+            }
+            P = 1.0 - run;
         } else {
             double lam = 0.0;
 #pragma unroll
-            for (int k = 0; k < 8; ++k) lam = lam + (double)ph[k] * Bs[k];
+            for (int k = 0; k < 8; ++k) {
+                const int s = (a - kDRow[k]) * XW + (b - kDCol[k]);
+                lam = lam + (double)(A.p_base * sg[s] * ex[k]) * sB[s];
+            }
             const double surv = exp(-(double)gam * lam);
             P = -expm1(-(double)gam * lam);
             lbar = Pbar * (double)gam * surv;
@@ -357,41 +386,45 @@ __global__ __launch_bounds__(256) void relaxed_bwd_kernel(
         }
         const bool interior = er >= 1 && er <= BH && ec >= 1 && ec <= BW;
         double suf = 1.0;
+        asm volatile("" ::: "memory");
 #pragma unroll
         for (int k = 7; k >= 0; --k) {
+            const int s = (a - kDRow[k]) * XW + (b - kDCol[k]);
+            const double Bu = sB[s];
+            const float ph = A.p_base * sg[s] * ex[k];
             double c, phibar;
             if constexpr (FORM == 0) {
                 const double excl = pre[k] * suf;
-                suf = suf * (1.0 - (double)q[k] * Bs[k]);
-                const double ybar = Pbar * Bs[k] * excl * (double)em[k];  // qbar dq/dy
+                suf = suf * (1.0 - (double)q[k] * Bu);
+                const double ybar = Pbar * Bu * excl * (double)em[k];  // qbar dq/dy
                 c = Pbar * (double)q[k] * excl;
                 phibar = ybar * (double)gam;
-                gam_bar += ybar * (double)ph[k];
+                gam_bar += ybar * (double)ph;
             } else {
-                c = lbar * (double)ph[k];
-                phibar = lbar * Bs[k];
+                c = lbar * (double)ph;
+                phibar = lbar * Bu;
             }
-            sC[k * NE + idx] = c;
-            sD[k * NE + idx] = phibar * p_base * (double)ex[k];  // -> gbar(source)
+            // the source u = v - D_k, if it is a cell of the tile
+            const int tr = er - 1 - kDRow[k], tc = ec - 1 - kDCol[k];
+            if (tr >= 0 && tr < BH && tc >= 0 && tc < BW) {
+                const int t = tr * BW + tc;
+                if (c != 0.0) lds_add(&sBbar[t], c);
+                if (phibar != 0.0) lds_add(&sFbar[t], phibar * p_base * (double)ex[k]);  // -> gbar(source)
+            }
             if (interior && phibar != 0.0) {
-                const int s = (a - kDRow[k]) * XW + (b - kDCol[k]);
-                const int64_t u = v - (int64_t)kDRow[k] * W - kDCol[k];
                 const double gu = sg[s];
                 const double phi = p_base * gu * (double)ex[k];
-                float V, Vx, Vy;
-                if constexpr (WC) {
-                    V = wind[u];
-                    Vx = wind[n_cells + u];
-                    Vy = wind[2 * n_cells + u];
-                } else {
-                    V = wenv.x;
-                    Vx = wenv.y;
-                    Vy = wenv.z;
-                }
                 const double xbar = phibar * phi;
                 acc[0] += phibar * gu * (double)ex[k];
-                acc[1] += xbar * (double)V;
-                acc[2] += xbar * (double)((kCos[k] * Vx + kSin[k] * Vy) - V);
+                if constexpr (WC) {
+                    const float V = sW[s], Vx = sW[NX + s], Vy = sW[2 * NX + s];
+                    acc[1] += xbar * (double)V;
+                    acc[2] += xbar * (double)((kCos[k] * Vx + kSin[k] * Vy) - V);
+                } else {  // the env's wind is common to the tile: factored out below
+                    acc[1] += xbar;
+                    acc[2] += xbar * (double)kCos[k];
+                    xbar_sin += xbar * (double)kSin[k];
+                }
                 acc[3] += xbar * (double)slope_of((Ev - sE[s]) * ((k & 1) ? A.inv_diag : A.inv_orth), A);
             }
         }
@@ -399,30 +432,29 @@ __global__ __launch_bounds__(256) void relaxed_bwd_kernel(
             gU0[v] = gU + nbar * P;
             acc[4] += gam_bar * (double)gv;
             acc[5] += gB * sB[a * XW + b];
-            sgt[(er - 1) * BW + (ec - 1)] = gam_bar * a_gamma;
+            if (gam_bar != 0.0) lds_add(&sFbar[(er - 1) * BW + (ec - 1)], gam_bar * a_gamma);
         }
     }
     __syncthreads();
 
-    // phase 2: gather the transpose stencil for the tile's own cells
-    for (int idx = tid; idx < BW * BH; idx += 256) {
+    // phase 2: the tile's own cells
+    for (int idx = tid; idx < NT; idx += 256) {
         const int rr = idx / BW, cc = idx % BW;
         const int gi = td.r0 + rr, gj = td.c0 + cc;
         if (gi >= H || gj >= W) continue;
         const int64_t u = ed.offset + (int64_t)gi * W + gj;
-        const int er = rr + 1, ec = cc + 1;
-        double bsum = 0.0, dsum = 0.0;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int e = (er + kDRow[k]) * EW + (ec + kDCol[k]);
-            bsum += sC[k * NE + e];
-            dsum += sD[k * NE + e];
-        }
-        gB0[u] = (double)A.p_continue * gB1[u] + bsum;
-        const double gb = (sgt[idx] + dsum) * (1.0 + (double)den[u]);
+        gB0[u] = (double)A.p_continue * gB1[u] + sBbar[idx];
+        const double gb = sFbar[idx] * (1.0 + (double)den[u]);
         const int c = cls[u];
 #pragma unroll
         for (int j = 0; j < 11; ++j) acc[6 + j] += (c == j) ? gb : 0.0;
+    }
+
+    if constexpr (!WC) {
+        // acc[1] and acc[2] hold the sums of xbar and xbar cos(k pi / 4)
+        const double V = wenv.x, Vx = wenv.y, Vy = wenv.z, s0 = acc[1];
+        acc[1] = s0 * V;
+        acc[2] = (acc[2] * Vx + xbar_sin * Vy) - s0 * V;
     }
 
     // workgroup reduction of the 17 partial sums, then one fp64 stripe
