@@ -11,9 +11,9 @@
 
 namespace firesim {
 
-// Tiles of the relaxed kernels: forward 32 x 16 cells, adjoint 32 x 13 cells.
+// Tiles of the relaxed kernels: forward 32 x 16 cells, adjoint 32 x 20 cells.
 constexpr int kRelaxTW = 32, kRelaxTH = 16;
-constexpr int kRelaxBW = 32, kRelaxBH = 13;
+constexpr int kRelaxBW = 32, kRelaxBH = 20;
 constexpr int kGradStripes = 64;  // fp64 partial-sum rows of the parameter gradient
 
 struct RelaxedTile {
