@@ -14,9 +14,10 @@ Reported beside it, each in its own object:
                 cell evaluates its neighbourhood each step;
   relaxed     - the relaxed forward + adjoint on 256 envs of 128 x 128 (T 100)
                 and on one 2048 x 2048 env (T 100), checkpoints every 10;
-  paper_setting, rl, uneven - the paper's 64 x 64^2 vectorised setting, the
-                RL layer on 65536 envs of 20 x 20, and the 4096-env uneven
-                batch with drops;
+  paper_setting, rl, uneven, large - the paper's 64 x 64^2 vectorised
+                setting, the RL layer on 65536 envs of 20 x 20, the 4096-env
+                uneven batch with drops, and 8 envs of 2048 x 2048 with
+                per-cell wind (1000 steps);
   cpu_baseline - the CPU oracle on the same stochastic workload.
 
 Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -37,6 +38,7 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 # 256 CUs x 64 lanes x 2.4 GHz: one non-packed 32-bit VALU op per lane per cycle
 ALU_PEAK_GOPS = 256 * 64 * 2.4
 STOCH_BYTES_PER_CELL = 10      # state r/w 2 B + fuel 4 B + elevation 4 B per cell-update
+STOCH_WIND_CELL_BYTES = 12     # per-cell wind adds V, Vx, Vy (3 x 4 B) per cell-update
 # relaxed, fp64 state: forward 40 B (U,B r/w 32 + fuel, elevation 8); adjoint
 # 61 B (U,B 16, adjoint r/w 32, fuel, elevation, density 12, class 1); the
 # forward is recomputed from checkpoints (40 B) and every 10th state stored (1.6 B)
@@ -361,6 +363,52 @@ def bench_rl(args, torch, fs, firegen):
             "cell_updates_per_s": rate * 400}
 
 
+def bench_large(args, torch, fs, firegen):
+    """8 envs of 2048 x 2048 with fractal terrain (0-2000 m), 11-class land
+    cover and per-cell wind, 1000 steps: the dense plan (22 algorithmic bytes
+    per cell-update) and the autotuner's choice."""
+    batch, params, T, seed = firegen.workload_large()
+    sim = fs.FireSim.from_batch(batch, params, seed=seed)
+    init = sim.states.clone()
+    stream = torch.cuda.current_stream()
+    cells = float(batch.n_cells)
+    bpc = STOCH_BYTES_PER_CELL + STOCH_WIND_CELL_BYTES
+
+    def run():
+        sim.states.copy_(init)
+        sim.t = 0
+        sim.step(T)
+
+    out = {"workload": "8 envs x 2048x2048, fractal terrain 0-2000 m, 11-class land cover, per-cell "
+                       "wind, 1000 steps", "unit": "cell-updates/s", "algorithmic_bytes_per_cell": bpc}
+    sim.set_plan(tile_rows=4, tile_width=256, temporal=1, skip_static=0, sparse=0, graph=1)
+    run()
+    torch.cuda.synchronize()
+    with StepTimer(torch, stream) as tm:
+        run()
+    ms = tm.ms()
+    rate = cells * T / (ms / 1e3)
+    out["dense"] = {"ms_per_pass": round(ms, 3), "value": rate,
+                    "hbm_GBs_at_22B": round(bpc * rate / 1e9, 1),
+                    "hbm_frac_at_22B": round(bpc * rate / 1e9 / HBM_PEAK_GBS, 4)}
+    sim.states.copy_(init)
+    sim.t = 0
+    sim.autotune(T_probe=50, allow_skip=True, allow_sparse=True)
+    best = sim.plan()
+    keys = ("tile_rows", "tile_width", "temporal", "skip_static", "sparse")
+    sim.set_plan(**{k: best[k] for k in keys}, graph=1)
+    run()
+    torch.cuda.synchronize()
+    with StepTimer(torch, stream) as tm:
+        run()
+    ms2 = tm.ms()
+    out["autotuned"] = {"plan": {k: best[k] for k in keys}, "ms_per_pass": round(ms2, 3),
+                        "value": cells * T / (ms2 / 1e3)}
+    log("[bench] large: dense %.2f ms (%.3e cell-updates/s, %.0f GB/s at 22 B), autotuned %s %.2f ms"
+        % (ms, rate, bpc * rate / 1e9, out["autotuned"]["plan"], ms2))
+    return out
+
+
 def relaxed_case(args, torch, fs, firegen, batch, params, T, k, label):
     sim = fs.FireSim.from_batch(batch, params, seed=0)
     sim.step(T)   # target scar: a stochastic run at the known parameters
@@ -452,6 +500,7 @@ def main():
     paper = None if args.no_extra else bench_paper_config(args, torch, fs, firegen)
     rl = None if args.no_extra else bench_rl(args, torch, fs, firegen)
     uneven = None if args.no_extra else bench_uneven(args, torch, fs, firegen)
+    large = None if args.no_extra else bench_large(args, torch, fs, firegen)
     relaxed = None if args.no_relaxed else bench_relaxed(args, torch, fs, firegen)
     if args.copy_calibration:
         a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
@@ -470,7 +519,7 @@ def main():
                       "n_env": int(batch.n_env), "H": 256, "W": 256, "T": st["T"], "plan": st["plan"],
                       "burning_cell_steps": st["burning"]},
            "roofline": st["roof"], "variants": variants, "dense_front": dense, "relaxed": relaxed,
-           "paper_setting": paper, "rl": rl, "uneven": uneven,
+           "paper_setting": paper, "rl": rl, "uneven": uneven, "large": large,
            "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
 
