@@ -50,7 +50,8 @@ RELAXED_WIND_CELL_BYTES = 3 * 12
 # the ignition probability 26 (gamma 1, product 1, exp 23, 1-e 1), one draw 29
 # (a quarter of a Philox4x32-10 block 25, uniform 2, compare 2)
 OPS_PHI, OPS_PROB, OPS_DRAW = 30, 26, 29
-KERNEL_SOURCES = ("paper_2512_06102_amd/csrc/stoch.hip", "paper_2512_06102_amd/csrc/devmath.hpp")
+KERNEL_SOURCES = ("paper_2512_06102_amd/csrc/stoch.hip", "paper_2512_06102_amd/csrc/stepcell.hpp",
+                  "paper_2512_06102_amd/csrc/devmath.hpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stoch_step_batch256_traffic.json")
 
 
@@ -336,31 +337,39 @@ def bench_uneven(args, torch, fs, firegen):
 
 def bench_rl(args, torch, fs, firegen):
     """RL air-tanker layer: 65536 envs of 20 x 20, 100 steps of random actions
-    (agent move + water drop + fire step + reward + 5 x 5 observation)."""
+    (agent move + water drop + fire step + reward + 5 x 5 observation), as one
+    launch per step (the env resident in LDS) and as separate act / step /
+    observation launches."""
     n = 65536
     batch = firegen.uniform_batch(20, 20, n_env=n, ignitions=())
     params = firegen.Params(p_base=0.45)
     sim = fs.FireSim.from_batch(batch, params, seed=0)
     sim.set_plan(tile_rows=4, tile_width=64, graph=0)
-    env = fs.RLEnv(sim, obs_radius=2, drop_radius=1, water_capacity=20, max_steps=1000)
     steps = 100
     g = torch.Generator(device="cuda").manual_seed(0)
     acts = torch.randint(0, 32, (steps, n), dtype=torch.int32, device="cuda", generator=g)
-    env.reset(episode=0)
-    for i in range(5):
-        env.step(acts[i])
-    torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
-    env.reset(episode=1)
-    with StepTimer(torch, stream) as tm:
-        for i in range(steps):
+    ms = {}
+    for single in (True, False):
+        env = fs.RLEnv(sim, obs_radius=2, drop_radius=1, water_capacity=20, max_steps=1000,
+                       single_launch=single)
+        env.reset(episode=0)
+        for i in range(5):
             env.step(acts[i])
-    ms = tm.ms()
-    rate = n * steps / (ms / 1e3)
-    log("[bench] rl: %.3f ms per step of %d envs, %.3e env-steps/s" % (ms / steps, n, rate))
+        torch.cuda.synchronize()
+        env.reset(episode=1)
+        with StepTimer(torch, stream) as tm:
+            for i in range(steps):
+                env.step(acts[i])
+        ms[single] = tm.ms()
+    rate = n * steps / (ms[True] / 1e3)
+    log("[bench] rl: %.3f ms per step of %d envs (one launch), %.3f ms (separate launches), %.3e env-steps/s"
+        % (ms[True] / steps, n, ms[False] / steps, rate))
     return {"workload": "65536 envs x 20x20, 100 RL steps, random moves and valve, 5x5 observations",
-            "value": rate, "unit": "env-steps/s", "ms_per_step": round(ms / steps, 4),
-            "cell_updates_per_s": rate * 400}
+            "value": rate, "unit": "env-steps/s", "ms_per_step": round(ms[True] / steps, 4),
+            "cell_updates_per_s": rate * 400,
+            "separate_launches": {"ms_per_step": round(ms[False] / steps, 4),
+                                  "value": n * steps / (ms[False] / 1e3)}}
 
 
 def bench_large(args, torch, fs, firegen):

@@ -52,9 +52,14 @@ class Agent:
 class RLEnvs:
     """Batched RL envs over an oracle.Sim."""
 
-    def __init__(self, batch, params, seed: int, cfg: Config):
+    def __init__(self, batch, params, seed: int, cfg: Config, wind_env_series=None, wind_cell_series=None):
         self.batch, self.cfg, self.seed = batch, cfg, int(seed)
         self.sim = oracle.Sim(batch, params, seed=seed)
+        self.wind = {}  # optional wind series of the fire steps, row = absolute step
+        if wind_env_series is not None:
+            self.wind["wind_env_series"] = wind_env_series
+        if wind_cell_series is not None:
+            self.wind["wind_cell_series"] = wind_cell_series
         self.agents = [Agent() for _ in range(batch.n_env)]
         self.burnable = ((batch.unburnable_mask >> batch.cls.astype(np.int64)) & 1) == 0
 
@@ -114,7 +119,8 @@ class RLEnvs:
             if valve and a.water > 0:
                 drops[0, e] = (a.row << 16) | a.col
                 a.water -= 1
-        counts = self.sim.step(1, actions=drops, counts=True, drop_mode=1, drop_radius=cfg.drop_radius)[0]
+        counts = self.sim.step(1, actions=drops, counts=True, drop_mode=1, drop_radius=cfg.drop_radius,
+                               **self.wind)[0]
         reward = np.zeros(b.n_env, np.float32)
         for e, a in enumerate(self.agents):
             if a.done:

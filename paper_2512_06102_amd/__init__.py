@@ -394,7 +394,8 @@ class FireSim:
 class SimRlConfig(ctypes.Structure):
     _fields_ = [("obs_radius", ctypes.c_int32), ("drop_radius", ctypes.c_int32),
                 ("water_capacity", ctypes.c_int32), ("max_steps", ctypes.c_int32),
-                ("burn_penalty", ctypes.c_float), ("extinguish_bonus", ctypes.c_float)]
+                ("burn_penalty", ctypes.c_float), ("extinguish_bonus", ctypes.c_float),
+                ("single_launch", ctypes.c_int32)]
 
 
 class RLEnv:
@@ -405,13 +406,20 @@ class RLEnv:
 
     Actions: int32 [n_env], bits 0-3 move (0 stay, 1..8 direction k = move-1,
     k = 0 east, counter-clockwise), bit 4 opens the valve.  Agents: int32
-    [n_env, 8] (row, col, water, steps, done, last_count, pad, pad)."""
+    [n_env, 8] (row, col, water, steps, done, last_count, pad, pad).
+
+    single_launch: each step is one kernel launch when every env fits it
+    (W % 4 == 0 and H * W <= 4096: the env's state is held in LDS and
+    stepped in place); otherwise, or with single_launch=False, the act, step
+    (under the simulator's launch plan) and observation kernels run apart.
+    Both give the same results."""
 
     def __init__(self, sim: "FireSim", obs_radius: int = 2, drop_radius: int = 1, water_capacity: int = 10,
-                 max_steps: int = 100, burn_penalty: float = 0.1, extinguish_bonus: float = 10.0):
+                 max_steps: int = 100, burn_penalty: float = 0.1, extinguish_bonus: float = 10.0,
+                 single_launch: bool = True):
         self.sim = sim
         self.cfg = SimRlConfig(obs_radius, drop_radius, water_capacity, max_steps, burn_penalty,
-                               extinguish_bonus)
+                               extinguish_bonus, int(bool(single_launch)))
         dev = sim.device
         side = 2 * obs_radius + 1
         self.agents = torch.zeros((sim.n_env, 8), dtype=torch.int32, device=dev)

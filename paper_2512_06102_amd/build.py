@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfiresim.so")
 SOURCES = ["capi.cpp", "stoch.hip", "relaxed.hip", "rl.hip"]
-HEADERS = ["devmath.hpp", "internal.hpp", "relaxed.hpp", "rl.hpp"]
+HEADERS = ["devmath.hpp", "internal.hpp", "stepcell.hpp", "relaxed.hpp", "rl.hpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

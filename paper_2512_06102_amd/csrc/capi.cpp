@@ -57,6 +57,7 @@ struct sim_handle {
     // reinforcement-learning layer: drop row and burning counts of one step
     int32_t* d_rl_drop = nullptr;
     int32_t* d_rl_counts = nullptr;
+    RlFusedShape rl_shape;  // the fused RL step's LDS layout (fits: every env fits it)
 
     EnvDev* d_envs = nullptr;
     float* d_g = nullptr;
@@ -384,6 +385,19 @@ int sim_init(sim_handle** out, const sim_params* p, int32_t n_env, const sim_env
     for (const sim_env& v : h->envs)
         if (v.W % 4 != 0 || v.offset % 4 != 0) h->aligned = false;
     if (h->wind_cell && n_cells % 4 != 0) h->aligned = false;
+    if (h->aligned) {
+        int64_t max_cells = 0, max_frame = 0;
+        for (const sim_env& v : h->envs) {
+            max_cells = std::max<int64_t>(max_cells, (int64_t)v.H * v.W);
+            max_frame = std::max<int64_t>(max_frame, ((int64_t)v.H + 2) * (v.W / 4 + 2));
+        }
+        RlFusedShape& rs = h->rl_shape;
+        if (max_cells <= 65536 && max_frame <= (int64_t)kRlFusedMaxLds) {
+            rs.frame_cap = (int32_t)((max_frame + 3) & ~3);
+            rs.cell_cap = (int32_t)max_cells;
+            rs.fits = rl_fused_lds_bytes(rs) <= kRlFusedMaxLds;
+        }
+    }
 
     std::vector<EnvDev> ed(n_env);
     for (int32_t e = 0; e < n_env; ++e)
@@ -566,6 +580,15 @@ int sim_rl_step(sim_handle* h, const sim_rl_config* cfg, uint8_t* states, sim_rl
     hipStream_t s = (hipStream_t)stream;
     if ((rc = ensure_tiles(h)) != SIM_OK) return rc;
     RlAgent* ag = reinterpret_cast<RlAgent*>(agents);
+    if (cfg->single_launch && h->rl_shape.fits) {
+        StepLaunch L = step_launch(h);
+        L.args.drop_mode = SIM_DROP_WATER;
+        L.args.drop_radius = cfg->drop_radius;
+        HIP_OR_FAIL(h, launch_rl_step_fused(s, h->d_envs, h->n_env, L.fields, L.args, h->rl_shape, states, ag,
+                                            actions, rl_dev(cfg), (uint32_t)h->t, obs, reward, done));
+        h->t += 1;
+        return SIM_OK;
+    }
     const int32_t water[2] = {SIM_DROP_WATER, cfg->drop_radius};
     HIP_OR_FAIL(h, launch_set_u32(s, h->d_t, (uint32_t)h->t));
     HIP_OR_FAIL(h, launch_rl_act(s, h->d_envs, h->n_env, ag, actions, h->d_rl_drop));

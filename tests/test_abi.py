@@ -36,9 +36,10 @@ def test_struct_layout_matches_header():
 #include <stddef.h>
 #include "firesim.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(sim_params), sizeof(sim_env), sizeof(sim_plan),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(sim_params), sizeof(sim_env), sizeof(sim_plan),
          offsetof(sim_params, veg), offsetof(sim_params, unburnable_mask),
-         offsetof(sim_env, env_id), offsetof(sim_env, Vy));
+         offsetof(sim_env, env_id), offsetof(sim_env, Vy), sizeof(sim_rl_config),
+         offsetof(sim_rl_config, single_launch));
   return 0;
 }
 """
@@ -50,7 +51,7 @@ int main(void) {
     got = [int(x) for x in subprocess.check_output([exe]).split()]
     want = [ctypes.sizeof(fs.SimParams), ctypes.sizeof(fs.SimEnv), ctypes.sizeof(fs.SimPlan),
             fs.SimParams.veg.offset, fs.SimParams.unburnable_mask.offset, fs.SimEnv.env_id.offset,
-            fs.SimEnv.Vy.offset]
+            fs.SimEnv.Vy.offset, ctypes.sizeof(fs.SimRlConfig), fs.SimRlConfig.single_launch.offset]
     assert got == want
 
 

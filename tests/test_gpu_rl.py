@@ -17,23 +17,39 @@ def _agents_np(env):
     return np.array([[a.row, a.col, a.water, a.steps, a.done, a.last_count] for a in env.agents], np.int32)
 
 
-@pytest.mark.parametrize("sizes,plan", [
-    ([(20, 20)] * 96, dict(graph=0)),
+# Batches: 20 x 20 envs (one launch per step holds 2 dwords per lane); envs
+# with W % 4 != 0 (the separate launches, whatever single_launch says); up to
+# 64 x 64 (16 dwords per lane); 32 x 32 (4 dwords per lane); per-cell wind;
+# per-env and per-cell wind series.
+@pytest.mark.parametrize("single_launch", [True, False])
+@pytest.mark.parametrize("sizes,plan,wind", [
+    ([(20, 20)] * 96, dict(graph=0), None),
     ([(20, 20)] * 40 + [(33, 17), (64, 64), (7, 9)], dict(graph=0, tile_width=64, tile_rows=2,
-                                                           skip_static=1, sparse=1)),
-    ([(20, 20)] * 30 + [(64, 64), (32, 48)], dict(graph=0, tile_width=64, temporal=4)),
+                                                           skip_static=1, sparse=1), None),
+    ([(20, 20)] * 30 + [(64, 64), (32, 48)], dict(graph=0, tile_width=64, temporal=4), None),
+    ([(32, 32)] * 12 + [(20, 20)] * 12, dict(graph=0), "cell"),
+    ([(20, 20)] * 24 + [(28, 16)], dict(graph=0), "env_series"),
+    ([(20, 20)] * 24 + [(12, 36)], dict(graph=0), "cell_series"),
 ])
-def test_rl_episodes_match_oracle(sizes, plan):
-    batch = firegen.landscape_batch(31, sizes)
+def test_rl_episodes_match_oracle(sizes, plan, wind, single_launch):
+    batch = firegen.landscape_batch(31, sizes, per_cell_wind=wind in ("cell", "cell_series"))
     params = firegen.Params(p_base=0.45, veg=tuple(firegen.veg_table(np.random.default_rng(31))))
     cfg = rl.Config(obs_radius=3, drop_radius=1, water_capacity=6, max_steps=25, burn_penalty=0.1,
                     extinguish_bonus=10.0)
-    ref = rl.RLEnvs(batch, params, 77, cfg)
+    ser = None
+    if wind in ("env_series", "cell_series"):
+        ser = firegen.wind_series(8, batch, 40, per_cell=wind == "cell_series", speed_step=1.0, turn_step=0.3)
+    ref = rl.RLEnvs(batch, params, 77, cfg, wind_env_series=ser if wind == "env_series" else None,
+                    wind_cell_series=ser if wind == "cell_series" else None)
     sim = fs.FireSim.from_batch(batch, params, seed=77)
     sim.set_plan(**plan)
+    if ser is not None:
+        dev = torch.from_numpy(ser).cuda()
+        sim.set_wind_series(cell_series=dev) if wind == "cell_series" else sim.set_wind_series(env_series=dev)
     env = fs.RLEnv(sim, obs_radius=cfg.obs_radius, drop_radius=cfg.drop_radius,
                    water_capacity=cfg.water_capacity, max_steps=cfg.max_steps,
-                   burn_penalty=cfg.burn_penalty, extinguish_bonus=cfg.extinguish_bonus)
+                   burn_penalty=cfg.burn_penalty, extinguish_bonus=cfg.extinguish_bonus,
+                   single_launch=single_launch)
     ref.sim.t = 0
     want_obs, want_done = ref.reset(episode=5)
     obs, done = env.reset(episode=5)
