@@ -185,11 +185,14 @@ typedef struct {
     float burn_penalty;      /* reward -= burn_penalty * (BURNING cells) */
     float extinguish_bonus;  /* reward += bonus on the step that puts the fire out */
     int32_t single_launch;   /* nonzero: sim_rl_step runs as one kernel launch
-                                when every env fits it (W % 4 == 0 and
-                                H * W <= 4096), the env's state resident in
-                                LDS and stepped in place; 0: separate act,
-                                step (under the launch plan) and observation
-                                launches.  Results are identical. */
+                                when every env fits it (W % 4 == 0 and about
+                                11 bytes of LDS per cell of the largest env
+                                within 64 KB: up to about 5,900 cells, e.g.
+                                64 x 64), the env's state resident in LDS and
+                                stepped in place; otherwise, or with 0,
+                                separate act, step (under the launch plan)
+                                and observation launches.  Results are
+                                identical. */
 } sim_rl_config;
 
 /* Per-env agent state, device memory, 32 bytes. */

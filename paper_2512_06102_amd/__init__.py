@@ -409,10 +409,10 @@ class RLEnv:
     [n_env, 8] (row, col, water, steps, done, last_count, pad, pad).
 
     single_launch: each step is one kernel launch when every env fits it
-    (W % 4 == 0 and H * W <= 4096: the env's state is held in LDS and
-    stepped in place); otherwise, or with single_launch=False, the act, step
-    (under the simulator's launch plan) and observation kernels run apart.
-    Both give the same results."""
+    (W % 4 == 0 and up to about 5,900 cells, e.g. 64 x 64: the env's state
+    is held in LDS and stepped in place); otherwise, or with
+    single_launch=False, the act, step (under the simulator's launch plan)
+    and observation kernels run apart.  Both give the same results."""
 
     def __init__(self, sim: "FireSim", obs_radius: int = 2, drop_radius: int = 1, water_capacity: int = 10,
                  max_steps: int = 100, burn_penalty: float = 0.1, extinguish_bonus: float = 10.0,
