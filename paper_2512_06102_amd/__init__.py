@@ -503,7 +503,7 @@ def calibrate(sim: FireSim, target, T: int, theta0, steps: int = 50, lr: float =
         opt.step()
         with torch.no_grad():
             theta.copy_(torch.maximum(torch.minimum(theta, hi), lo))
-        losses.append(float(L))
+        losses.append(float(L.detach()))
         if callback is not None:
-            callback(it, float(L), theta.detach().clone())
+            callback(it, losses[-1], theta.detach().clone())
     return theta.detach(), losses
