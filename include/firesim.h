@@ -246,7 +246,8 @@ int sim_rl_step(sim_handle* h, const sim_rl_config* cfg, uint8_t* states, sim_rl
 int sim_get_step(const sim_handle* h, uint64_t* t);
 int sim_set_step(sim_handle* h, uint64_t t);
 
-/* Launch plan of sim_step (results never depend on it).
+/* Launch plan of sim_step, and of sim_step_relaxed_bwd for `sparse` (results
+ * never depend on it, up to the summation order of the relaxed gradient).
  *  tile_rows    rows of 4-cell groups each lane owns in its tile (1, 2, 4 or 8),
  *               0 = default (4)
  *  tile_width   widest tile in cells (64, 128 or 256), 0 = default (256);
@@ -264,7 +265,11 @@ int sim_set_step(sim_handle* h, uint64_t t);
  *               elevation; 0: every cell reads its 10 bytes every step
  *  sparse       1: after the first step of a call, a tile with no burning
  *               cell in it or in its 8 neighbouring tiles, and no drop on it,
- *               is not computed (its cells cannot change); 0: every tile runs
+ *               is not computed (its cells cannot change); 0: every tile runs.
+ *               In sim_step_relaxed_bwd, 1 skips the adjoint step s on tiles
+ *               farther than s + 1 cells from every cell with initial burning
+ *               mass (B_0 != 0): the parameter gradient is unchanged, since
+ *               it only sums terms carrying B_s, which is zero there.
  *  graph        1: capture the T launches of a call into a HIP graph and
  *               replay it (re-captured when T, the pointers or the plan
  *               change); 0: launch directly */

@@ -753,6 +753,7 @@ static RelaxedInputs relaxed_inputs(const sim_handle* h, int32_t form = 0)
     in.E = h->d_E;
     in.wind = h->wind_cell ? h->d_wind : nullptr;
     in.n_cells = h->n_cells;
+    in.sparse = h->plan.sparse;
     if (h->series_cell) {  // relaxed step t takes row t of the wind series
         in.wind = h->series_cell;
         in.wind_stride = 3 * h->n_cells;

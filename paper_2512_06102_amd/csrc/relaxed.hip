@@ -258,6 +258,76 @@ __global__ __launch_bounds__(256) void relaxed_fwd_kernel(
     }
 }
 
+// Sparse adjoint.  The parameter gradient of step s sums over edges u -> v
+// with B_s(u) != 0, so u lies within s cells (Chebyshev) of S_0, the cells
+// with initial burning mass, and v within s + 1; it needs the adjoint of
+// step s + 1 there.  That in turn is exact wherever its inputs of step s + 2
+// are, one cell further out, and so on up to the seed at T.  So the adjoint
+// step s must be exact only within s + 1 cells of S_0, and a tile farther
+// from every cell of S_0 can be skipped: whatever its cells hold (finite:
+// the buffers start at zero) only ever meets B = 0 in the gradient sums.
+// Its cells' adjoint values are then not those of the dense sweep; only
+// the parameter gradient is returned.
+//
+// tile_mass_kernel flags the adjoint tiles holding initial burning mass;
+// tile_integral_kernel builds each env's integral image of the flags (one
+// workgroup per env, in LDS).
+__global__ __launch_bounds__(256) void tile_mass_kernel(const RelaxedTile* __restrict__ tiles,
+                                                        const EnvDev* __restrict__ envs,
+                                                        const double* __restrict__ B, int32_t* __restrict__ mass)
+{
+    const RelaxedTile td = tiles[blockIdx.x];
+    const EnvDev ed = envs[td.env];
+    int any = 0;
+    for (int idx = threadIdx.x; idx < BW * BH; idx += 256) {
+        const int gi = td.r0 + idx / BW, gj = td.c0 + idx % BW;
+        if (gi < ed.H && gj < ed.W && B[ed.offset + (int64_t)gi * ed.W + gj] != 0.0) any = 1;
+    }
+    any = __syncthreads_or(any);
+    if (threadIdx.x == 0) mass[blockIdx.x] = any ? 1 : 0;
+}
+
+__global__ __launch_bounds__(256) void tile_integral_kernel(const TileGrid* __restrict__ grids,
+                                                            const int32_t* __restrict__ mass,
+                                                            int32_t* __restrict__ integ)
+{
+    extern __shared__ int32_t sI[];
+    const TileGrid tg = grids[blockIdx.x];
+    const int W1 = tg.cols + 1, n = (tg.rows + 1) * W1;
+    for (int i = threadIdx.x; i < n; i += 256) {
+        const int r = i / W1, c = i % W1;
+        sI[i] = (r && c) ? mass[tg.first + (r - 1) * tg.cols + (c - 1)] : 0;
+    }
+    __syncthreads();
+    for (int r = threadIdx.x + 1; r <= tg.rows; r += 256) {
+        int run = 0;
+        for (int c = 1; c <= tg.cols; ++c) sI[r * W1 + c] = (run += sI[r * W1 + c]);
+    }
+    __syncthreads();
+    for (int c = threadIdx.x + 1; c <= tg.cols; c += 256) {
+        int run = 0;
+        for (int r = 1; r <= tg.rows; ++r) sI[r * W1 + c] = (run += sI[r * W1 + c]);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += 256) integ[tg.ioff + i] = sI[i];
+}
+
+// Does the adjoint step s need this tile: is a tile with initial mass within
+// a = floor(s / BH) + 1 tile rows and b = floor(s / BW) + 1 tile columns
+// (the tile bands whose nearest cells are at most s + 1 apart)?
+__device__ __forceinline__ bool tile_in_reach(const RelaxedTile& td, const TileGrid* grids, const int32_t* integ,
+                                              int32_t s)
+{
+    const TileGrid tg = grids[td.env];
+    const int i = td.r0 / BH, j = td.c0 / BW;
+    const int a = s / BH + 1, b = s / BW + 1;
+    const int i0 = max(i - a, 0), i1 = min(i + a, tg.rows - 1);
+    const int j0 = max(j - b, 0), j1 = min(j + b, tg.cols - 1);
+    const int32_t* I = integ + tg.ioff;
+    const int W1 = tg.cols + 1;
+    return I[(i1 + 1) * W1 + (j1 + 1)] - I[i0 * W1 + (j1 + 1)] - I[(i1 + 1) * W1 + j0] + I[i0 * W1 + j0] > 0;
+}
+
 // Atomic add to a double in LDS (ds_add_f64).
 __device__ __forceinline__ void lds_add(double* p, double v)
 {
@@ -294,7 +364,8 @@ __global__ __launch_bounds__(256) void relaxed_bwd_kernel(
     const float* __restrict__ den, int64_t n_cells, RelaxedArgs A, const double* __restrict__ U,
     const double* __restrict__ B, const double* __restrict__ gU1, const double* __restrict__ gB1,
     double* __restrict__ gU0, double* __restrict__ gB0, double* __restrict__ stripes,
-    const float* __restrict__ env_wind)
+    const float* __restrict__ env_wind, const TileGrid* __restrict__ grids, const int32_t* __restrict__ integ,
+    int32_t step)
 {
     constexpr int XW = BW + 4, XH = BH + 4;  // staged: the targets' sources
     constexpr int EW = BW + 2, EH = BH + 2;  // targets: the tile and its ring
@@ -306,6 +377,7 @@ __global__ __launch_bounds__(256) void relaxed_bwd_kernel(
     __shared__ float ew[8];
     __shared__ double sred[4][17];
     const RelaxedTile td = tiles[blockIdx.x];
+    if (integ && !tile_in_reach(td, grids, integ, step)) return;  // sparse: the whole workgroup
     const EnvDev ed = envs[td.env];
     const int H = ed.H, W = ed.W, tid = threadIdx.x;
     for (int idx = tid; idx < NX; idx += 256) {
@@ -727,11 +799,11 @@ hipError_t fwd_step(hipStream_t s, const RelaxedInputs& in, const RelaxedArgs& A
 template <bool WC, int FORM>
 void launch_bwd(hipStream_t s, const RelaxedInputs& in, const RelaxedState& R, const RelaxedArgs& A,
                 const float* g, const double* U, const double* B, const double* gU1, const double* gB1,
-                double* gU0, double* gB0, double* stripes)
+                double* gU0, double* gB0, double* stripes, const int32_t* integ, int32_t step)
 {
     hipLaunchKernelGGL((relaxed_bwd_kernel<WC, FORM>), dim3(R.n_btiles), dim3(256), 0, s, R.d_btiles,
                        in.envs, g, in.E, in.wind, in.cls, in.den, in.n_cells, A, U, B, gU1, gB1, gU0,
-                       gB0, stripes, in.env_wind);
+                       gB0, stripes, in.env_wind, R.d_tgrid, integ, step);
 }
 
 }  // namespace
@@ -740,11 +812,18 @@ int relaxed_prepare(RelaxedState& R, const std::vector<sim_env>& envs)
 {
     if (R.d_tiles) return 0;
     std::vector<RelaxedTile> tiles, btiles;
+    std::vector<TileGrid> grids;
+    int64_t ioff = 0, max_img = 0;
     for (int32_t e = 0; e < (int32_t)envs.size(); ++e) {
         for (int r0 = 0; r0 < envs[e].H; r0 += TH)
             for (int c0 = 0; c0 < envs[e].W; c0 += TW) tiles.push_back(RelaxedTile{e, r0, c0, 0});
+        TileGrid tg{(int32_t)btiles.size(), (envs[e].H + BH - 1) / BH, (envs[e].W + BW - 1) / BW, (int32_t)ioff};
         for (int r0 = 0; r0 < envs[e].H; r0 += BH)
             for (int c0 = 0; c0 < envs[e].W; c0 += BW) btiles.push_back(RelaxedTile{e, r0, c0, 0});
+        const int64_t img = (int64_t)(tg.rows + 1) * (tg.cols + 1);
+        ioff += img;
+        max_img = std::max(max_img, img);
+        grids.push_back(tg);
     }
     if (hipMalloc(&R.d_tiles, tiles.size() * sizeof(RelaxedTile)) != hipSuccess) return -1;
     if (hipMemcpy(R.d_tiles, tiles.data(), tiles.size() * sizeof(RelaxedTile), hipMemcpyHostToDevice) !=
@@ -758,6 +837,16 @@ int relaxed_prepare(RelaxedState& R, const std::vector<sim_env>& envs)
     R.n_btiles = (int32_t)btiles.size();
     R.n_env = (int32_t)envs.size();
     if (hipMalloc(&R.d_loss_acc, sizeof(double) * 3 * R.n_env) != hipSuccess) return -1;
+    if (ioff < INT32_MAX && 4 * max_img <= 64 * 1024) {
+        if (hipMalloc(&R.d_tgrid, grids.size() * sizeof(TileGrid)) != hipSuccess ||
+            hipMalloc(&R.d_tmass, btiles.size() * sizeof(int32_t)) != hipSuccess ||
+            hipMalloc(&R.d_tinteg, (size_t)ioff * sizeof(int32_t)) != hipSuccess)
+            return -1;
+        if (hipMemcpy(R.d_tgrid, grids.data(), grids.size() * sizeof(TileGrid), hipMemcpyHostToDevice) !=
+            hipSuccess)
+            return -1;
+        R.sparse_lds = (int32_t)(4 * max_img);
+    }
     return 0;
 }
 
@@ -795,7 +884,8 @@ int relaxed_prepare_pool(RelaxedState& R, const std::vector<sim_env>& envs, int 
 void relaxed_free(RelaxedState& R)
 {
     for (void* p : {(void*)R.d_tiles, (void*)R.d_btiles, (void*)R.d_loss_acc, (void*)R.d_pool,
-                    (void*)R.d_env_blocks, (void*)R.d_pool_vals, (void*)R.d_bce_acc})
+                    (void*)R.d_env_blocks, (void*)R.d_pool_vals, (void*)R.d_bce_acc, (void*)R.d_tgrid,
+                    (void*)R.d_tmass, (void*)R.d_tinteg})
         if (p) (void)hipFree(p);
     R = RelaxedState{};
 }
@@ -907,6 +997,18 @@ hipError_t relaxed_backward(hipStream_t s, const RelaxedInputs& in, const sim_pa
     double* nb = adj + 3 * n;
     if (e == hipSuccess) e = copy_f64(s, cu, gU_T, n);
     if (e == hipSuccess) e = gB_T ? copy_f64(s, cb, gB_T, n) : fill_f64(s, cb, n, 0.0);
+    // sparse adjoint: tiles with initial burning mass (checkpoint 0 holds B_0),
+    // their integral images, and zeroed output buffers (skipped tiles keep them)
+    const int32_t* integ = nullptr;
+    if (in.sparse && R.sparse_lds > 0 && T > 0 && e == hipSuccess) {
+        hipLaunchKernelGGL(tile_mass_kernel, dim3(R.n_btiles), dim3(256), 0, s, R.d_btiles, in.envs, ckpt + n,
+                           R.d_tmass);
+        hipLaunchKernelGGL(tile_integral_kernel, dim3(R.n_env), dim3(256), (size_t)R.sparse_lds, s, R.d_tgrid,
+                           R.d_tmass, R.d_tinteg);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = fill_f64(s, nu, 2 * n, 0.0);
+        integ = R.d_tinteg;
+    }
     const int32_t n_seg = T > 0 ? (T + k - 1) / k : 0;
     for (int32_t sg = n_seg - 1; sg >= 0 && e == hipSuccess; --sg) {
         const int32_t t0 = sg * k, t1 = std::min(T, t0 + k);
@@ -924,11 +1026,11 @@ hipError_t relaxed_backward(hipStream_t s, const RelaxedInputs& in, const sim_pa
             const double *Ut = state_u(j), *Bt = state_b(j);
             const RelaxedInputs it = at_step(in, t);
             if (it.wind)
-                it.form ? launch_bwd<true, 1>(s, it, R, A, g, Ut, Bt, cu, cb, nu, nb, stripes)
-                        : launch_bwd<true, 0>(s, it, R, A, g, Ut, Bt, cu, cb, nu, nb, stripes);
+                it.form ? launch_bwd<true, 1>(s, it, R, A, g, Ut, Bt, cu, cb, nu, nb, stripes, integ, t)
+                        : launch_bwd<true, 0>(s, it, R, A, g, Ut, Bt, cu, cb, nu, nb, stripes, integ, t);
             else
-                it.form ? launch_bwd<false, 1>(s, it, R, A, g, Ut, Bt, cu, cb, nu, nb, stripes)
-                        : launch_bwd<false, 0>(s, it, R, A, g, Ut, Bt, cu, cb, nu, nb, stripes);
+                it.form ? launch_bwd<false, 1>(s, it, R, A, g, Ut, Bt, cu, cb, nu, nb, stripes, integ, t)
+                        : launch_bwd<false, 0>(s, it, R, A, g, Ut, Bt, cu, cb, nu, nb, stripes, integ, t);
             e = hipGetLastError();
             std::swap(cu, nu);
             std::swap(cb, nb);

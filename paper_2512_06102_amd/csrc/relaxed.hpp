@@ -20,6 +20,13 @@ struct RelaxedTile {
     int32_t env, r0, c0, pad;
 };
 
+// The adjoint tiles of one env form a rows x cols grid starting at tile
+// `first`; its (rows + 1) x (cols + 1) integral image of tiles holding
+// initial burning mass starts at `ioff` (sparse adjoint).
+struct TileGrid {
+    int32_t first, rows, cols, ioff;
+};
+
 // Per-handle state of the relaxed path (built on first use).
 struct RelaxedState {
     RelaxedTile* d_tiles = nullptr;   // forward / loss tiles
@@ -34,6 +41,13 @@ struct RelaxedState {
     int32_t* d_env_blocks = nullptr;  // blocks per env
     double* d_pool_vals = nullptr;    // [2][n_pool]: block means of S and Y
     double* d_bce_acc = nullptr;      // [2][n_env]: BCE sum, squared-error sum
+    // sparse adjoint: per-env tile grids, per-tile initial-mass flags and
+    // their integral images (sparse_lds: bytes of the largest image; 0 when
+    // an image would not fit in LDS, and the adjoint then stays dense)
+    TileGrid* d_tgrid = nullptr;
+    int32_t* d_tmass = nullptr;
+    int32_t* d_tinteg = nullptr;
+    int32_t sparse_lds = 0;
 };
 
 struct RelaxedInputs {
@@ -49,6 +63,7 @@ struct RelaxedInputs {
     int32_t form;       // 0: product form of p_ignite, 1: 1 - exp(-gamma sum B phi)
     int64_t wind_stride = 0;          // floats between the per-cell wind planes of steps t, t+1
     const float* env_wind = nullptr;  // per-env wind series [T][n_env][3] or nullptr
+    int32_t sparse = 0;               // adjoint: skip tiles beyond the reach of the initial burning mass
 };
 
 int relaxed_prepare(RelaxedState& R, const std::vector<sim_env>& envs);
