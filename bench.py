@@ -497,7 +497,9 @@ def main():
     ap.add_argument("--no-relaxed", action="store_true")
     ap.add_argument("--no-variants", action="store_true", help="skip the front-skipping plans")
     ap.add_argument("--no-dense-front", action="store_true")
-    ap.add_argument("--no-extra", action="store_true", help="skip the paper-setting and RL objects")
+    ap.add_argument("--no-extra", action="store_true", help="skip the paper-setting, RL, uneven and large objects")
+    ap.add_argument("--extras", default="paper,rl,uneven,large",
+                    help="comma-separated subset of the extra objects to run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (HBM counter calibration)")
@@ -520,10 +522,11 @@ def main():
     variants = None if args.no_variants else bench_variants(args, torch, fs, st)
     dense = None if args.no_dense_front else bench_dense_front(args, torch, fs, firegen, st)
     st.pop("sim")
-    paper = None if args.no_extra else bench_paper_config(args, torch, fs, firegen)
-    rl = None if args.no_extra else bench_rl(args, torch, fs, firegen)
-    uneven = None if args.no_extra else bench_uneven(args, torch, fs, firegen)
-    large = None if args.no_extra else bench_large(args, torch, fs, firegen)
+    extras = set() if args.no_extra else set(args.extras.split(","))
+    paper = bench_paper_config(args, torch, fs, firegen) if "paper" in extras else None
+    rl = bench_rl(args, torch, fs, firegen) if "rl" in extras else None
+    uneven = bench_uneven(args, torch, fs, firegen) if "uneven" in extras else None
+    large = bench_large(args, torch, fs, firegen) if "large" in extras else None
     relaxed = None if args.no_relaxed else bench_relaxed(args, torch, fs, firegen)
     if args.copy_calibration:
         a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
