@@ -39,12 +39,19 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 ALU_PEAK_GOPS = 256 * 64 * 2.4
 STOCH_BYTES_PER_CELL = 10      # state r/w 2 B + fuel 4 B + elevation 4 B per cell-update
 STOCH_WIND_CELL_BYTES = 12     # per-cell wind adds V, Vx, Vy (3 x 4 B) per cell-update
-# relaxed, fp64 state: forward 40 B (U,B r/w 32 + fuel, elevation 8); adjoint
-# 61 B (U,B 16, adjoint r/w 32, fuel, elevation, density 12, class 1); the
-# forward is recomputed from checkpoints (40 B) and every 10th state stored (1.6 B)
-RELAXED_BYTES_PER_CELL_STEP = 40 + 40 + 61 + 1.6
-# per-cell wind adds V, Vx, Vy (12 B) to each of the three passes
-RELAXED_WIND_CELL_BYTES = 3 * 12
+# relaxed, fp64 state, per cell-step: forward 40 B (U,B r/w 32 + fuel,
+# elevation 8) and adjoint 61 B (U,B 16, adjoint r/w 32, fuel, elevation,
+# density 12, class 1); per-cell wind adds V, Vx, Vy (12 B) to each pass
+RELAXED_FWD_BYTES, RELAXED_ADJ_BYTES, RELAXED_WIND_BYTES = 40, 61, 12
+
+
+def relaxed_bytes_per_cell_step(T: int, k: int, wind_cell: bool) -> float:
+    """Forward, adjoint and the recompute of every checkpoint segment but the
+    last (whose states the forward leaves in place): (ceil(T/k) - 1)(k - 1)
+    recomputed steps; plus copying the initial state into checkpoint 0."""
+    recomputed = ((T + k - 1) // k - 1) * (k - 1) / T
+    w = RELAXED_WIND_BYTES if wind_cell else 0
+    return (RELAXED_FWD_BYTES + w) * (1 + recomputed) + RELAXED_ADJ_BYTES + w + 32.0 / T
 # fp32/int32 operations of the method (separate multiply and add, as the step
 # is specified): one phi term 30 (slope 2, exponent 2, exp 23, scale 2, sum 1),
 # the ignition probability 26 (gamma 1, product 1, exp 23, 1-e 1), one draw 29
@@ -445,7 +452,7 @@ def relaxed_case(args, torch, fs, firegen, batch, params, T, k, label):
 
     ms, loss, grad = timed()   # dense adjoint: the roofline figure
     cs = float(batch.n_cells) * T / (ms / 1e3)
-    bpc = RELAXED_BYTES_PER_CELL_STEP + (RELAXED_WIND_CELL_BYTES if batch.wind_cell is not None else 0)
+    bpc = round(relaxed_bytes_per_cell_step(T, k, batch.wind_cell is not None), 2)
     gbs = cs * bpc / 1e9
     # sparse adjoint (tiles beyond the reach of the initial fire skipped): an
     # effective rate, same gradient

@@ -791,7 +791,7 @@ int sim_step_relaxed_fwd(sim_handle* h, const sim_params* p, double* U, double* 
     if ((rc = relaxed_prepare(h->relaxed, h->envs)) != 0)
         return fail(h, SIM_ENOMEM, "relaxed tile list allocation failed");
     hipError_t e = relaxed_forward((hipStream_t)stream, relaxed_inputs(h, form), *p, U, B, T, ckpt_every,
-                                   workspace);
+                                   workspace, h->relaxed);
     if (e != hipSuccess) return fail(h, SIM_EHIP, "relaxed forward failed: %s", hipGetErrorString(e));
     return SIM_OK;
 }

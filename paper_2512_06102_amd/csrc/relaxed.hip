@@ -901,36 +901,51 @@ hipError_t launch_relaxed_init(hipStream_t s, const uint8_t* init_states, int64_
     return hipGetLastError();
 }
 
+// The forward writes each step's output where it is needed next: the
+// checkpoint slot of every k-th state, the segment slots 1.. of the last
+// segment's states (so the backward need not recompute that segment), the
+// caller's U, B for the final state, and otherwise one of two scratch states
+// (the forward buffer and segment slot 0, which the backward never uses).
 hipError_t relaxed_forward(hipStream_t s, const RelaxedInputs& in, const sim_params& p, double* U,
-                           double* B, int32_t T, int32_t k, void* workspace)
+                           double* B, int32_t T, int32_t k, void* workspace, RelaxedState& R)
 {
+    R.last_segment_ws = nullptr;
     if (T == 0) return hipSuccess;
     const int64_t n = in.n_cells;
     const WsLayout L = layout(n, T, k);
     char* ws = static_cast<char*>(workspace);
     float* g = reinterpret_cast<float*>(ws + L.g);
     double* ckpt = reinterpret_cast<double*>(ws + L.ckpt);
-    double* pp = reinterpret_cast<double*>(ws + L.fwd);
+    double* seg = reinterpret_cast<double*>(ws + L.seg);
+    double* scratch[2] = {reinterpret_cast<double*>(ws + L.fwd), seg};
     const RelaxedArgs A = relaxed_args(p);
+    const int32_t t_last = ((T - 1) / k) * k;  // first step of the last segment
     hipError_t e = fuel(s, in, p, g);
-    double* cu = U;
-    double* cb = B;
-    double* nu = pp;
-    double* nb = pp + n;
+    if (e == hipSuccess) e = copy_f64(s, ckpt, U, n);
+    if (e == hipSuccess) e = copy_f64(s, ckpt + n, B, n);
+    const double* cu = ckpt;  // state t
+    const double* cb = ckpt + n;
     for (int32_t t = 0; t < T && e == hipSuccess; ++t) {
-        if (t % k == 0) {
-            double* slot = ckpt + (size_t)(t / k) * 2 * n;
-            e = copy_f64(s, slot, cu, n);
-            if (e == hipSuccess) e = copy_f64(s, slot + n, cb, n);
+        const int32_t t1 = t + 1;
+        double *nu, *nb;
+        if (t1 == T) {
+            nu = U;
+            nb = B;
+        } else if (t1 % k == 0) {
+            nu = ckpt + (size_t)(t1 / k) * 2 * n;
+            nb = nu + n;
+        } else if (t1 > t_last) {
+            nu = seg + (size_t)(t1 - t_last) * 2 * n;
+            nb = nu + n;
+        } else {
+            nu = scratch[0] == cu ? scratch[1] : scratch[0];
+            nb = nu + n;
         }
-        if (e == hipSuccess) e = fwd_step(s, at_step(in, t), A, g, cu, cb, nu, nb);
-        std::swap(cu, nu);
-        std::swap(cb, nb);
+        e = fwd_step(s, at_step(in, t), A, g, cu, cb, nu, nb);
+        cu = nu;
+        cb = nb;
     }
-    if (e == hipSuccess && cu != U) {
-        e = copy_f64(s, U, cu, n);
-        if (e == hipSuccess) e = copy_f64(s, B, cb, n);
-    }
+    if (e == hipSuccess) R.last_segment_ws = workspace;
     return e;
 }
 
@@ -1018,7 +1033,11 @@ hipError_t relaxed_backward(hipStream_t s, const RelaxedInputs& in, const sim_pa
         auto state_b = [&](int32_t j) -> const double* {
             return j == 0 ? base + n : seg + (size_t)j * 2 * n + n;
         };
-        for (int32_t j = 1; j < t1 - t0 && e == hipSuccess; ++j)
+        // the last segment's states are in place after the forward, until an
+        // earlier segment's recompute overwrites them
+        const bool stored = sg == n_seg - 1 && R.last_segment_ws == workspace;
+        if (sg < n_seg - 1) R.last_segment_ws = nullptr;
+        for (int32_t j = 1; j < t1 - t0 && !stored && e == hipSuccess; ++j)
             e = fwd_step(s, at_step(in, t0 + j - 1), A, g, state_u(j - 1), state_b(j - 1),
                          seg + (size_t)j * 2 * n, seg + (size_t)j * 2 * n + n);
         for (int32_t t = t1 - 1; t >= t0 && e == hipSuccess; --t) {

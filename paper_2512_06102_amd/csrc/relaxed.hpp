@@ -48,6 +48,9 @@ struct RelaxedState {
     int32_t* d_tmass = nullptr;
     int32_t* d_tinteg = nullptr;
     int32_t sparse_lds = 0;
+    // workspace whose segment slots hold the last segment's states, as the
+    // last forward left them (the backward then skips that recompute)
+    const void* last_segment_ws = nullptr;
 };
 
 struct RelaxedInputs {
@@ -74,7 +77,7 @@ size_t relaxed_workspace_bytes(int64_t n_cells, int32_t T, int32_t ckpt_every);
 hipError_t launch_relaxed_init(hipStream_t s, const uint8_t* init_states, int64_t n, double* U,
                                double* B);
 hipError_t relaxed_forward(hipStream_t s, const RelaxedInputs& in, const sim_params& p, double* U,
-                           double* B, int32_t T, int32_t ckpt_every, void* workspace);
+                           double* B, int32_t T, int32_t ckpt_every, void* workspace, RelaxedState& R);
 hipError_t relaxed_loss(hipStream_t s, const RelaxedInputs& in, const uint8_t* init_states,
                         const double* U_T, const uint8_t* target, float* loss, double* gU_T,
                         double scale, RelaxedState& R);

@@ -45,3 +45,12 @@ def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_relaxed_bytes_per_cell_step():
+    """T = 100, checkpoints every 10: 9 of the 10 segments are recomputed, 9
+    steps each (81 of 100); the forward's last segment stays in place."""
+    assert abs(bench.relaxed_bytes_per_cell_step(100, 10, False) - (40 * 1.81 + 61 + 0.32)) < 1e-9
+    assert abs(bench.relaxed_bytes_per_cell_step(100, 10, True) - (52 * 1.81 + 73 + 0.32)) < 1e-9
+    # a single segment is never recomputed
+    assert abs(bench.relaxed_bytes_per_cell_step(21, 40, False) - (40 + 61 + 32 / 21)) < 1e-9

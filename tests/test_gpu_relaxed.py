@@ -364,3 +364,31 @@ def test_sparse_adjoint_matches_dense(per_cell_wind, form, k):
     assert np.allclose(g_sparse, g_dense, rtol=1e-9, atol=1e-12 * scale)
     _, g64, _ = _oracle(batch, params, Y, T, form=form)
     _check_grad(g_sparse, g64)
+
+
+@pytest.mark.parametrize("k", [5, 40])
+def test_backward_repeats_and_other_workspaces(k):
+    """The forward leaves the last checkpoint segment's states in the
+    workspace for the backward; a second backward (which must recompute it),
+    and a backward after a forward on another workspace, give the same
+    gradient."""
+    batch = firegen.landscape_batch(44, [(48, 40), (36, 52)], elev_max=60.0)
+    params = _params(5)
+    T = 21
+    Y = torch.from_numpy(_target(batch, params, T, 3)).cuda()
+    sim = fs.FireSim.from_batch(batch, params, seed=0)
+    p = fs.make_params(params)
+    p.unburnable_mask = batch.unburnable_mask
+    ws, ws2 = sim.relaxed_workspace(T, k), sim.relaxed_workspace(T, k)
+    U, B = sim.relaxed_init()
+    sim.relaxed_fwd(p, U, B, T, k, ws)
+    _, gU = sim.relaxed_loss(U, Y, scale=1.0 / batch.n_env)
+    g1 = sim.relaxed_bwd(p, gU, None, T, k, ws).cpu().numpy()
+    g2 = sim.relaxed_bwd(p, gU, None, T, k, ws).cpu().numpy()
+    U2, B2 = sim.relaxed_init()
+    sim.relaxed_fwd(p, U2, B2, T, k, ws2)
+    g3 = sim.relaxed_bwd(p, gU, None, T, k, ws).cpu().numpy()
+    torch.cuda.synchronize()
+    scale = np.max(np.abs(g1))
+    for g in (g2, g3):
+        assert np.allclose(g, g1, rtol=1e-9, atol=1e-12 * scale)
