@@ -454,22 +454,25 @@ def relaxed_case(args, torch, fs, firegen, batch, params, T, k, label):
     cs = float(batch.n_cells) * T / (ms / 1e3)
     bpc = round(relaxed_bytes_per_cell_step(T, k, batch.wind_cell is not None), 2)
     gbs = cs * bpc / 1e9
-    # sparse adjoint (tiles beyond the reach of the initial fire skipped): an
-    # effective rate, same gradient
-    sim.set_plan(sparse=1)
-    ms_sp, _, grad_sp = timed()
-    sim.set_plan(sparse=0)
-    rel = float((grad_sp - grad).abs().max() / grad.abs().max())
-    log("[bench] relaxed %s: %.2f ms per fwd+bwd, %.3e cell-steps/s, %.0f GB/s, loss %.4f; sparse adjoint "
-        "%.2f ms (gradient max rel. difference %.1e)" % (label, ms, cs, gbs, float(loss.mean()), ms_sp, rel))
-    return {"value": cs, "unit": "cell-steps/s", "ms_per_fwd_bwd": round(ms, 3), "workload": label,
-            "algorithmic_bytes_per_cell_step": bpc, "achieved_GBs": round(gbs, 1),
-            "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "loss": round(float(loss.mean()), 6),
-            "sparse_adjoint": {"ms_per_fwd_bwd": round(ms_sp, 3),
-                               "value": float(batch.n_cells) * T / (ms_sp / 1e3),
-                               "grad_max_rel_difference": rel,
-                               "note": "effective rate: adjoint tiles beyond the reach of the initial "
-                                       "burning mass are skipped"}}
+    log("[bench] relaxed %s: %.2f ms per fwd+bwd, %.3e cell-steps/s, %.0f GB/s, loss %.4f"
+        % (label, ms, cs, gbs, float(loss.mean())))
+    out = {"value": cs, "unit": "cell-steps/s", "ms_per_fwd_bwd": round(ms, 3), "workload": label,
+           "algorithmic_bytes_per_cell_step": bpc, "achieved_GBs": round(gbs, 1),
+           "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "loss": round(float(loss.mean()), 6)}
+    if args.relaxed_sparse:
+        # sparse adjoint (tiles beyond the reach of the initial fire skipped):
+        # an effective rate, same gradient
+        sim.set_plan(sparse=1)
+        ms_sp, _, grad_sp = timed()
+        sim.set_plan(sparse=0)
+        rel = float((grad_sp - grad).abs().max() / grad.abs().max())
+        log("[bench] relaxed %s, sparse adjoint: %.2f ms (gradient max rel. difference %.1e)" % (label, ms_sp, rel))
+        out["sparse_adjoint"] = {"ms_per_fwd_bwd": round(ms_sp, 3),
+                                 "value": float(batch.n_cells) * T / (ms_sp / 1e3),
+                                 "grad_max_rel_difference": rel,
+                                 "note": "effective rate: adjoint tiles beyond the reach of the initial "
+                                         "burning mass are skipped"}
+    return out
 
 
 def bench_relaxed(args, torch, fs, firegen):
@@ -499,6 +502,7 @@ def main():
     ap.add_argument("--sparse", type=int, default=0)
     ap.add_argument("--graph", type=int, default=1)
     ap.add_argument("--relaxed-reps", type=int, default=2)
+    ap.add_argument("--relaxed-sparse", type=int, default=1, help="also time the sparse adjoint")
     ap.add_argument("--no-stochastic", action="store_true",
                     help="skip the timed headline run (profiling of the other parts)")
     ap.add_argument("--no-relaxed", action="store_true")
