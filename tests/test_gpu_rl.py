@@ -92,3 +92,37 @@ def test_rl_rejects_bad_config():
         with pytest.raises(fs.SimError):
             env.step(torch.zeros(4, dtype=torch.int32))
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("single_launch", [True, False])
+@pytest.mark.parametrize("obs_radius,drop_radius,water,max_steps", [(0, 0, 3, 4), (31, 255, 2, 30), (5, 2, 0, 1)])
+def test_rl_edge_configs(obs_radius, drop_radius, water, max_steps, single_launch):
+    """Edge cases of the RL layer against the oracle: a one-cell and a 63 x 63
+    window, a drop of radius 0 and one covering the grid, no water, one-step
+    episodes; grids down to 1 x 4 and 4 x 4, and a 64 x 64 one."""
+    sizes = [(20, 20)] * 6 + [(1, 4), (4, 4), (3, 8), (64, 64), (12, 44)]
+    batch = firegen.landscape_batch(45, sizes)
+    params = firegen.Params(p_base=0.9, veg=tuple(firegen.veg_table(np.random.default_rng(45))))
+    cfg = rl.Config(obs_radius=obs_radius, drop_radius=drop_radius, water_capacity=water,
+                    max_steps=max_steps, burn_penalty=0.25, extinguish_bonus=3.0)
+    ref = rl.RLEnvs(batch, params, 5, cfg)
+    sim = fs.FireSim.from_batch(batch, params, seed=5)
+    env = fs.RLEnv(sim, obs_radius=cfg.obs_radius, drop_radius=cfg.drop_radius,
+                   water_capacity=cfg.water_capacity, max_steps=cfg.max_steps,
+                   burn_penalty=cfg.burn_penalty, extinguish_bonus=cfg.extinguish_bonus,
+                   single_launch=single_launch)
+    want_obs, _ = ref.reset(episode=2)
+    obs, _ = env.reset(episode=2)
+    torch.cuda.synchronize()
+    assert np.array_equal(obs.cpu().numpy(), want_obs)
+    rng = np.random.default_rng(11)
+    for step in range(12):
+        act = rng.integers(0, 32, batch.n_env).astype(np.int32)
+        want_obs, want_r, want_d = ref.step(act)
+        obs, r, d = env.step(torch.from_numpy(act))
+        torch.cuda.synchronize()
+        assert np.array_equal(sim.states.cpu().numpy(), ref.sim.states), step
+        assert np.array_equal(obs.cpu().numpy(), want_obs), step
+        assert np.array_equal(r.cpu().numpy(), want_r), step
+        assert np.array_equal(d.cpu().numpy(), want_d), step
+        assert np.array_equal(env.agents.cpu().numpy()[:, :6], _agents_np(ref)), step
