@@ -32,8 +32,9 @@
 //     lane, instead of leaving it to the lanes that own the cells, keeps the
 //     step at memory speed.  A wave whose lists would overflow falls back to
 //     each lane handling its own cells.
-//  5. Owners assemble the new dwords and store them (nontemporal); the BURNING count is
-//     reduced across the wave and added to the env's counter with one atomic.
+//  5. Owners assemble the new dwords and store them (nontemporal in the
+//     dense plan); the BURNING count is reduced across the wave and added
+//     to the env's counter with one atomic.
 // Workgroup b runs on XCD b % 8; tiles are dealt so that each XCD walks a
 // contiguous run of the tile list (neighbouring tiles share lines in that
 // XCD's L2).
@@ -374,11 +375,15 @@ __global__ __launch_bounds__(kWave) void stoch_step_kernel(
             }
         }
         uint8_t* o = (dst + base) + (uint32_t)(gi * W + gj0);
-        if constexpr (ALIGNED) {
-            // nontemporal: nothing in this launch reads the new state, so its
-            // lines need not displace the halo rows neighbouring tiles still
-            // read from L2 (about 2% faster on the 1024 x 256^2 batch)
+        if constexpr (ALIGNED && !SKIP) {
+            // dense plan: nontemporal, as the fuel and elevation streamed
+            // through every step evict the state from the caches anyway, and
+            // nothing in this launch reads the new state (about 2% faster on
+            // the 1024 x 256^2 batch).  The front-skipping plans move a few
+            // bytes per cell and find the state still cached the next step.
             __builtin_nontemporal_store(out, reinterpret_cast<uint32_t*>(o));
+        } else if constexpr (ALIGNED) {
+            *reinterpret_cast<uint32_t*>(o) = out;
         } else {
 #pragma unroll
             for (int c = 0; c < 4; ++c)
