@@ -126,3 +126,37 @@ def test_rl_edge_configs(obs_radius, drop_radius, water, max_steps, single_launc
         assert np.array_equal(r.cpu().numpy(), want_r), step
         assert np.array_equal(d.cpu().numpy(), want_d), step
         assert np.array_equal(env.agents.cpu().numpy()[:, :6], _agents_np(ref)), step
+
+
+@pytest.mark.parametrize("single_launch", [True, False])
+def test_rl_benchmark_configuration_sampled(single_launch):
+    """The benchmark's RL configuration at full size (65536 envs of 20 x 20,
+    its plan and settings): 12 steps of random actions, with 16 sampled envs
+    (first and last included) checked bit-exactly against the oracle run on
+    those envs alone (envs are independent; draws are keyed by env_id)."""
+    n = 65536
+    batch = firegen.uniform_batch(20, 20, n_env=n, ignitions=())
+    params = firegen.Params(p_base=0.45)
+    sim = fs.FireSim.from_batch(batch, params, seed=0)
+    sim.set_plan(tile_rows=4, tile_width=64, graph=0)
+    env = fs.RLEnv(sim, obs_radius=2, drop_radius=1, water_capacity=20, max_steps=1000,
+                   single_launch=single_launch)
+    rng = np.random.default_rng(17)
+    pick = np.unique(np.concatenate([[0, n - 1], rng.integers(0, n, 14)]))
+    cfg = rl.Config(obs_radius=2, drop_radius=1, water_capacity=20, max_steps=1000)
+    ref = rl.RLEnvs(batch.subset(pick), params, 0, cfg)
+    cells = np.concatenate([np.arange(e * 400, (e + 1) * 400) for e in pick])
+    want_obs, _ = ref.reset(episode=1)
+    obs, _ = env.reset(episode=1)
+    torch.cuda.synchronize()
+    assert np.array_equal(obs.cpu().numpy()[pick], want_obs)
+    for step in range(12):
+        act = rng.integers(0, 32, n).astype(np.int32)
+        want_obs, want_r, want_d = ref.step(act[pick])
+        obs, r, d = env.step(torch.from_numpy(act))
+        torch.cuda.synchronize()
+        assert np.array_equal(sim.states.cpu().numpy()[cells], ref.sim.states), step
+        assert np.array_equal(obs.cpu().numpy()[pick], want_obs), step
+        assert np.array_equal(r.cpu().numpy()[pick], want_r), step
+        assert np.array_equal(d.cpu().numpy()[pick], want_d), step
+        assert np.array_equal(env.agents.cpu().numpy()[pick, :6], _agents_np(ref)), step
