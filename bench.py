@@ -18,6 +18,7 @@ Reported beside it, each in its own object:
                 setting, the RL layer on 65536 envs of 20 x 20, the 4096-env
                 uneven batch with drops, and 8 envs of 2048 x 2048 with
                 per-cell wind (1000 steps);
+  copy_probe  - a 1 GiB device copy: the attainable HBM bandwidth;
   cpu_baseline - the CPU oracle on the same stochastic workload.
 
 Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -83,6 +84,25 @@ def stored_traffic(plan_key: str):
     if rec.get("kernel_hash") != kernel_hash() or rec.get("plan") != plan_key:
         return None
     return rec.get("bytes_per_launch")
+
+
+def copy_probe(torch):
+    """Attainable HBM bandwidth on this GPU: a 1 GiB device-to-device copy
+    (read + write bytes per second, best of 5)."""
+    a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    stream = torch.cuda.current_stream()
+    best = float("inf")
+    for _ in range(5):
+        with StepTimer(torch, stream) as tm:
+            b.copy_(a)
+        best = min(best, tm.ms())
+    gbs = 2 * a.numel() / (best / 1e3) / 1e9
+    log("[bench] copy probe: 1 GiB in %.3f ms = %.0f GB/s (read + write)" % (best, gbs))
+    del a, b
+    return {"kind": "1 GiB device copy (torch copy_), best of 5", "ms": round(best, 4), "GBs": round(gbs, 1),
+            "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4)}
 
 
 def cpu_baseline(batch, params, T, seed):
@@ -545,6 +565,7 @@ def main():
         for _ in range(3):
             b.copy_(a)
         torch.cuda.synchronize()
+    probe = copy_probe(torch)
     cpu = None if args.no_cpu else cpu_baseline(st["batch"], st["params"], st["T"], st["seed"])
     batch = st["batch"]
     out = {"metric": "cell-updates/s stochastic step + relaxed fwd+bwd cell-steps/s, % HBM peak",
@@ -556,7 +577,7 @@ def main():
                       "n_env": int(batch.n_env), "H": 256, "W": 256, "T": st["T"], "plan": st["plan"],
                       "burning_cell_steps": st["burning"]},
            "roofline": st["roof"], "variants": variants, "dense_front": dense, "relaxed": relaxed,
-           "paper_setting": paper, "rl": rl, "uneven": uneven, "large": large,
+           "paper_setting": paper, "rl": rl, "uneven": uneven, "large": large, "copy_probe": probe,
            "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
 
