@@ -458,7 +458,7 @@ def relaxed_case(args, torch, fs, firegen, batch, params, T, k, label):
     def fwd_bwd():
         U, B = sim.relaxed_init()
         sim.relaxed_fwd(theta, U, B, T, k, ws)
-        loss, gU = sim.relaxed_loss(U, Y, scale=1.0 / batch.n_env)
+        loss, gU, _ = sim.relaxed_loss(U, Y, scale=1.0 / batch.n_env)
         return loss, sim.relaxed_bwd(theta, gU, None, T, k, ws)
 
     def timed():

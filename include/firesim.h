@@ -27,9 +27,14 @@
  *    northern edge, so row index grows southward and column index eastward.
  *  - Cell states are uint8: SIM_UNBURNABLE (no fuel), SIM_FLAMMABLE (the
  *    paper's "unburned"), SIM_BURNING, SIM_BURNT.
- *  - All kernels of one handle run on the device that was current at
- *    sim_init.  Calls on one handle must not overlap (they share its
- *    internal buffers and its step counter).
+ *  - A handle lives on the device that was current at sim_init.  Every call
+ *    on it makes that device current while it runs and restores the
+ *    caller's device on return, so handles on several GPUs can be driven
+ *    from one thread; `stream` must belong to the handle's device.  Calls on
+ *    one handle must not overlap (they share its internal buffers and its
+ *    step counter).
+ *  - Each call shows as a range named after it in a marker trace
+ *    (roctx; rocprofv3 --marker-trace).
  */
 #ifndef FIRESIM_H
 #define FIRESIM_H
@@ -248,6 +253,11 @@ int sim_set_step(sim_handle* h, uint64_t t);
 
 /* Launch plan of sim_step, and of sim_step_relaxed_bwd for `sparse` (results
  * never depend on it, up to the summation order of the relaxed gradient).
+ * A new handle starts with {tile_rows 4, tile_width 64, temporal 1,
+ * skip_static 1, sparse 1, graph 0}: fuel and elevation are read only at
+ * front cells and tiles with no fire in reach are skipped.  The dense plan
+ * {4, 256, 1, 0, 0, 0} streams every cell's state, fuel and elevation each
+ * step (the HBM roofline reference).
  *  tile_rows    rows of 4-cell groups each lane owns in its tile (1, 2, 4 or 8),
  *               0 = default (4)
  *  tile_width   widest tile in cells (64, 128 or 256), 0 = default (256);
@@ -335,24 +345,30 @@ int sim_step_relaxed_fwd(sim_handle* h, const sim_params* p, double* U, double* 
 
 /* Soft-IoU loss of the final relaxed state against a binary target scar.
  * Per env e: S = 1 - U_T on burnable cells, I = sum S Y, D = sum S + sum Y - I,
- * loss[e] = 1 - I / D (0 when D = 0).  gU_T (device double[n_cells], or NULL)
- * receives scale * d loss[e] / d U_T summed over envs, i.e. the seed of the
- * backward for the objective scale * sum_e loss[e].
- *  target  device uint8[n_cells], nonzero = burnt in the target scar.
- *  loss    device float[n_env]. */
+ * loss[e] = 1 - I / D (0 when D = 0) (the calibration objective of section 4
+ * with the IoU as its score).
+ *  target     device uint8[n_cells], nonzero = burnt in the target scar.
+ *  loss       device float[n_env]: the per-env losses (rounded from fp64).
+ *  gU_T       device double[n_cells] or NULL: scale * d loss[e] / d U_T, the
+ *             seed of sim_step_relaxed_bwd for the objective below.
+ *  objective  device double[1] or NULL: scale * sum_e loss[e] in fp64 (scale
+ *             = 1 / n_env gives the mean over envs).
+ * Every sum runs in a fixed order, so equal inputs give equal bits.  On the
+ * first call the handle allocates its scratch (3 doubles per 4096-cell chunk
+ * of every env and 4 per env). */
 int sim_relaxed_loss(sim_handle* h, const double* U_T, const uint8_t* target, float* loss,
-                     double* gU_T, double scale, void* stream);
+                     double* gU_T, double scale, double* objective, void* stream);
 
 /* The paper's calibration loss (section 4): per env e, binary cross-entropy
  * of S = clip(1 - U_T on burnable cells, 0 elsewhere; eps, 1 - eps) against
  * the target scar Y, averaged over the env's cells, plus mse_weight times the
  * mean squared error between the pool x pool block averages of S and Y
- * (blocks at the far edges cover what is left).  loss[e] is written; gU_T
- * (or NULL) receives scale * d loss[e] / d U_T as for sim_relaxed_loss
- * (zero where S is clipped).  1 <= pool <= 64, 0 < eps < 0.5. */
+ * (blocks at the far edges cover what is left).  loss[e], gU_T (or NULL; zero
+ * where S is clipped) and objective (or NULL) as for sim_relaxed_loss.
+ * 1 <= pool <= 64, 0 < eps < 0.5. */
 int sim_relaxed_loss_bce(sim_handle* h, const double* U_T, const uint8_t* target, int32_t pool,
                          double mse_weight, double eps, float* loss, double* gU_T, double scale,
-                         void* stream);
+                         double* objective, void* stream);
 
 /* Gradient of a scalar objective J(U_T, B_T) with respect to the parameter
  * vector (p_base, alpha_w1, alpha_w2, alpha_s, alpha_gamma, p_continue,

@@ -103,8 +103,8 @@ def lib() -> ctypes.CDLL:
         L.sim_relaxed_workspace_bytes.restype = SZ
         D = ctypes.c_double
         L.sim_step_relaxed_fwd.argtypes = [P, P, P, P, I32, I32, I32, P, SZ, P]
-        L.sim_relaxed_loss.argtypes = [P, P, P, P, P, D, P]
-        L.sim_relaxed_loss_bce.argtypes = [P, P, P, I32, D, D, P, P, D, P]
+        L.sim_relaxed_loss.argtypes = [P, P, P, P, P, D, P, P]
+        L.sim_relaxed_loss_bce.argtypes = [P, P, P, I32, D, D, P, P, D, P, P]
         L.sim_step_relaxed_bwd.argtypes = [P, P, P, P, I32, I32, I32, P, SZ, P, P]
         L.sim_debug_exp.argtypes = [P, P, I64, P]
         L.sim_debug_atan.argtypes = [P, P, I64, P]
@@ -358,22 +358,27 @@ class FireSim:
                                           self._s()), self.handle)
 
     def relaxed_loss(self, U_T, target, scale: float = 1.0, want_grad: bool = True):
+        """Soft-IoU loss: (per-env losses float32 [n_env], seed scale x dL/dU_T
+        or None, objective float64 [1] = scale x sum of the per-env losses)."""
         loss = torch.empty(self.n_env, dtype=torch.float32, device=self.device)
+        obj = torch.empty(1, dtype=torch.float64, device=self.device)
         g = torch.empty_like(U_T) if want_grad else None
         _check(lib().sim_relaxed_loss(self.handle, _ptr(U_T), _ptr(target), _ptr(loss), _ptr(g),
-                                      float(scale), self._s()), self.handle)
-        return loss, g
+                                      float(scale), _ptr(obj), self._s()), self.handle)
+        return loss, g, obj
 
     def relaxed_loss_bce(self, U_T, target, pool: int = 8, mse_weight: float = 1.0, eps: float = 1e-6,
                          scale: float = 1.0, want_grad: bool = True):
         """Per-env BCE of the clipped soft scar plus mse_weight x MSE of its
-        pool x pool block means, and scale x dL/dU_T."""
+        pool x pool block means; returns (losses, scale x dL/dU_T or None,
+        objective float64 [1] = scale x sum of the losses)."""
         loss = torch.empty(self.n_env, dtype=torch.float32, device=self.device)
+        obj = torch.empty(1, dtype=torch.float64, device=self.device)
         g = torch.empty_like(U_T) if want_grad else None
         _check(lib().sim_relaxed_loss_bce(self.handle, _ptr(U_T), _ptr(target), int(pool),
                                           float(mse_weight), float(eps), _ptr(loss), _ptr(g),
-                                          float(scale), self._s()), self.handle)
-        return loss, g
+                                          float(scale), _ptr(obj), self._s()), self.handle)
+        return loss, g, obj
 
     def relaxed_loss_any(self, kind: str, U_T, target, scale: float = 1.0, **kw):
         if kind == "iou":
@@ -461,9 +466,9 @@ class RelaxedCalibrationLoss(torch.autograd.Function):
         U, B = sim.relaxed_init()
         ws = sim.relaxed_workspace(T, ckpt_every)
         sim.relaxed_fwd(p, U, B, T, ckpt_every, ws, form)
-        L, gU = sim.relaxed_loss_any(loss, U, target, scale=1.0 / sim.n_env, **(loss_kw or {}))
+        _, gU, obj = sim.relaxed_loss_any(loss, U, target, scale=1.0 / sim.n_env, **(loss_kw or {}))
         ctx.sim, ctx.p, ctx.T, ctx.k, ctx.ws, ctx.gU, ctx.form = sim, p, T, ckpt_every, ws, gU, form
-        return L.double().mean().cpu()
+        return obj.cpu().reshape(())   # the library's fp64 mean over envs
 
     @staticmethod
     def backward(ctx, grad_out):

@@ -6,6 +6,7 @@ fp32 instructions are disabled.
 """
 from __future__ import annotations
 
+import concurrent.futures
 import os
 import shutil
 import subprocess
@@ -22,6 +23,8 @@ HIPCC_FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result",
 ]
+# roctx ranges around every C-ABI call
+LINK_FLAGS = ["-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib", "-lrocprofiler-sdk-roctx"]
 
 
 def hipcc() -> str:
@@ -36,17 +39,29 @@ def sources():
 
 
 def build(force: bool = True, verbose: bool = False) -> str:
-    """Compile the library; with force=False reuse a build newer than its sources."""
+    """Compile the library; with force=False reuse a build newer than its sources.
+    Each source compiles to its own object in parallel, then one link."""
     deps = sources() + [os.path.join(CSRC, h) for h in HEADERS] + [
         os.path.join(HERE, "..", "include", "firesim.h")]
     if not force and os.path.exists(LIB) and \
             os.path.getmtime(LIB) >= max(os.path.getmtime(d) for d in deps):
         return LIB
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc(), *HIPCC_FLAGS, "-x", "hip", *sources(), "-o", tmp]
+    obj_dir = os.path.join(HERE, "_build")
+    os.makedirs(obj_dir, exist_ok=True)
+    tag = "%d" % os.getpid()
+    objs = [os.path.join(obj_dir, os.path.basename(src) + "." + tag + ".o") for src in sources()]
+    cmds = [[hipcc(), *[f for f in HIPCC_FLAGS if f != "-shared"], "-x", "hip", "-c", src, "-o", obj]
+            for src, obj in zip(sources(), objs)]
     if verbose:
-        print(" ".join(cmd))
-    subprocess.check_call(cmd)
+        for c in cmds:
+            print(" ".join(c))
+    with concurrent.futures.ThreadPoolExecutor(max_workers=len(cmds)) as ex:
+        for f in [ex.submit(subprocess.check_call, c) for c in cmds]:
+            f.result()
+    tmp = LIB + ".tmp" + tag
+    subprocess.check_call([hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp, *LINK_FLAGS])
+    for o in objs:
+        os.remove(o)
     os.replace(tmp, LIB)
     return LIB
 

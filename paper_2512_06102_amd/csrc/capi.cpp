@@ -2,6 +2,7 @@
 // device memory, the tile list, step sequencing and graph replay.  All model
 // arithmetic runs in the kernels (stoch.hip, relaxed.hip).
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <cmath>
@@ -46,7 +47,10 @@ struct sim_handle {
     bool wind_cell = false;
     uint64_t seed = 0;
     uint64_t t = 0;
-    sim_plan plan{4, 256, 1, 0, 0, 0};
+    // default launch plan: fuel and elevation read only at front cells, and
+    // tiles with no fire in reach skipped (the dense plan, which streams every
+    // cell's 10 bytes each step, is {4, 256, 1, 0, 0, 0})
+    sim_plan plan{4, 64, 1, 1, 1, 0};
     // wind series (caller-owned device memory, indexed by the absolute step)
     const float* series_env = nullptr;   // [series_T][n_env][3]
     const float* series_cell = nullptr;  // [series_T][3][n_cells]
@@ -60,6 +64,9 @@ struct sim_handle {
     RlFusedShape rl_shape;  // the fused RL step's LDS layout (fits: every env fits it)
 
     EnvDev* d_envs = nullptr;
+    int32_t* d_chunk_env = nullptr;    // env of every loss chunk (kLossChunk cells)
+    int32_t n_chunks = 0;
+    double* d_loss_scratch = nullptr;  // soft-IoU loss partial sums (allocated on first use)
     float* d_g = nullptr;
     float* d_E = nullptr;
     uint8_t* d_cls = nullptr;
@@ -97,6 +104,30 @@ int fail(sim_handle* h, int code, const char* fmt, ...)
     return code;
 }
 
+// Every entry point runs with the handle's GPU current (the caller's
+// current device is restored on return) and shows as a named range in a
+// marker trace (rocprofv3 --marker-trace).
+class CallScope {
+public:
+    CallScope(const char* name, const sim_handle* h)
+    {
+        roctxRangePushA(name);
+        if (h && hipGetDevice(&prev_) == hipSuccess && prev_ != h->device)
+            switched_ = hipSetDevice(h->device) == hipSuccess;
+    }
+    ~CallScope()
+    {
+        if (switched_) (void)hipSetDevice(prev_);
+        roctxRangePop();
+    }
+    CallScope(const CallScope&) = delete;
+    CallScope& operator=(const CallScope&) = delete;
+
+private:
+    int prev_ = 0;
+    bool switched_ = false;
+};
+
 #define HIP_OR_FAIL(h, expr)                                                              \
     do {                                                                                  \
         hipError_t e_ = (expr);                                                           \
@@ -106,7 +137,7 @@ int fail(sim_handle* h, int code, const char* fmt, ...)
 
 void free_all(sim_handle* h)
 {
-    void* ptrs[] = {h->d_envs, h->d_g, h->d_E, h->d_cls, h->d_den, h->d_wind, h->d_init_states,
+    void* ptrs[] = {h->d_envs, h->d_chunk_env, h->d_loss_scratch, h->d_g, h->d_E, h->d_cls, h->d_den, h->d_wind, h->d_init_states,
                     h->d_tmp, h->d_t, h->d_tiles, h->d_tile_nbr, h->d_tile_burn, h->d_tile_eq,
                     h->d_rl_drop, h->d_rl_counts};
     for (void* p : ptrs)
@@ -328,6 +359,7 @@ int sim_init(sim_handle** out, const sim_params* p, int32_t n_env, const sim_env
              const float* elevation, const float* wind_cell, const int32_t* ignitions,
              int32_t n_ign, uint64_t seed, uint8_t* states_out, void* stream)
 {
+    CallScope scope("sim_init", nullptr);
     g_init_error.clear();
     if (!out) return fail(nullptr, SIM_EINVAL, "out is NULL");
     *out = nullptr;
@@ -400,9 +432,14 @@ int sim_init(sim_handle** out, const sim_params* p, int32_t n_env, const sim_env
     }
 
     std::vector<EnvDev> ed(n_env);
-    for (int32_t e = 0; e < n_env; ++e)
+    std::vector<int32_t> chunk_env;
+    for (int32_t e = 0; e < n_env; ++e) {
         ed[e] = EnvDev{envs[e].offset, envs[e].H, envs[e].W, envs[e].env_id,
-                       envs[e].V, envs[e].Vx, envs[e].Vy, 0.0f};
+                       envs[e].V, envs[e].Vx, envs[e].Vy, (int32_t)chunk_env.size()};
+        const int64_t nch = ((int64_t)envs[e].H * envs[e].W + kLossChunk - 1) / kLossChunk;
+        chunk_env.insert(chunk_env.end(), (size_t)nch, e);
+    }
+    h->n_chunks = (int32_t)chunk_env.size();
     const size_t n = (size_t)n_cells;
     int rc;
 #define ALLOC(ptr, bytes)                                                                   \
@@ -411,6 +448,7 @@ int sim_init(sim_handle** out, const sim_params* p, int32_t n_env, const sim_env
         return bail(SIM_ENOMEM);                                                            \
     }
     ALLOC(h->d_envs, sizeof(EnvDev) * n_env);
+    ALLOC(h->d_chunk_env, sizeof(int32_t) * chunk_env.size());
     ALLOC(h->d_g, 4 * n);
     ALLOC(h->d_E, 4 * n);
     ALLOC(h->d_cls, n);
@@ -421,7 +459,9 @@ int sim_init(sim_handle** out, const sim_params* p, int32_t n_env, const sim_env
     if (h->wind_cell) ALLOC(h->d_wind, 12 * n);
 #undef ALLOC
     int32_t* d_ign = nullptr;
-    if (hipMemcpy(h->d_envs, ed.data(), sizeof(EnvDev) * n_env, hipMemcpyHostToDevice) != hipSuccess) {
+    if (hipMemcpy(h->d_envs, ed.data(), sizeof(EnvDev) * n_env, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(h->d_chunk_env, chunk_env.data(), sizeof(int32_t) * chunk_env.size(),
+                  hipMemcpyHostToDevice) != hipSuccess) {
         fail(h, SIM_EHIP, "env table upload failed");
         return bail(SIM_EHIP);
     }
@@ -516,12 +556,14 @@ int step_common(sim_handle* h, uint8_t* states, const int32_t* actions, int32_t 
 int sim_step(sim_handle* h, uint8_t* states, const int32_t* actions, int32_t T, int32_t* counts,
              void* stream)
 {
+    CallScope scope("sim_step", h);
     return step_common(h, states, actions, T, counts, nullptr, stream);
 }
 
 int sim_step_history(sim_handle* h, uint8_t* states, const int32_t* actions, int32_t T, int32_t* counts,
                      uint8_t* history, void* stream)
 {
+    CallScope scope("sim_step_history", h);
     if (h && !history) return fail(h, SIM_EINVAL, "history is NULL");
     return step_common(h, states, actions, T, counts, history, stream);
 }
@@ -556,6 +598,7 @@ RlConfigDev rl_dev(const sim_rl_config* cfg)
 int sim_rl_reset(sim_handle* h, const sim_rl_config* cfg, uint8_t* states, sim_rl_agent* agents,
                  const int32_t* reset_mask, uint64_t episode, uint8_t* obs, int32_t* done_out, void* stream)
 {
+    CallScope scope("sim_rl_reset", h);
     int rc = rl_check(h, cfg, states, agents, obs);
     if (rc != SIM_OK) return rc;
     hipStream_t s = (hipStream_t)stream;
@@ -571,6 +614,7 @@ int sim_rl_reset(sim_handle* h, const sim_rl_config* cfg, uint8_t* states, sim_r
 int sim_rl_step(sim_handle* h, const sim_rl_config* cfg, uint8_t* states, sim_rl_agent* agents,
                 const int32_t* actions, uint8_t* obs, float* reward, int32_t* done, void* stream)
 {
+    CallScope scope("sim_rl_step", h);
     int rc = rl_check(h, cfg, states, agents, obs);
     if (rc != SIM_OK) return rc;
     if (!actions || !reward || !done) return fail(h, SIM_EINVAL, "actions, reward and done are required");
@@ -601,6 +645,7 @@ int sim_rl_step(sim_handle* h, const sim_rl_config* cfg, uint8_t* states, sim_rl
 
 int sim_set_drop(sim_handle* h, int32_t mode, int32_t radius)
 {
+    CallScope scope("sim_set_drop", h);
     if (!h) return fail(nullptr, SIM_EINVAL, "handle is NULL");
     if (mode != SIM_DROP_SUPPRESS && mode != SIM_DROP_WATER) return fail(h, SIM_EINVAL, "unknown drop mode");
     if (radius < 0 || radius > 255) return fail(h, SIM_EINVAL, "drop radius must be in 0..255");
@@ -612,6 +657,7 @@ int sim_set_drop(sim_handle* h, int32_t mode, int32_t radius)
 
 int sim_set_wind_series(sim_handle* h, const float* env_wind, const float* cell_wind, int64_t series_T)
 {
+    CallScope scope("sim_set_wind_series", h);
     if (!h) return fail(nullptr, SIM_EINVAL, "handle is NULL");
     if (env_wind && cell_wind) return fail(h, SIM_EINVAL, "give a per-env or a per-cell series, not both");
     if ((env_wind || cell_wind) && series_T < 1) return fail(h, SIM_EINVAL, "series_T must be >= 1");
@@ -634,6 +680,7 @@ int sim_get_step(const sim_handle* h, uint64_t* t)
 
 int sim_set_step(sim_handle* h, uint64_t t)
 {
+    CallScope scope("sim_set_step", h);
     if (!h) return SIM_EINVAL;
     if (t > 0xFFFFFFFFull) return fail(h, SIM_EINVAL, "step counter must be < 2^32");
     h->t = t;
@@ -642,6 +689,7 @@ int sim_set_step(sim_handle* h, uint64_t t)
 
 int sim_set_plan(sim_handle* h, const sim_plan* plan)
 {
+    CallScope scope("sim_set_plan", h);
     if (!h || !plan) return SIM_EINVAL;
     sim_plan p = *plan;
     const int rc = validate_plan(h, p);
@@ -661,6 +709,7 @@ int sim_autotune(sim_handle* h, const uint8_t* states, int32_t T_probe, int32_t 
                  int32_t allow_sparse, sim_tune_result* results, int32_t max_results,
                  int32_t* n_results, void* stream)
 {
+    CallScope scope("sim_autotune", h);
     if (!h) return fail(nullptr, SIM_EINVAL, "handle is NULL");
     if (!states || T_probe < 1 || max_results < 0 || (max_results > 0 && !results))
         return fail(h, SIM_EINVAL, "need states, T_probe >= 1 and a results array");
@@ -728,6 +777,7 @@ int sim_autotune(sim_handle* h, const uint8_t* states, int32_t T_probe, int32_t 
 
 int sim_relaxed_init(sim_handle* h, double* U, double* B, void* stream)
 {
+    CallScope scope("sim_relaxed_init", h);
     if (!h || !U || !B) return fail(h, SIM_EINVAL, "handle, U and B are required");
     HIP_OR_FAIL(h, launch_relaxed_init(
                        (hipStream_t)stream, h->d_init_states, h->n_cells, U, B));
@@ -777,6 +827,7 @@ int sim_step_relaxed_fwd(sim_handle* h, const sim_params* p, double* U, double* 
                          int32_t ckpt_every, int32_t form, void* workspace, size_t workspace_bytes,
                          void* stream)
 {
+    CallScope scope("sim_step_relaxed_fwd", h);
     if (!h) return fail(nullptr, SIM_EINVAL, "handle is NULL");
     int rc = check_relaxed_params(h, p);
     if (rc) return rc;
@@ -796,23 +847,33 @@ int sim_step_relaxed_fwd(sim_handle* h, const sim_params* p, double* U, double* 
     return SIM_OK;
 }
 
-int sim_relaxed_loss(sim_handle* h, const double* U_T, const uint8_t* target, float* loss,
-                     double* gU_T, double scale, void* stream)
+static LossBatch loss_batch(const sim_handle* h)
 {
+    return LossBatch{h->d_envs, h->n_env, h->d_chunk_env, h->n_chunks, h->d_init_states};
+}
+
+int sim_relaxed_loss(sim_handle* h, const double* U_T, const uint8_t* target, float* loss,
+                     double* gU_T, double scale, double* objective, void* stream)
+{
+    CallScope scope("sim_relaxed_loss", h);
     if (!h) return fail(nullptr, SIM_EINVAL, "handle is NULL");
     if (!U_T || !target || !loss) return fail(h, SIM_EINVAL, "U_T, target and loss are required");
-    if (relaxed_prepare(h->relaxed, h->envs) != 0)
-        return fail(h, SIM_ENOMEM, "relaxed tile list allocation failed");
-    hipError_t e = relaxed_loss((hipStream_t)stream, relaxed_inputs(h), h->d_init_states, U_T,
-                                target, loss, gU_T, scale, h->relaxed);
+    if (!h->d_loss_scratch &&
+        hipMalloc(&h->d_loss_scratch, sizeof(double) * loss_scratch_doubles(h->n_chunks, h->n_env)) != hipSuccess) {
+        h->d_loss_scratch = nullptr;
+        return fail(h, SIM_ENOMEM, "loss scratch allocation failed");
+    }
+    hipError_t e = relaxed_loss((hipStream_t)stream, loss_batch(h), U_T, target, loss, gU_T, scale, objective,
+                                h->d_loss_scratch);
     if (e != hipSuccess) return fail(h, SIM_EHIP, "relaxed loss failed: %s", hipGetErrorString(e));
     return SIM_OK;
 }
 
 int sim_relaxed_loss_bce(sim_handle* h, const double* U_T, const uint8_t* target, int32_t pool,
                          double mse_weight, double eps, float* loss, double* gU_T, double scale,
-                         void* stream)
+                         double* objective, void* stream)
 {
+    CallScope scope("sim_relaxed_loss_bce", h);
     if (!h) return fail(nullptr, SIM_EINVAL, "handle is NULL");
     if (!U_T || !target || !loss) return fail(h, SIM_EINVAL, "U_T, target and loss are required");
     if (pool < 1 || pool > 64 || !(eps > 0.0 && eps < 0.5) || !(mse_weight >= 0.0))
@@ -820,7 +881,7 @@ int sim_relaxed_loss_bce(sim_handle* h, const double* U_T, const uint8_t* target
     if (relaxed_prepare(h->relaxed, h->envs) != 0 || relaxed_prepare_pool(h->relaxed, h->envs, pool) != 0)
         return fail(h, SIM_ENOMEM, "relaxed tables allocation failed");
     hipError_t e = relaxed_loss_bce((hipStream_t)stream, relaxed_inputs(h), h->d_init_states, U_T,
-                                    target, pool, mse_weight, eps, loss, gU_T, scale, h->relaxed);
+                                    target, pool, mse_weight, eps, loss, gU_T, scale, objective, h->relaxed);
     if (e != hipSuccess) return fail(h, SIM_EHIP, "relaxed loss failed: %s", hipGetErrorString(e));
     return SIM_OK;
 }
@@ -829,6 +890,7 @@ int sim_step_relaxed_bwd(sim_handle* h, const sim_params* p, const double* gU_T,
                          int32_t T, int32_t ckpt_every, int32_t form, void* workspace,
                          size_t workspace_bytes, double* grad, void* stream)
 {
+    CallScope scope("sim_step_relaxed_bwd", h);
     if (!h) return fail(nullptr, SIM_EINVAL, "handle is NULL");
     int rc = check_relaxed_params(h, p);
     if (rc) return rc;
@@ -849,18 +911,21 @@ int sim_step_relaxed_bwd(sim_handle* h, const sim_params* p, const double* gU_T,
 
 int sim_debug_atan(const float* x, float* y, int64_t n, void* stream)
 {
+    CallScope scope("sim_debug_atan", nullptr);
     if (n < 0 || (n > 0 && (!x || !y))) return SIM_EINVAL;
     return launch_debug_atan((hipStream_t)stream, x, y, n) == hipSuccess ? SIM_OK : SIM_EHIP;
 }
 
 int sim_debug_exp(const float* x, float* y, int64_t n, void* stream)
 {
+    CallScope scope("sim_debug_exp", nullptr);
     if (n < 0 || (n > 0 && (!x || !y))) return SIM_EINVAL;
     return launch_debug_exp((hipStream_t)stream, x, y, n) == hipSuccess ? SIM_OK : SIM_EHIP;
 }
 
 int sim_debug_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int64_t n, void* stream)
 {
+    CallScope scope("sim_debug_philox", nullptr);
     if (n < 0 || (n > 0 && (!ctr || !key || !out))) return SIM_EINVAL;
     return launch_debug_philox((hipStream_t)stream, ctr, key, out, n) == hipSuccess ? SIM_OK : SIM_EHIP;
 }
@@ -872,6 +937,7 @@ const char* sim_last_error(const sim_handle* h)
 
 void sim_destroy(sim_handle* h)
 {
+    CallScope scope("sim_destroy", h);
     if (!h) return;
     (void)hipDeviceSynchronize();
     free_all(h);

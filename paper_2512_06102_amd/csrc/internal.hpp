@@ -8,14 +8,17 @@ namespace firesim {
 
 enum : uint8_t { kUnburnable = 0, kFlammable = 1, kBurning = 2, kBurnt = 3 };
 
-// Device copy of one env descriptor.
+// Device copy of one env descriptor.  The env's cells also form
+// ceil(H W / kLossChunk) runs of kLossChunk cells for the loss reductions,
+// numbered from chunk0 in a batch-wide list.
 struct EnvDev {
     int64_t offset;
     int32_t H, W;
     uint32_t env_id;
     float V, Vx, Vy;
-    float pad;
+    int32_t chunk0;
 };
+constexpr int kLossChunk = 4096;
 
 // Scalar parameters of the stochastic step, as kernel arguments.
 struct StepArgs {

@@ -573,82 +573,139 @@ __global__ void stripes_sum_kernel(const double* __restrict__ stripes, double* _
     grad[j] = s;
 }
 
-// Per-env sums of the soft-IoU loss: I = sum S Y, sum S, sum Y.
-__global__ __launch_bounds__(256) void loss_sums_kernel(
-    const RelaxedTile* __restrict__ tiles, const EnvDev* __restrict__ envs,
-    const uint8_t* __restrict__ init_states, const double* __restrict__ U_T,
-    const uint8_t* __restrict__ target, double* __restrict__ acc, int32_t n_env)
+// ---------------------------------------------------------------- losses
+// Every reduction below runs in a fixed order (lane-strided partial sums,
+// xor butterflies, then the four wave sums in order), so the losses, the
+// objective and the seed are the same bits on every call.
+
+// Sum over the 64 lanes of a wave (every lane receives it).
+__device__ __forceinline__ double wave_sum(double v)
 {
-    __shared__ double sred[4][3];
-    const RelaxedTile td = tiles[blockIdx.x];
-    const EnvDev ed = envs[td.env];
-    const int tid = threadIdx.x;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// Sum over a 256-lane workgroup, returned to every lane.
+__device__ __forceinline__ double block_sum256(double v, double* red)
+{
+    v = wave_sum(v);
+    __syncthreads();  // red may still be read by a previous call
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+// Soft IoU, stage 1: per loss chunk (kLossChunk cells of one env), the sums
+// I = sum S Y, sum S and sum Y, with S = 1 - U_T on burnable cells.
+__global__ __launch_bounds__(256) void iou_partials_kernel(const int32_t* __restrict__ chunk_env,
+                                                           const EnvDev* __restrict__ envs,
+                                                           const uint8_t* __restrict__ init_states,
+                                                           const double* __restrict__ U_T,
+                                                           const uint8_t* __restrict__ target,
+                                                           double* __restrict__ partial)
+{
+    __shared__ double red[4];
+    const int c = blockIdx.x;
+    const EnvDev ed = envs[chunk_env[c]];
+    const int64_t n = (int64_t)ed.H * ed.W;
+    const int64_t first = (int64_t)(c - ed.chunk0) * kLossChunk;
+    const int64_t last = min(first + (int64_t)kLossChunk, n);
     double sy = 0.0, ss = 0.0, yy = 0.0;
-    for (int idx = tid; idx < TW * TH; idx += 256) {
-        const int gi = td.r0 + idx / TW, gj = td.c0 + idx % TW;
-        if (gi >= ed.H || gj >= ed.W) continue;
-        const int64_t v = ed.offset + (int64_t)gi * ed.W + gj;
+    for (int64_t i = first + threadIdx.x; i < last; i += 256) {
+        const int64_t v = ed.offset + i;
         const double S = init_states[v] != kUnburnable ? 1.0 - U_T[v] : 0.0;
         const double Y = target[v] ? 1.0 : 0.0;
         sy += S * Y;
         ss += S;
         yy += Y;
     }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        sy += __shfl_xor(sy, off);
-        ss += __shfl_xor(ss, off);
-        yy += __shfl_xor(yy, off);
-    }
-    if ((tid & 63) == 0) {
-        sred[tid >> 6][0] = sy;
-        sred[tid >> 6][1] = ss;
-        sred[tid >> 6][2] = yy;
-    }
-    __syncthreads();
-    if (tid < 3) {
-        const double t = sred[0][tid] + sred[1][tid] + sred[2][tid] + sred[3][tid];
-        if (t != 0.0) unsafeAtomicAdd(acc + tid * n_env + td.env, t);
+    sy = block_sum256(sy, red);
+    ss = block_sum256(ss, red);
+    yy = block_sum256(yy, red);
+    if (threadIdx.x == 0) {
+        partial[3 * c] = sy;
+        partial[3 * c + 1] = ss;
+        partial[3 * c + 2] = yy;
     }
 }
 
-__global__ __launch_bounds__(256) void loss_grad_kernel(
-    const RelaxedTile* __restrict__ tiles, const EnvDev* __restrict__ envs,
-    const uint8_t* __restrict__ init_states, const uint8_t* __restrict__ target,
-    const double* __restrict__ acc, int32_t n_env, double scale, double* __restrict__ gU_T)
+// Soft IoU, stage 2 (one wave per env): the env's sums over its chunks and
+// L_e = 1 - I / D, D = sum S + sum Y - I (0 when D = 0).
+__global__ __launch_bounds__(64) void iou_env_kernel(const EnvDev* __restrict__ envs,
+                                                     const double* __restrict__ partial,
+                                                     double* __restrict__ sums, double* __restrict__ env_loss,
+                                                     float* __restrict__ loss)
 {
-    const RelaxedTile td = tiles[blockIdx.x];
-    const EnvDev ed = envs[td.env];
-    const double I = acc[td.env], Ssum = acc[n_env + td.env], Ysum = acc[2 * n_env + td.env];
-    const double D = Ssum + Ysum - I;
-    for (int idx = threadIdx.x; idx < TW * TH; idx += 256) {
-        const int gi = td.r0 + idx / TW, gj = td.c0 + idx % TW;
-        if (gi >= ed.H || gj >= ed.W) continue;
-        const int64_t v = ed.offset + (int64_t)gi * ed.W + gj;
+    const int e = blockIdx.x, lane = threadIdx.x;
+    const EnvDev ed = envs[e];
+    const int nch = (int)(((int64_t)ed.H * ed.W + kLossChunk - 1) / kLossChunk);
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int c = lane; c < nch; c += 64) {
+        const double* p = partial + 3 * (int64_t)(ed.chunk0 + c);
+        a0 += p[0];
+        a1 += p[1];
+        a2 += p[2];
+    }
+    a0 = wave_sum(a0);
+    a1 = wave_sum(a1);
+    a2 = wave_sum(a2);
+    if (lane == 0) {
+        const double D = (a1 + a2) - a0;
+        const double L = D > 0.0 ? 1.0 - a0 / D : 0.0;
+        sums[3 * e] = a0;
+        sums[3 * e + 1] = a1;
+        sums[3 * e + 2] = a2;
+        env_loss[e] = L;
+        loss[e] = (float)L;
+    }
+}
+
+// The objective scale * sum_e L_e (one workgroup).
+__global__ __launch_bounds__(256) void objective_kernel(const double* __restrict__ env_loss, int32_t n_env,
+                                                        double scale, double* __restrict__ objective)
+{
+    __shared__ double red[4];
+    double a = 0.0;
+    for (int e = threadIdx.x; e < n_env; e += 256) a += env_loss[e];
+    a = block_sum256(a, red);
+    if (threadIdx.x == 0) objective[0] = scale * a;
+}
+
+// Soft IoU, stage 3: the seed scale * dL_e/dU_T = scale (Y D - I (1 - Y)) / D^2
+// on burnable cells (dL/dU = -dL/dS), 0 elsewhere.
+__global__ __launch_bounds__(256) void iou_seed_kernel(const int32_t* __restrict__ chunk_env,
+                                                       const EnvDev* __restrict__ envs,
+                                                       const uint8_t* __restrict__ init_states,
+                                                       const uint8_t* __restrict__ target,
+                                                       const double* __restrict__ sums, double scale,
+                                                       double* __restrict__ gU_T)
+{
+    const int c = blockIdx.x;
+    const int e = chunk_env[c];
+    const EnvDev ed = envs[e];
+    const int64_t n = (int64_t)ed.H * ed.W;
+    const int64_t first = (int64_t)(c - ed.chunk0) * kLossChunk;
+    const int64_t last = min(first + (int64_t)kLossChunk, n);
+    const double I = sums[3 * e], D = (sums[3 * e + 1] + sums[3 * e + 2]) - I;
+    for (int64_t i = first + threadIdx.x; i < last; i += 256) {
+        const int64_t v = ed.offset + i;
         double gv = 0.0;
         if (D > 0.0 && init_states[v] != kUnburnable) {
             const double Y = target[v] ? 1.0 : 0.0;
-            gv = scale * (Y * D - I * (1.0 - Y)) / (D * D);  // dL/dU = -dL/dS
+            gv = scale * (Y * D - I * (1.0 - Y)) / (D * D);
         }
         gU_T[v] = gv;
     }
 }
 
-__global__ void loss_final_kernel(const double* __restrict__ acc, int32_t n_env, float* __restrict__ loss)
-{
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n_env) return;
-    const double I = acc[e], D = acc[n_env + e] + acc[2 * n_env + e] - acc[e];
-    loss[e] = D > 0.0 ? (float)(1.0 - I / D) : 0.0f;
-}
-
 // The paper's calibration loss: BCE of the clipped soft scar plus the mean
-// squared error of pool x pool block averages.  One lane per pooled block.
+// squared error of pool x pool block averages.  One lane per pooled block:
+// the block means of S and Y, the block's BCE sum and squared error.
 __global__ __launch_bounds__(256) void bce_pool_sums_kernel(
     const RelaxedTile* __restrict__ blocks, int32_t n_pool, int32_t pool, const EnvDev* __restrict__ envs,
     const uint8_t* __restrict__ init_states, const double* __restrict__ U_T,
-    const uint8_t* __restrict__ target, double eps, double* __restrict__ vals, double* __restrict__ acc,
-    int32_t n_env)
+    const uint8_t* __restrict__ target, double eps, double* __restrict__ vals)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= n_pool) return;
@@ -670,8 +727,32 @@ __global__ __launch_bounds__(256) void bce_pool_sums_kernel(
     const double pS = sS / cnt, pY = sY / cnt;
     vals[b] = pS;
     vals[n_pool + b] = pY;
-    unsafeAtomicAdd(acc + pb.env, bce);
-    unsafeAtomicAdd(acc + n_env + pb.env, (pS - pY) * (pS - pY));
+    vals[2 * (int64_t)n_pool + b] = bce;
+    vals[3 * (int64_t)n_pool + b] = (pS - pY) * (pS - pY);
+}
+
+// Per env (one wave): BCE over its cells plus mse_weight times the mean
+// squared error over its blocks.
+__global__ __launch_bounds__(64) void bce_env_kernel(const EnvDev* __restrict__ envs,
+                                                     const int32_t* __restrict__ env_blocks, int32_t n_pool,
+                                                     const double* __restrict__ vals, double mse_weight,
+                                                     double* __restrict__ env_loss, float* __restrict__ loss)
+{
+    const int e = blockIdx.x, lane = threadIdx.x;
+    const int first = env_blocks[2 * e], nb = env_blocks[2 * e + 1];
+    double bce = 0.0, sq = 0.0;
+    for (int b = lane; b < nb; b += 64) {
+        bce += vals[2 * (int64_t)n_pool + first + b];
+        sq += vals[3 * (int64_t)n_pool + first + b];
+    }
+    bce = wave_sum(bce);
+    sq = wave_sum(sq);
+    if (lane == 0) {
+        const double n_e = (double)envs[e].H * (double)envs[e].W;
+        const double L = bce / n_e + mse_weight * sq / (double)nb;
+        env_loss[e] = L;
+        loss[e] = (float)L;
+    }
 }
 
 __global__ __launch_bounds__(256) void bce_pool_grad_kernel(
@@ -685,7 +766,7 @@ __global__ __launch_bounds__(256) void bce_pool_grad_kernel(
     const RelaxedTile pb = blocks[b];
     const EnvDev ed = envs[pb.env];
     const int i1 = min(pb.r0 + pool, ed.H), j1 = min(pb.c0 + pool, ed.W);
-    const double n_e = (double)ed.H * (double)ed.W, m_e = (double)env_blocks[pb.env];
+    const double n_e = (double)ed.H * (double)ed.W, m_e = (double)env_blocks[2 * pb.env + 1];
     const double cnt = (double)(i1 - pb.r0) * (double)(j1 - pb.c0);
     const double dmse = 2.0 * (vals[b] - vals[n_pool + b]) / m_e / cnt;  // d mse / d S of each cell
     for (int i = pb.r0; i < i1; ++i)
@@ -700,16 +781,6 @@ __global__ __launch_bounds__(256) void bce_pool_grad_kernel(
             }
             gU_T[v] = gv;
         }
-}
-
-__global__ void bce_pool_final_kernel(const double* __restrict__ acc, const EnvDev* __restrict__ envs,
-                                      const int32_t* __restrict__ env_blocks, int32_t n_env,
-                                      double mse_weight, float* __restrict__ loss)
-{
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n_env) return;
-    const double n_e = (double)envs[e].H * (double)envs[e].W;
-    loss[e] = (float)(acc[e] / n_e + mse_weight * acc[n_env + e] / (double)env_blocks[e]);
 }
 
 int blocks_for(int64_t n)
@@ -836,7 +907,6 @@ int relaxed_prepare(RelaxedState& R, const std::vector<sim_env>& envs)
     R.n_tiles = (int32_t)tiles.size();
     R.n_btiles = (int32_t)btiles.size();
     R.n_env = (int32_t)envs.size();
-    if (hipMalloc(&R.d_loss_acc, sizeof(double) * 3 * R.n_env) != hipSuccess) return -1;
     if (ioff < INT32_MAX && 4 * max_img <= 64 * 1024) {
         if (hipMalloc(&R.d_tgrid, grids.size() * sizeof(TileGrid)) != hipSuccess ||
             hipMalloc(&R.d_tmass, btiles.size() * sizeof(int32_t)) != hipSuccess ||
@@ -854,23 +924,24 @@ int relaxed_prepare_pool(RelaxedState& R, const std::vector<sim_env>& envs, int 
 {
     if (R.d_pool && R.pool_k == pool) return 0;
     for (void** p : {(void**)&R.d_pool, (void**)&R.d_env_blocks, (void**)&R.d_pool_vals,
-                     (void**)&R.d_bce_acc}) {
+                     (void**)&R.d_bce_loss}) {
         if (*p) (void)hipFree(*p);
         *p = nullptr;
     }
     std::vector<RelaxedTile> blocks;
-    std::vector<int32_t> per_env;
+    std::vector<int32_t> per_env;  // first block, number of blocks
     for (int32_t e = 0; e < (int32_t)envs.size(); ++e) {
         const size_t before = blocks.size();
         for (int r0 = 0; r0 < envs[e].H; r0 += pool)
             for (int c0 = 0; c0 < envs[e].W; c0 += pool) blocks.push_back(RelaxedTile{e, r0, c0, 0});
+        per_env.push_back((int32_t)before);
         per_env.push_back((int32_t)(blocks.size() - before));
     }
     R.n_pool = (int32_t)blocks.size();
     if (hipMalloc(&R.d_pool, blocks.size() * sizeof(RelaxedTile)) != hipSuccess ||
         hipMalloc(&R.d_env_blocks, per_env.size() * sizeof(int32_t)) != hipSuccess ||
-        hipMalloc(&R.d_pool_vals, 2 * blocks.size() * sizeof(double)) != hipSuccess ||
-        hipMalloc(&R.d_bce_acc, 2 * per_env.size() * sizeof(double)) != hipSuccess)
+        hipMalloc(&R.d_pool_vals, 4 * blocks.size() * sizeof(double)) != hipSuccess ||
+        hipMalloc(&R.d_bce_loss, envs.size() * sizeof(double)) != hipSuccess)
         return -1;
     if (hipMemcpy(R.d_pool, blocks.data(), blocks.size() * sizeof(RelaxedTile), hipMemcpyHostToDevice) !=
             hipSuccess ||
@@ -883,8 +954,8 @@ int relaxed_prepare_pool(RelaxedState& R, const std::vector<sim_env>& envs, int 
 
 void relaxed_free(RelaxedState& R)
 {
-    for (void* p : {(void*)R.d_tiles, (void*)R.d_btiles, (void*)R.d_loss_acc, (void*)R.d_pool,
-                    (void*)R.d_env_blocks, (void*)R.d_pool_vals, (void*)R.d_bce_acc, (void*)R.d_tgrid,
+    for (void* p : {(void*)R.d_tiles, (void*)R.d_btiles, (void*)R.d_pool,
+                    (void*)R.d_env_blocks, (void*)R.d_pool_vals, (void*)R.d_bce_loss, (void*)R.d_tgrid,
                     (void*)R.d_tmass, (void*)R.d_tinteg})
         if (p) (void)hipFree(p);
     R = RelaxedState{};
@@ -917,7 +988,7 @@ hipError_t relaxed_forward(hipStream_t s, const RelaxedInputs& in, const sim_par
     float* g = reinterpret_cast<float*>(ws + L.g);
     double* ckpt = reinterpret_cast<double*>(ws + L.ckpt);
     double* seg = reinterpret_cast<double*>(ws + L.seg);
-    double* scratch[2] = {reinterpret_cast<double*>(ws + L.fwd), seg};
+    double* spare[2] = {reinterpret_cast<double*>(ws + L.fwd), seg};
     const RelaxedArgs A = relaxed_args(p);
     const int32_t t_last = ((T - 1) / k) * k;  // first step of the last segment
     hipError_t e = fuel(s, in, p, g);
@@ -938,7 +1009,7 @@ hipError_t relaxed_forward(hipStream_t s, const RelaxedInputs& in, const sim_par
             nu = seg + (size_t)(t1 - t_last) * 2 * n;
             nb = nu + n;
         } else {
-            nu = scratch[0] == cu ? scratch[1] : scratch[0];
+            nu = spare[0] == cu ? spare[1] : spare[0];
             nb = nu + n;
         }
         e = fwd_step(s, at_step(in, t), A, g, cu, cb, nu, nb);
@@ -949,21 +1020,25 @@ hipError_t relaxed_forward(hipStream_t s, const RelaxedInputs& in, const sim_par
     return e;
 }
 
-hipError_t relaxed_loss(hipStream_t s, const RelaxedInputs& in, const uint8_t* init_states,
-                        const double* U_T, const uint8_t* target, float* loss, double* gU_T,
-                        double scale, RelaxedState& R)
+hipError_t relaxed_loss(hipStream_t s, const LossBatch& lb, const double* U_T, const uint8_t* target,
+                        float* loss, double* gU_T, double scale, double* objective, double* scr)
 {
-    hipError_t e = fill_f64(s, R.d_loss_acc, (int64_t)3 * in.n_env, 0.0);
+    double* partial = scr;
+    double* sums = partial + 3 * (size_t)lb.n_chunks;
+    double* env_loss = sums + 3 * (size_t)lb.n_env;
+    hipLaunchKernelGGL(iou_partials_kernel, dim3(lb.n_chunks), dim3(256), 0, s, lb.chunk_env, lb.envs,
+                       lb.init_states, U_T, target, partial);
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(loss_sums_kernel, dim3(in.n_tiles), dim3(256), 0, s, in.tiles, in.envs,
-                       init_states, U_T, target, R.d_loss_acc, in.n_env);
+    hipLaunchKernelGGL(iou_env_kernel, dim3(lb.n_env), dim3(64), 0, s, lb.envs, partial, sums, env_loss, loss);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(loss_final_kernel, dim3((in.n_env + 255) / 256), dim3(256), 0, s, R.d_loss_acc,
-                       in.n_env, loss);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (objective) {
+        hipLaunchKernelGGL(objective_kernel, dim3(1), dim3(256), 0, s, env_loss, lb.n_env, scale, objective);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     if (gU_T) {
-        hipLaunchKernelGGL(loss_grad_kernel, dim3(in.n_tiles), dim3(256), 0, s, in.tiles, in.envs,
-                           init_states, target, R.d_loss_acc, in.n_env, scale, gU_T);
+        hipLaunchKernelGGL(iou_seed_kernel, dim3(lb.n_chunks), dim3(256), 0, s, lb.chunk_env, lb.envs,
+                           lb.init_states, target, sums, scale, gU_T);
         e = hipGetLastError();
     }
     return e;
@@ -971,17 +1046,21 @@ hipError_t relaxed_loss(hipStream_t s, const RelaxedInputs& in, const uint8_t* i
 
 hipError_t relaxed_loss_bce(hipStream_t s, const RelaxedInputs& in, const uint8_t* init_states,
                             const double* U_T, const uint8_t* target, int pool, double mse_weight,
-                            double eps, float* loss, double* gU_T, double scale, RelaxedState& R)
+                            double eps, float* loss, double* gU_T, double scale, double* objective,
+                            RelaxedState& R)
 {
-    hipError_t e = fill_f64(s, R.d_bce_acc, (int64_t)2 * in.n_env, 0.0);
-    if (e != hipSuccess) return e;
     const int nb = (R.n_pool + 255) / 256;
     hipLaunchKernelGGL(bce_pool_sums_kernel, dim3(nb), dim3(256), 0, s, R.d_pool, R.n_pool, pool, in.envs,
-                       init_states, U_T, target, eps, R.d_pool_vals, R.d_bce_acc, in.n_env);
+                       init_states, U_T, target, eps, R.d_pool_vals);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(bce_env_kernel, dim3(in.n_env), dim3(64), 0, s, in.envs, R.d_env_blocks, R.n_pool,
+                       R.d_pool_vals, mse_weight, R.d_bce_loss, loss);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(bce_pool_final_kernel, dim3((in.n_env + 255) / 256), dim3(256), 0, s, R.d_bce_acc,
-                       in.envs, R.d_env_blocks, in.n_env, mse_weight, loss);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (objective) {
+        hipLaunchKernelGGL(objective_kernel, dim3(1), dim3(256), 0, s, R.d_bce_loss, in.n_env, scale, objective);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     if (gU_T) {
         hipLaunchKernelGGL(bce_pool_grad_kernel, dim3(nb), dim3(256), 0, s, R.d_pool, R.n_pool, pool, in.envs,
                            R.d_env_blocks, init_states, U_T, target, eps, mse_weight, R.d_pool_vals, scale,

@@ -33,14 +33,13 @@ struct RelaxedState {
     int32_t n_tiles = 0;
     RelaxedTile* d_btiles = nullptr;  // adjoint tiles
     int32_t n_btiles = 0;
-    double* d_loss_acc = nullptr;  // [3][n_env]: sum S Y, sum S, sum Y
     int32_t n_env = 0;
     // pooled blocks of the BCE + pooled-MSE loss (built for one pool size)
     RelaxedTile* d_pool = nullptr;  // env, r0, c0 of each pool x pool block
     int32_t n_pool = 0, pool_k = 0;
-    int32_t* d_env_blocks = nullptr;  // blocks per env
-    double* d_pool_vals = nullptr;    // [2][n_pool]: block means of S and Y
-    double* d_bce_acc = nullptr;      // [2][n_env]: BCE sum, squared-error sum
+    int32_t* d_env_blocks = nullptr;  // [n_env][2]: first block, number of blocks
+    double* d_pool_vals = nullptr;    // [4][n_pool]: block means of S and Y, BCE sum, squared error
+    double* d_bce_loss = nullptr;     // [n_env]: per-env loss in fp64
     // sparse adjoint: per-env tile grids, per-tile initial-mass flags and
     // their integral images (sparse_lds: bytes of the largest image; 0 when
     // an image would not fit in LDS, and the adjoint then stays dense)
@@ -78,12 +77,32 @@ hipError_t launch_relaxed_init(hipStream_t s, const uint8_t* init_states, int64_
                                double* B);
 hipError_t relaxed_forward(hipStream_t s, const RelaxedInputs& in, const sim_params& p, double* U,
                            double* B, int32_t T, int32_t ckpt_every, void* workspace, RelaxedState& R);
-hipError_t relaxed_loss(hipStream_t s, const RelaxedInputs& in, const uint8_t* init_states,
-                        const double* U_T, const uint8_t* target, float* loss, double* gU_T,
-                        double scale, RelaxedState& R);
+// The batch as the loss kernels see it: envs with their chunk0, the env of
+// every loss chunk, and the initial fire state (burnable cells).
+struct LossBatch {
+    const EnvDev* envs;
+    int32_t n_env;
+    const int32_t* chunk_env;
+    int32_t n_chunks;
+    const uint8_t* init_states;
+};
+
+// Scratch of the soft-IoU loss in doubles: per chunk 3 partial sums, per env
+// 3 sums and its loss.
+inline size_t loss_scratch_doubles(int32_t n_chunks, int32_t n_env)
+{
+    return 3 * (size_t)n_chunks + 4 * (size_t)n_env;
+}
+
+// Soft IoU per env, its fp64 objective scale * sum_e L_e (objective may be
+// nullptr) and the seed scale * dL_e/dU_T (gU_T may be nullptr).  Every sum
+// runs in a fixed order, so repeated calls give the same bits.
+hipError_t relaxed_loss(hipStream_t s, const LossBatch& lb, const double* U_T, const uint8_t* target,
+                        float* loss, double* gU_T, double scale, double* objective, double* scratch);
 hipError_t relaxed_loss_bce(hipStream_t s, const RelaxedInputs& in, const uint8_t* init_states,
                             const double* U_T, const uint8_t* target, int pool, double mse_weight,
-                            double eps, float* loss, double* gU_T, double scale, RelaxedState& R);
+                            double eps, float* loss, double* gU_T, double scale, double* objective,
+                            RelaxedState& R);
 hipError_t relaxed_backward(hipStream_t s, const RelaxedInputs& in, const sim_params& p,
                             const double* gU_T, const double* gB_T, int32_t T, int32_t ckpt_every,
                             void* workspace, double* grad, RelaxedState& R);

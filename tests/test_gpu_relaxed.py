@@ -48,11 +48,14 @@ def _gpu_loss_grad(batch, params, Y, T, k, form="product", loss_kind="iou", spar
     U, B = sim.relaxed_init()
     ws = sim.relaxed_workspace(T, k)
     sim.relaxed_fwd(p, U, B, T, k, ws, form)
-    loss, gU = sim.relaxed_loss_any(loss_kind, U, torch.from_numpy(Y).cuda(), scale=1.0 / batch.n_env,
-                                    **loss_kw)
+    loss, gU, obj = sim.relaxed_loss_any(loss_kind, U, torch.from_numpy(Y).cuda(), scale=1.0 / batch.n_env,
+                                         **loss_kw)
     grad = sim.relaxed_bwd(p, gU, None, T, k, ws, form)
     torch.cuda.synchronize()
-    return U.cpu().numpy(), B.cpu().numpy(), loss.cpu().numpy(), grad.cpu().numpy()
+    # the library's fp64 objective is the mean of its per-env losses
+    Lf = loss.cpu().numpy().astype(np.float64)
+    assert abs(obj.item() - Lf.mean()) <= 1e-6 * max(1.0, abs(Lf.mean()))
+    return U.cpu().numpy(), B.cpu().numpy(), loss.cpu().numpy(), grad.cpu().numpy(), obj.item()
 
 
 def _check_grad(g, g64):
@@ -88,12 +91,12 @@ def test_forward_loss_and_gradient_small(per_cell_wind):
     params = _params(1)
     T, k = 24, 5
     Y = _target(batch, params, T, 4)
-    U, B, loss, grad = _gpu_loss_grad(batch, params, Y, T, k)
+    U, B, loss, grad, obj = _gpu_loss_grad(batch, params, Y, T, k)
     L64, g64, finals = _oracle(batch, params, Y, T)
     for e in range(batch.n_env):
         assert np.max(np.abs(batch.env_view(U, e) - finals[e][0])) <= 1e-5
         assert np.max(np.abs(batch.env_view(B, e) - finals[e][1])) <= 1e-5
-    assert abs(float(loss.mean()) - L64) <= 1e-5
+    assert abs(obj - L64) <= 1e-5
     _check_grad(grad, g64)
 
 
@@ -111,12 +114,12 @@ def test_forms_and_losses(form, loss_kind, loss_kw):
     params = _params(5)
     T, k = 20, 6
     Y = _target(batch, params, T, 9)
-    U, B, loss, grad = _gpu_loss_grad(batch, params, Y, T, k, form, loss_kind, **loss_kw)
+    U, B, loss, grad, obj = _gpu_loss_grad(batch, params, Y, T, k, form, loss_kind, **loss_kw)
     L64, g64, finals = _oracle(batch, params, Y, T, form, loss_kind, **loss_kw)
     for e in range(batch.n_env):
         assert np.max(np.abs(batch.env_view(U, e) - finals[e][0])) <= 1e-5
         assert np.max(np.abs(batch.env_view(B, e) - finals[e][1])) <= 1e-5
-    assert abs(float(loss.astype(np.float64).mean()) - L64) <= 1e-5 * max(1.0, abs(L64))
+    assert abs(obj - L64) <= 1e-5 * max(1.0, abs(L64))
     _check_grad(grad, g64)
 
 
@@ -165,8 +168,8 @@ def test_checkpoint_interval_does_not_change_gradient(k):
     params = _params(2)
     T = 21
     Y = _target(batch, params, T, 6)
-    _, _, _, g_ref = _gpu_loss_grad(batch, params, Y, T, 21)
-    _, _, _, g = _gpu_loss_grad(batch, params, Y, T, k)
+    g_ref = _gpu_loss_grad(batch, params, Y, T, 21)[3]
+    g = _gpu_loss_grad(batch, params, Y, T, k)[3]
     assert np.allclose(g, g_ref, rtol=1e-6, atol=1e-9 * np.max(np.abs(g_ref)))
 
 
@@ -209,7 +212,7 @@ def test_full_size_relaxed128():
     theta_star = params
     params = params.replace(p_base=params.p_base * 1.2, alpha_w1=params.alpha_w1 * 1.2,
                             alpha_w2=params.alpha_w2 * 1.2, alpha_s=params.alpha_s * 1.2)
-    U, B, loss, _ = _gpu_loss_grad(batch, params, Y, T, k)
+    U, B, loss, _, _ = _gpu_loss_grad(batch, params, Y, T, k)
     sample = [0, 77, 200, 255]
     for e in sample:
         env = relaxed64.from_batch(batch, e, params.cell_size)
@@ -218,7 +221,7 @@ def test_full_size_relaxed128():
         assert np.max(np.abs(batch.env_view(U, e) - Us[-1])) <= 1e-5, e
     sub = batch.subset(range(16))
     Ysub = np.concatenate([batch.env_view(Y, e).ravel() for e in range(16)])
-    _, _, _, g = _gpu_loss_grad(sub, params, Ysub, T, k)
+    g = _gpu_loss_grad(sub, params, Ysub, T, k)[3]
     _, g64, _ = _oracle(sub, params, Ysub, T)
     _check_grad(g, g64)
     assert theta_star.p_base == 0.58
@@ -255,7 +258,7 @@ def test_relaxed2048_launch_config():
     M = T + 8
     params = params.replace(p_base=params.p_base * 1.2, alpha_s=params.alpha_s * 1.2)
     Y = _target(batch, params, 60, 2)
-    U, B, loss, g = _gpu_loss_grad(batch, params, Y, T, k)
+    U, B, loss, g, _ = _gpu_loss_grad(batch, params, Y, T, k)
     U2, B2 = U.reshape(H, W), B.reshape(H, W)
     rng = np.random.default_rng(17)
     centres = [(int(r[1]), int(r[2])) for r in batch.ignitions[:3]]
@@ -280,7 +283,7 @@ def test_relaxed2048_launch_config():
     assert np.all(U[~burnable.ravel()] == 0) and np.all(B[~burnable.ravel()] == 0)
     assert 0.0 < float(loss[0]) < 1.0
     assert np.all(np.isfinite(g))
-    _, _, _, g25 = _gpu_loss_grad(batch, params, Y, T, 25)
+    g25 = _gpu_loss_grad(batch, params, Y, T, 25)[3]
     assert np.allclose(g, g25, rtol=1e-6, atol=1e-9 * np.max(np.abs(g)))
     # directional derivative along the normalised gradient (fp64 state, h 1e-3)
     theta = _theta32(params)
@@ -305,11 +308,11 @@ def test_slope_angle_mode(form):
     params = _params(8, slope_mode=1)
     T, k = 18, 5
     Y = _target(batch, params, T, 11)
-    U, B, loss, grad = _gpu_loss_grad(batch, params, Y, T, k, form)
+    U, B, loss, grad, obj = _gpu_loss_grad(batch, params, Y, T, k, form)
     L64, g64, finals = _oracle(batch, params, Y, T, form, slope_mode=1)
     for e in range(batch.n_env):
         assert np.max(np.abs(batch.env_view(U, e) - finals[e][0])) <= 1e-5
-    assert abs(float(loss.astype(np.float64).mean()) - L64) <= 1e-5
+    assert abs(obj - L64) <= 1e-5
     _check_grad(grad, g64)
 
 
@@ -331,7 +334,7 @@ def test_wind_series(per_cell):
     U, B = sim.relaxed_init()
     ws = sim.relaxed_workspace(T, k)
     sim.relaxed_fwd(p, U, B, T, k, ws)
-    loss, gU = sim.relaxed_loss(U, torch.from_numpy(Y).cuda(), scale=1.0 / batch.n_env)
+    loss, gU, obj = sim.relaxed_loss(U, torch.from_numpy(Y).cuda(), scale=1.0 / batch.n_env)
     grad = sim.relaxed_bwd(p, gU, None, T, k, ws).cpu().numpy()
     torch.cuda.synchronize()
     kw = {"wind_cell_series" if per_cell else "wind_env_series": ser}
@@ -339,7 +342,7 @@ def test_wind_series(per_cell):
     Un = U.cpu().numpy()
     for e in range(batch.n_env):
         assert np.max(np.abs(batch.env_view(Un, e) - finals[e][0])) <= 1e-5
-    assert abs(float(loss.cpu().double().mean()) - L64) <= 1e-5
+    assert abs(obj.item() - L64) <= 1e-5
     _check_grad(grad, g64)
     ws2 = sim.relaxed_workspace(T + 1, k)
     U, B = sim.relaxed_init()
@@ -358,8 +361,8 @@ def test_sparse_adjoint_matches_dense(per_cell_wind, form, k):
     params = _params(4)
     T = 30
     Y = _target(batch, params, T, 9)
-    *_, g_dense = _gpu_loss_grad(batch, params, Y, T, k, form)
-    *_, g_sparse = _gpu_loss_grad(batch, params, Y, T, k, form, sparse=1)
+    g_dense = _gpu_loss_grad(batch, params, Y, T, k, form)[3]
+    g_sparse = _gpu_loss_grad(batch, params, Y, T, k, form, sparse=1)[3]
     scale = np.max(np.abs(g_dense))
     assert np.allclose(g_sparse, g_dense, rtol=1e-9, atol=1e-12 * scale)
     _, g64, _ = _oracle(batch, params, Y, T, form=form)
@@ -382,7 +385,7 @@ def test_backward_repeats_and_other_workspaces(k):
     ws, ws2 = sim.relaxed_workspace(T, k), sim.relaxed_workspace(T, k)
     U, B = sim.relaxed_init()
     sim.relaxed_fwd(p, U, B, T, k, ws)
-    _, gU = sim.relaxed_loss(U, Y, scale=1.0 / batch.n_env)
+    _, gU, _ = sim.relaxed_loss(U, Y, scale=1.0 / batch.n_env)
     g1 = sim.relaxed_bwd(p, gU, None, T, k, ws).cpu().numpy()
     g2 = sim.relaxed_bwd(p, gU, None, T, k, ws).cpu().numpy()
     U2, B2 = sim.relaxed_init()
