@@ -359,6 +359,21 @@ int sim_step_relaxed_fwd(sim_handle* h, const sim_params* p, double* U, double* 
 int sim_relaxed_loss(sim_handle* h, const double* U_T, const uint8_t* target, float* loss,
                      double* gU_T, double scale, double* objective, void* stream);
 
+/* sim_relaxed_loss for callers that cannot allocate device memory (code under
+ * stream capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and arguments, with the partial sums kept in a static device
+ * array of 4 MiB (2^19 doubles) per GPU instead of handle memory.  It calls
+ * no hipMalloc or hipFree, ever.
+ *  Limit: 3 doubles per 4096-cell chunk of every env plus 4 per env must fit
+ *  2^19 (e.g. 128 Mi cells in 8 envs, or 4096 envs of 512 x 512); a larger
+ *  batch gets SIM_EINVAL and a message naming sim_relaxed_loss.
+ * Every call on one GPU shares that GPU's array, which keeps the last call's
+ * contents (every slot is written before it is read): calls that overlap in
+ * time on one GPU, on any streams or handles, race and must be ordered by the
+ * caller.  Results equal sim_relaxed_loss's bit for bit. */
+int sim_relaxed_loss_noalloc(sim_handle* h, const double* U_T, const uint8_t* target, float* loss,
+                             double* gU_T, double scale, double* objective, void* stream);
+
 /* The paper's calibration loss (section 4): per env e, binary cross-entropy
  * of S = clip(1 - U_T on burnable cells, 0 elsewhere; eps, 1 - eps) against
  * the target scar Y, averaged over the env's cells, plus mse_weight times the

@@ -41,7 +41,7 @@ EXPORTED = ("sim_init", "sim_step", "sim_get_step", "sim_set_step", "sim_set_pla
             "sim_autotune", "sim_set_wind_series", "sim_step_history", "sim_set_drop",
             "sim_rl_reset", "sim_rl_step",
             "sim_relaxed_init", "sim_relaxed_workspace_bytes", "sim_step_relaxed_fwd",
-            "sim_relaxed_loss", "sim_relaxed_loss_bce", "sim_step_relaxed_bwd", "sim_debug_exp", "sim_debug_atan", "sim_debug_philox",
+            "sim_relaxed_loss", "sim_relaxed_loss_noalloc", "sim_relaxed_loss_bce", "sim_step_relaxed_bwd", "sim_debug_exp", "sim_debug_atan", "sim_debug_philox",
             "sim_last_error", "sim_destroy")
 
 
@@ -104,6 +104,7 @@ def lib() -> ctypes.CDLL:
         D = ctypes.c_double
         L.sim_step_relaxed_fwd.argtypes = [P, P, P, P, I32, I32, I32, P, SZ, P]
         L.sim_relaxed_loss.argtypes = [P, P, P, P, P, D, P, P]
+        L.sim_relaxed_loss_noalloc.argtypes = [P, P, P, P, P, D, P, P]
         L.sim_relaxed_loss_bce.argtypes = [P, P, P, I32, D, D, P, P, D, P, P]
         L.sim_step_relaxed_bwd.argtypes = [P, P, P, P, I32, I32, I32, P, SZ, P, P]
         L.sim_debug_exp.argtypes = [P, P, I64, P]
@@ -366,6 +367,13 @@ class FireSim:
         _check(lib().sim_relaxed_loss(self.handle, _ptr(U_T), _ptr(target), _ptr(loss), _ptr(g),
                                       float(scale), _ptr(obj), self._s()), self.handle)
         return loss, g, obj
+
+    def relaxed_loss_noalloc(self, U_T, target, loss, gU_T, objective, scale: float = 1.0):
+        """Soft-IoU loss into caller-given outputs (loss float32 [n_env], gU_T
+        float64 like U_T or None, objective float64 [1] or None), with the
+        library's static scratch: no device allocation on this path."""
+        _check(lib().sim_relaxed_loss_noalloc(self.handle, _ptr(U_T), _ptr(target), _ptr(loss), _ptr(gU_T),
+                                              float(scale), _ptr(objective), self._s()), self.handle)
 
     def relaxed_loss_bce(self, U_T, target, pool: int = 8, mse_weight: float = 1.0, eps: float = 1e-6,
                          scale: float = 1.0, want_grad: bool = True):

@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -23,6 +24,31 @@ using namespace firesim;
 namespace {
 
 thread_local std::string g_init_error;
+
+// Scratch of sim_relaxed_loss_noalloc: one copy per GPU, held until the
+// process ends.  Host code never passes `scratch` itself (on the host it only
+// names the variable); sim_init looks up its device address once per device
+// with hipGetSymbolAddress and the entry point uses that address.
+constexpr size_t kNoallocScratchDoubles = (size_t)1 << 19;  // 4 MiB
+static __device__ __align__(256) double scratch[kNoallocScratchDoubles];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on device `dev`, which must be current.
+hipError_t noalloc_scratch(int dev, double** out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_dev[dev] = static_cast<double*>(ptr);
+    }
+    *out = g_scratch_dev[dev];
+    return hipSuccess;
+}
 
 struct GraphCache {
     hipGraphExec_t exec = nullptr;
@@ -67,6 +93,7 @@ struct sim_handle {
     int32_t* d_chunk_env = nullptr;    // env of every loss chunk (kLossChunk cells)
     int32_t n_chunks = 0;
     double* d_loss_scratch = nullptr;  // soft-IoU loss partial sums (allocated on first use)
+    double* noalloc_scratch = nullptr; // this device's static scratch (sim_relaxed_loss_noalloc)
     float* d_g = nullptr;
     float* d_E = nullptr;
     uint8_t* d_cls = nullptr;
@@ -406,6 +433,13 @@ int sim_init(sim_handle** out, const sim_params* p, int32_t n_env, const sim_env
     if (hipGetDevice(&h->device) != hipSuccess) {
         h->err = "hipGetDevice failed (no GPU?)";
         return bail(SIM_EHIP);
+    }
+    {
+        const hipError_t e = noalloc_scratch(h->device, &h->noalloc_scratch);
+        if (e != hipSuccess) {
+            fail(h, SIM_EHIP, "static scratch lookup on device %d failed: %s", h->device, hipGetErrorString(e));
+            return bail(SIM_EHIP);
+        }
     }
     h->params = *p;
     h->n_env = n_env;
@@ -865,6 +899,24 @@ int sim_relaxed_loss(sim_handle* h, const double* U_T, const uint8_t* target, fl
     }
     hipError_t e = relaxed_loss((hipStream_t)stream, loss_batch(h), U_T, target, loss, gU_T, scale, objective,
                                 h->d_loss_scratch);
+    if (e != hipSuccess) return fail(h, SIM_EHIP, "relaxed loss failed: %s", hipGetErrorString(e));
+    return SIM_OK;
+}
+
+int sim_relaxed_loss_noalloc(sim_handle* h, const double* U_T, const uint8_t* target, float* loss,
+                             double* gU_T, double scale, double* objective, void* stream)
+{
+    CallScope scope("sim_relaxed_loss_noalloc", h);
+    if (!h) return fail(nullptr, SIM_EINVAL, "handle is NULL");
+    if (!U_T || !target || !loss) return fail(h, SIM_EINVAL, "U_T, target and loss are required");
+    const size_t need = loss_scratch_doubles(h->n_chunks, h->n_env);
+    if (need > kNoallocScratchDoubles)
+        return fail(h, SIM_EINVAL,
+                    "the batch needs %zu scratch doubles (3 per 4096-cell chunk, 4 per env), "
+                    "the static scratch holds %zu: use sim_relaxed_loss",
+                    need, kNoallocScratchDoubles);
+    hipError_t e = relaxed_loss((hipStream_t)stream, loss_batch(h), U_T, target, loss, gU_T, scale, objective,
+                                h->noalloc_scratch);
     if (e != hipSuccess) return fail(h, SIM_EHIP, "relaxed loss failed: %s", hipGetErrorString(e));
     return SIM_OK;
 }
