@@ -448,6 +448,7 @@ def bench_large(args, torch, fs, firegen):
 def relaxed_case(args, torch, fs, firegen, batch, params, T, k, label):
     sim = fs.FireSim.from_batch(batch, params, seed=0)
     sim.step(T)   # target scar: a stochastic run at the known parameters
+    sim.set_plan(sparse=0)  # the dense adjoint: every tile, every step
     Y = ((sim.states == firegen.BURNING) | (sim.states == firegen.BURNT)).to(torch.uint8)
     theta = fs.params_with_theta(sim.params, [params.p_base * 1.2, params.alpha_w1 * 1.2,
                                               params.alpha_w2 * 1.2, params.alpha_s * 1.2,

@@ -94,6 +94,7 @@ struct sim_handle {
     int32_t n_chunks = 0;
     double* d_loss_scratch = nullptr;  // soft-IoU loss partial sums (allocated on first use)
     double* noalloc_scratch = nullptr; // this device's static scratch (sim_relaxed_loss_noalloc)
+    int64_t n_adj_tiles = 0;           // tiles of the relaxed adjoint (they size its workspace)
     float* d_g = nullptr;
     float* d_E = nullptr;
     uint8_t* d_cls = nullptr;
@@ -474,6 +475,7 @@ int sim_init(sim_handle** out, const sim_params* p, int32_t n_env, const sim_env
         chunk_env.insert(chunk_env.end(), (size_t)nch, e);
     }
     h->n_chunks = (int32_t)chunk_env.size();
+    h->n_adj_tiles = relaxed_adj_tiles(h->envs);
     const size_t n = (size_t)n_cells;
     int rc;
 #define ALLOC(ptr, bytes)                                                                   \
@@ -821,7 +823,7 @@ int sim_relaxed_init(sim_handle* h, double* U, double* B, void* stream)
 size_t sim_relaxed_workspace_bytes(const sim_handle* h, int32_t T, int32_t ckpt_every)
 {
     if (!h || T < 0 || ckpt_every < 1) return 0;
-    return relaxed_workspace_bytes(h->n_cells, T, ckpt_every);
+    return relaxed_workspace_bytes(h->n_cells, h->n_adj_tiles, T, ckpt_every);
 }
 
 static RelaxedInputs relaxed_inputs(const sim_handle* h, int32_t form = 0)
@@ -870,9 +872,9 @@ int sim_step_relaxed_fwd(sim_handle* h, const sim_params* p, double* U, double* 
         return fail(h, SIM_EINVAL, "the wind series covers %lld steps, the relaxed run needs %d",
                     (long long)h->series_T, T);
     if (!U || !B || T < 0 || ckpt_every < 1) return fail(h, SIM_EINVAL, "bad U/B/T/ckpt_every");
-    if (T > 0 && (!workspace || workspace_bytes < relaxed_workspace_bytes(h->n_cells, T, ckpt_every)))
+    if (T > 0 && (!workspace || workspace_bytes < relaxed_workspace_bytes(h->n_cells, h->n_adj_tiles, T, ckpt_every)))
         return fail(h, SIM_EINVAL, "workspace too small (%zu < %zu)", workspace_bytes,
-                    relaxed_workspace_bytes(h->n_cells, T, ckpt_every));
+                    relaxed_workspace_bytes(h->n_cells, h->n_adj_tiles, T, ckpt_every));
     if ((rc = relaxed_prepare(h->relaxed, h->envs)) != 0)
         return fail(h, SIM_ENOMEM, "relaxed tile list allocation failed");
     hipError_t e = relaxed_forward((hipStream_t)stream, relaxed_inputs(h, form), *p, U, B, T, ckpt_every,
@@ -951,7 +953,7 @@ int sim_step_relaxed_bwd(sim_handle* h, const sim_params* p, const double* gU_T,
         return fail(h, SIM_EINVAL, "the wind series covers %lld steps, the relaxed run needs %d",
                     (long long)h->series_T, T);
     if (!gU_T || !grad || T < 0 || ckpt_every < 1) return fail(h, SIM_EINVAL, "bad gU_T/grad/T/ckpt_every");
-    if (T > 0 && (!workspace || workspace_bytes < relaxed_workspace_bytes(h->n_cells, T, ckpt_every)))
+    if (T > 0 && (!workspace || workspace_bytes < relaxed_workspace_bytes(h->n_cells, h->n_adj_tiles, T, ckpt_every)))
         return fail(h, SIM_EINVAL, "workspace too small");
     if ((rc = relaxed_prepare(h->relaxed, h->envs)) != 0)
         return fail(h, SIM_ENOMEM, "relaxed tile list allocation failed");

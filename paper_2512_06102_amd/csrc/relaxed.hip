@@ -18,16 +18,16 @@
 // gamma(v) = alpha_gamma g(v), g = (1 + veg[class]) (1 + den), to the 17
 // parameters.
 //
-// The forward works on 32 x 16 tiles, the adjoint on 32 x 20 tiles (256 lanes).
-// The adjoint's transpose stencil (Bbar(u) gathers from the targets around
-// u, and those need B two cells away) is done in one launch per step: the
-// tile stages B, g and E (and per-cell wind) with a two-cell halo in LDS;
-// phase 1 evaluates every target of the tile plus a one-cell ring and adds
-// c_k and the source-side fuel adjoint d_k into LDS slots of the sources in
-// the tile (LDS atomics: the summation order of a slot is not fixed);
-// phase 2 finishes the tile's own cells.  Parameter
-// gradients are summed per lane, reduced per workgroup, and added to one of
-// 64 fp64 stripes with atomics; a last kernel sums the stripes.
+// The forward works on 32 x 16 tiles with a one-cell halo in LDS.  The
+// adjoint's transpose stencil (Bbar(u) gathers the terms of the targets
+// around u, and those need B two cells away) runs in one launch per step on
+// 64 x 16 tiles, one wave each: lanes own columns, walk the rows, and pass
+// neighbouring values and terms by DPP lane shifts; terms that cross into
+// another tile go through an exchange record that the owning tile adds in the
+// next step.  Every sum runs in a fixed order (no atomics), so the gradient
+// is the same bits on every run.  Parameter gradients are summed per lane,
+// reduced per wave and added to the tile's own row of partial sums; a last
+// kernel sums the rows.
 //
 // Precision: the recurrence amplifies small burning mass exponentially (in
 // the mean-field model every region reachable from a burning cell
@@ -109,38 +109,14 @@ __device__ __forceinline__ float one_minus_exp_neg(float y)
 __device__ __forceinline__ float2 q_and_survival(float y)
 {
     const float qs = y * (1.0f - y * (0.5f - y * ((float)(1.0 / 6.0) - y * ((float)(1.0 / 24.0) - y * (float)(1.0 / 120.0)))));
-    const float el = hexp(-y);
-    return y < 0.0625f ? make_float2(qs, 1.0f - qs) : make_float2(1.0f - el, el);
-}
-
-// Sums of 17 values over the 64 lanes of a wave, written to out[0..16].
-// Recursive halving: at the exchange with lane ^ 32 the lower half keeps the
-// sums of values 0-7 and the upper half those of 8-15, and so on down to one
-// value per lane at lane ^ 4; lanes ^ 2 and ^ 1 finish it.  Lane l then
-// holds value 8 b5 + 4 b4 + 2 b3 + b2 (bits of l).  Value 16 is summed on
-// its own.  17 + 6 exchanges instead of 17 x 6.
-__device__ __forceinline__ void wave_sum17(const double (&a)[17], int lane, double* out)
-{
-    double b8[8], b4[4], b2[2];
-    const bool h5 = lane & 32, h4 = lane & 16, h3 = lane & 8, h2 = lane & 4;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) b8[j] = (h5 ? a[8 + j] : a[j]) + __shfl_xor(h5 ? a[j] : a[8 + j], 32);
-#pragma unroll
-    for (int j = 0; j < 4; ++j) b4[j] = (h4 ? b8[4 + j] : b8[j]) + __shfl_xor(h4 ? b8[j] : b8[4 + j], 16);
-#pragma unroll
-    for (int j = 0; j < 2; ++j) b2[j] = (h3 ? b4[2 + j] : b4[j]) + __shfl_xor(h3 ? b4[j] : b4[2 + j], 8);
-    double b1 = (h2 ? b2[1] : b2[0]) + __shfl_xor(h2 ? b2[0] : b2[1], 4);
-    b1 += __shfl_xor(b1, 2);
-    b1 += __shfl_xor(b1, 1);
-    double last = a[16];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) last += __shfl_xor(last, off);
-    if ((lane & 3) == 0) out[((lane >> 5) & 1) * 8 + ((lane >> 4) & 1) * 4 + ((lane >> 3) & 1) * 2 + ((lane >> 2) & 1)] = b1;
-    if (lane == 0) out[16] = last;
+    float el = hexp(-y);
+    float qt = qs;
+    // both are computed: a select, not a divergent branch
+    asm volatile("" : "+v"(el), "+v"(qt));
+    return y < 0.0625f ? make_float2(qt, 1.0f - qt) : make_float2(1.0f - el, el);
 }
 
 constexpr int TW = kRelaxTW, TH = kRelaxTH;  // forward tile
-constexpr int BW = kRelaxBW, BH = kRelaxBH;  // adjoint tile
 
 __global__ __launch_bounds__(256) void relaxed_init_kernel(const uint8_t* __restrict__ st, int64_t n,
                                                            double* __restrict__ U, double* __restrict__ B)
@@ -258,16 +234,163 @@ __global__ __launch_bounds__(256) void relaxed_fwd_kernel(
     }
 }
 
+// ---------------------------------------------------------------- adjoint
+// Adjoint tiles are AW = 64 columns (one wave, one column per lane) by AR
+// rows.  A wave walks its tile's rows top to bottom with the target row r in
+// the middle of a three-row window of sources (rows r-1, r, r+1).  Each lane
+// loads its own column; the left and right columns come from the
+// neighbouring lanes by wave-wide DPP shifts, and lanes 0 and 63 load the
+// column just outside the tile (the "ghost" column) themselves.
+//
+// Every target is evaluated once, by the tile that holds it.  Its terms c_k
+// (into Bbar of source u_k) and d_k (into the fuel adjoint of u_k) go to
+// running sums of the three source rows of the own column and, by the same
+// DPP shifts, of the two neighbouring columns, always added in the same
+// order.  Row r-1 is complete once target row r is done and is finished
+// then.  Sums that belong to cells of another tile (the rows just above and
+// below the tile and the ghost columns) are written to the tile's exchange
+// record; the tile that owns those cells adds them, in a fixed order, to
+// Bbar_{t+1} when it reads it in the next adjoint step.  Their fuel-adjoint
+// part is turned into veg gradient by the producing lane, which reads the
+// land-cover class and density of the foreign cell.  No atomics: Bbar, Ubar
+// and the gradient are the same bits on every run.
+constexpr int AW = kAdjW, AR = kAdjR;
+constexpr int kXTop = 0, kXBot = AW, kXLeft = 2 * AW, kXRight = 2 * AW + AR + 2;
+static_assert(kXRight + AR + 2 <= kXTile, "exchange record");
+
+// Wave-wide shifts (DPP wave_shr:1 / wave_shl:1): from_left gives lane i the
+// value of lane i-1, from_right that of lane i+1.  The lane with no source
+// (0, resp. 63) reads 0 in the *0 forms and keeps `edge` in the *_or forms.
+template <bool ZERO>
+__device__ __forceinline__ int shr1(int old, int v) { return __builtin_amdgcn_update_dpp(old, v, 0x138, 0xf, 0xf, ZERO); }
+template <bool ZERO>
+__device__ __forceinline__ int shl1(int old, int v) { return __builtin_amdgcn_update_dpp(old, v, 0x130, 0xf, 0xf, ZERO); }
+__device__ __forceinline__ float from_left_or(float edge, float v)
+{
+    return __int_as_float(shr1<false>(__float_as_int(edge), __float_as_int(v)));
+}
+__device__ __forceinline__ float from_right_or(float edge, float v)
+{
+    return __int_as_float(shl1<false>(__float_as_int(edge), __float_as_int(v)));
+}
+__device__ __forceinline__ int lo32(double v) { return (int)(unsigned)(unsigned long long)__double_as_longlong(v); }
+__device__ __forceinline__ int hi32(double v) { return (int)(__double_as_longlong(v) >> 32); }
+__device__ __forceinline__ double mk64(int lo, int hi)
+{
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+__device__ __forceinline__ double from_left_or(double edge, double v)
+{
+    return mk64(shr1<false>(lo32(edge), lo32(v)), shr1<false>(hi32(edge), hi32(v)));
+}
+__device__ __forceinline__ double from_right_or(double edge, double v)
+{
+    return mk64(shl1<false>(lo32(edge), lo32(v)), shl1<false>(hi32(edge), hi32(v)));
+}
+__device__ __forceinline__ double from_left0(double v) { return mk64(shr1<true>(0, lo32(v)), shr1<true>(0, hi32(v))); }
+__device__ __forceinline__ double from_right0(double v) { return mk64(shl1<true>(0, lo32(v)), shl1<true>(0, hi32(v))); }
+
+// Sum over the 64 lanes of a wave by xor butterflies (every lane receives the
+// same bits: each level adds the same two values, only their order differs).
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// A source cell as the adjoint reads it: B, fuel g, elevation E and (per-cell
+// wind only) V, Vx, Vy.  Off-grid cells are all zero.
+struct AdjCell {
+    double B;
+    float g, E, V, Vx, Vy;
+};
+
+// An env's arrays from its first cell (wave-uniform pointers).  Cells are
+// addressed by a 32-bit byte offset from them, so loads take a scalar base;
+// the relaxed path therefore accepts envs of fewer than 2^29 cells.
+struct AdjEnv {
+    const double *U, *B, *gU1, *gB1;
+    double *gU0, *gB0;
+    const float *g, *E, *V, *Vx, *Vy, *den;
+    const uint8_t* cls;
+};
+
+template <class T>
+__device__ __forceinline__ T ld_at(const T* base, uint32_t i)
+{
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + i * (uint32_t)sizeof(T));
+}
+template <class T>
+__device__ __forceinline__ void st_at(T* base, uint32_t i, T v)
+{
+    *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + i * (uint32_t)sizeof(T)) = v;
+}
+
+template <bool WC>
+__device__ __forceinline__ AdjCell load_adj_cell(const AdjEnv& P, uint32_t o, bool in)
+{
+    AdjCell c{0.0, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    if (in) {
+        c.B = ld_at(P.B, o);
+        c.g = ld_at(P.g, o);
+        c.E = ld_at(P.E, o);
+        if constexpr (WC) {
+            c.V = ld_at(P.V, o);
+            c.Vx = ld_at(P.Vx, o);
+            c.Vy = ld_at(P.Vy, o);
+        }
+    }
+    return c;
+}
+
+// The left (right) neighbour of each lane's cell: the neighbouring lane's
+// cell, or for lane 0 (63) its ghost cell, the column just outside the tile.
+template <bool WC>
+__device__ __forceinline__ AdjCell left_of(const AdjCell& x, const AdjCell& ghost)
+{
+    AdjCell r{from_left_or(ghost.B, x.B), from_left_or(ghost.g, x.g), from_left_or(ghost.E, x.E), 0.0f, 0.0f, 0.0f};
+    if constexpr (WC) {
+        r.V = from_left_or(ghost.V, x.V);
+        r.Vx = from_left_or(ghost.Vx, x.Vx);
+        r.Vy = from_left_or(ghost.Vy, x.Vy);
+    }
+    return r;
+}
+
+template <bool WC>
+__device__ __forceinline__ AdjCell right_of(const AdjCell& x, const AdjCell& ghost)
+{
+    AdjCell r{from_right_or(ghost.B, x.B), from_right_or(ghost.g, x.g), from_right_or(ghost.E, x.E), 0.0f, 0.0f, 0.0f};
+    if constexpr (WC) {
+        r.V = from_right_or(ghost.V, x.V);
+        r.Vx = from_right_or(ghost.Vx, x.Vx);
+        r.Vy = from_right_or(ghost.Vy, x.Vy);
+    }
+    return r;
+}
+
+// Running sums of one source cell: c into Bbar, d into the fuel adjoint.
+struct CD {
+    double c, d;
+};
+
+__device__ __forceinline__ CD cd_add(CD a, CD b) { return CD{a.c + b.c, a.d + b.d}; }
+// a + m b with m = 1 or 0 (the ghost sums of lanes 0 and 63)
+__device__ __forceinline__ CD cd_fma(CD b, double m, CD a) { return CD{fma(b.c, m, a.c), fma(b.d, m, a.d)}; }
+__device__ __forceinline__ CD cd_from_left(CD a) { return CD{from_left0(a.c), from_left0(a.d)}; }
+__device__ __forceinline__ CD cd_from_right(CD a) { return CD{from_right0(a.c), from_right0(a.d)}; }
+
 // Sparse adjoint.  The parameter gradient of step s sums over edges u -> v
 // with B_s(u) != 0, so u lies within s cells (Chebyshev) of S_0, the cells
-// with initial burning mass, and v within s + 1; it needs the adjoint of
-// step s + 1 there.  That in turn is exact wherever its inputs of step s + 2
-// are, one cell further out, and so on up to the seed at T.  So the adjoint
-// step s must be exact only within s + 1 cells of S_0, and a tile farther
-// from every cell of S_0 can be skipped: whatever its cells hold (finite:
-// the buffers start at zero) only ever meets B = 0 in the gradient sums.
-// Its cells' adjoint values are then not those of the dense sweep; only
-// the parameter gradient is returned.
+// with initial burning mass, and v within s + 1; it needs Bbar_{s+1} and
+// Ubar_{s+1} there.  Bbar_s(u) in turn needs the terms of the targets next
+// to u, whose inputs are one cell further out, and so on up to the seed at
+// T: the adjoint step s must be exact within s + 1 cells of S_0, and it
+// evaluates targets within s + 2.  A tile with no cell within s + 2 of S_0 is
+// skipped: whatever its cells and exchange record hold (finite: the buffers
+// start at zero) only ever meets B = 0 in the gradient sums, so only the
+// parameter gradient is returned.
 //
 // tile_mass_kernel flags the adjoint tiles holding initial burning mass;
 // tile_integral_kernel builds each env's integral image of the flags (one
@@ -279,8 +402,8 @@ __global__ __launch_bounds__(256) void tile_mass_kernel(const RelaxedTile* __res
     const RelaxedTile td = tiles[blockIdx.x];
     const EnvDev ed = envs[td.env];
     int any = 0;
-    for (int idx = threadIdx.x; idx < BW * BH; idx += 256) {
-        const int gi = td.r0 + idx / BW, gj = td.c0 + idx % BW;
+    for (int idx = threadIdx.x; idx < AW * AR; idx += 256) {
+        const int gi = td.r0 + idx / AW, gj = td.c0 + idx % AW;
         if (gi < ed.H && gj < ed.W && B[ed.offset + (int64_t)gi * ed.W + gj] != 0.0) any = 1;
     }
     any = __syncthreads_or(any);
@@ -312,15 +435,12 @@ __global__ __launch_bounds__(256) void tile_integral_kernel(const TileGrid* __re
     for (int i = threadIdx.x; i < n; i += 256) integ[tg.ioff + i] = sI[i];
 }
 
-// Does the adjoint step s need this tile: is a tile with initial mass within
-// a = floor(s / BH) + 1 tile rows and b = floor(s / BW) + 1 tile columns
-// (the tile bands whose nearest cells are at most s + 1 apart)?
-__device__ __forceinline__ bool tile_in_reach(const RelaxedTile& td, const TileGrid* grids, const int32_t* integ,
-                                              int32_t s)
+// Does the adjoint step s need tile (band i, strip j): is a tile with initial
+// mass within a = floor((s + 1) / AR) + 1 bands and b = floor((s + 1) / AW) + 1
+// strips (the tiles whose nearest cells are at most s + 2 apart)?
+__device__ __forceinline__ bool adj_tile_in_reach(int i, int j, const TileGrid& tg, const int32_t* integ, int32_t s)
 {
-    const TileGrid tg = grids[td.env];
-    const int i = td.r0 / BH, j = td.c0 / BW;
-    const int a = s / BH + 1, b = s / BW + 1;
+    const int a = (s + 1) / AR + 1, b = (s + 1) / AW + 1;
     const int i0 = max(i - a, 0), i1 = min(i + a, tg.rows - 1);
     const int j0 = max(j - b, 0), j1 = min(j + b, tg.cols - 1);
     const int32_t* I = integ + tg.ioff;
@@ -328,263 +448,387 @@ __device__ __forceinline__ bool tile_in_reach(const RelaxedTile& td, const TileG
     return I[(i1 + 1) * W1 + (j1 + 1)] - I[i0 * W1 + (j1 + 1)] - I[(i1 + 1) * W1 + j0] + I[i0 * W1 + j0] > 0;
 }
 
-// Atomic add to a double in LDS (ds_add_f64).
-__device__ __forceinline__ void lds_add(double* p, double v)
-{
-    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-
-// Wind exponent of direction k at a staged source cell (per env, or from the
-// staged per-cell wind).
-template <bool WC>
-__device__ __forceinline__ float staged_wind(int k, const float* ew, const float* sW, int s, int nx,
-                                             const RelaxedArgs& A)
-{
-    if constexpr (WC)
-        return wind_exponent(k, A.alpha_w1, A.alpha_w2, sW[s], sW[nx + s], sW[2 * nx + s]);
-    else
-        return ew[k];
-}
-
-// One adjoint step on a 32 x 20 tile: (U_t, B_t), (Ubar_{t+1}, Bbar_{t+1})
-// -> (Ubar_t, Bbar_t), and the step's contribution to the parameter gradient.
-// Both forms reduce to per-edge phibar_k and per-target gammabar:
+// One adjoint step: (U_t, B_t), (Ubar_{t+1}, Bbar_{t+1}) -> (Ubar_t, Bbar_t)
+// and the step's terms of the parameter gradient, added to the tile's row of
+// gsum.  Both forms reduce to per-edge phibar_k and per-target gammabar:
 //   FORM 0: ybar_k = Pbar B_k E_k exp(-y_k), phibar_k = ybar_k gamma,
 //           gammabar = sum_k ybar_k phi_k, c_k = Pbar q_k E_k;
 //   FORM 1: lambdabar = Pbar gamma (1 - P), phibar_k = lambdabar B_k,
-//           gammabar = Pbar lambda (1 - P), c_k = lambdabar phi_k.
-// The targets are the tile and its one-cell ring (34 x 22 = 748, three
-// passes of 256 lanes); each target adds c_k and the source-side fuel adjoint to
-// the LDS slots of its sources inside the tile, so per tile cell only two
-// doubles of LDS are needed and occupancy is set by registers.
-template <bool WC, int FORM>
-__global__ __launch_bounds__(256) void relaxed_bwd_kernel(
-    const RelaxedTile* __restrict__ tiles, const EnvDev* __restrict__ envs, const float* __restrict__ g,
+//           gammabar = Pbar lambda (1 - P), c_k = lambdabar phi_k;
+// d_k = phibar_k p_base exp(x_k) (dphi/dg of the source).  Four tiles (waves)
+// per workgroup, dealt to the XCDs in contiguous runs of the tile list.
+// SL: slope S = rise / run (0) or atan(rise / run) (1).
+template <bool WC, int FORM, int SL>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void relaxed_adj_kernel(
+    const RelaxedTile* __restrict__ tiles, int32_t n_tiles, int32_t groups_per_xcd,
+    const TileGrid* __restrict__ grids, const EnvDev* __restrict__ envs, const float* __restrict__ g,
     const float* __restrict__ E, const float* __restrict__ wind, const uint8_t* __restrict__ cls,
     const float* __restrict__ den, int64_t n_cells, RelaxedArgs A, const double* __restrict__ U,
     const double* __restrict__ B, const double* __restrict__ gU1, const double* __restrict__ gB1,
-    double* __restrict__ gU0, double* __restrict__ gB0, double* __restrict__ stripes,
-    const float* __restrict__ env_wind, const TileGrid* __restrict__ grids, const int32_t* __restrict__ integ,
-    int32_t step)
+    double* __restrict__ gU0, double* __restrict__ gB0, const double* __restrict__ Xin,
+    double* __restrict__ Xout, double* __restrict__ gsum, const float* __restrict__ env_wind,
+    const int32_t* __restrict__ integ, int32_t step)
 {
-    constexpr int XW = BW + 4, XH = BH + 4;  // staged: the targets' sources
-    constexpr int EW = BW + 2, EH = BH + 2;  // targets: the tile and its ring
-    constexpr int NX = XW * XH, NE = EW * EH, NT = BW * BH;
-    __shared__ double sB[NX];
-    __shared__ float sg[NX], sE[NX];
-    __shared__ float sW[WC ? 3 * NX : 1];      // per-cell wind V, Vx, Vy of the staged cells
-    __shared__ double sBbar[NT], sFbar[NT];  // per tile cell: sum_k c_k, fuel adjoint
-    __shared__ float ew[8];
-    __shared__ double sred[4][17];
-    const RelaxedTile td = tiles[blockIdx.x];
-    if (integ && !tile_in_reach(td, grids, integ, step)) return;  // sparse: the whole workgroup
+    __shared__ double sveg[4][11][64];  // per lane: fuel adjoint x (1 + den) by land-cover class
+    __shared__ double sxc[4][AR][2];    // incoming Bbar terms of the first and last column, per row
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform: tile values in SGPRs
+    const int b = blockIdx.x;
+    const int tix = (((b & 7) * groups_per_xcd + (b >> 3)) << 2) + wv;
+    if (tix >= n_tiles) return;
+    const RelaxedTile td = tiles[tix];
+    const TileGrid tg = grids[td.env];
+    const int tb = td.r0 / AR, ts = td.c0 / AW;  // band and strip of the tile
+    if (integ && !adj_tile_in_reach(tb, ts, tg, integ, step)) return;  // sparse: the whole wave
     const EnvDev ed = envs[td.env];
-    const int H = ed.H, W = ed.W, tid = threadIdx.x;
-    for (int idx = tid; idx < NX; idx += 256) {
-        const int gi = td.r0 - 2 + idx / XW, gj = td.c0 - 2 + idx % XW;
-        const bool in = gi >= 0 && gi < H && gj >= 0 && gj < W;
-        const int64_t v = ed.offset + (int64_t)gi * W + gj;
-        sB[idx] = in ? B[v] : 0.0;
-        sg[idx] = in ? g[v] : 0.0f;
-        sE[idx] = in ? E[v] : 0.0f;
-        if constexpr (WC) {
-            sW[idx] = in ? wind[v] : 0.0f;
-            sW[NX + idx] = in ? wind[n_cells + v] : 0.0f;
-            sW[2 * NX + idx] = in ? wind[2 * n_cells + v] : 0.0f;
-        }
+    const int H = ed.H, W = ed.W;
+    const int r0 = td.r0;
+    const int rows = min(AR, H - r0);
+    const int c = td.c0 + lane;
+    const bool act = c < W;
+    // ghost column: c0 - 1 for lane 0, c0 + 64 for lane 63 (if on the grid)
+    const int cg = lane == 0 ? td.c0 - 1 : td.c0 + AW;
+    const bool ghost = (lane == 0 && td.c0 > 0) || (lane == 63 && td.c0 + AW < W);
+    const double mL = lane == 0 ? 1.0 : 0.0, mR = lane == 63 ? 1.0 : 0.0;
+    const int64_t base = ed.offset;
+    AdjEnv P;
+    P.U = U + base;
+    P.B = B + base;
+    P.gU1 = gU1 + base;
+    P.gB1 = gB1 + base;
+    P.gU0 = gU0 + base;
+    P.gB0 = gB0 + base;
+    P.g = g + base;
+    P.E = E + base;
+    P.den = den + base;
+    P.cls = cls + base;
+    if constexpr (WC) {
+        P.V = wind + base;
+        P.Vx = wind + n_cells + base;
+        P.Vy = wind + 2 * n_cells + base;
+    } else {
+        P.V = P.Vx = P.Vy = nullptr;
     }
-    for (int idx = tid; idx < NT; idx += 256) sBbar[idx] = sFbar[idx] = 0.0;
-    const float3 wenv = env_wind_of(ed, env_wind, td.env);  // this step's per-env wind
-    if (!WC && tid < 8) ew[tid] = wind_exponent(tid, A.alpha_w1, A.alpha_w2, wenv.x, wenv.y, wenv.z);
-    __syncthreads();
+    // cell (r, col) of the env; wraps for the row above row 0, which is never read
+    auto at = [&](int r, int col) { return (uint32_t)(r * W + col); };
+    auto tile_of = [&](int bi, int sj) { return (int64_t)(tg.first + bi * tg.cols + sj) * kXTile; };
+    const int64_t xrec = (int64_t)tix * kXTile;
 
-    double acc[17];
 #pragma unroll
-    for (int j = 0; j < 17; ++j) acc[j] = 0.0;
-    double xbar_sin = 0.0;  // per-env wind: sum of xbar sin(k pi / 4)
-    const double p_base = A.p_base, a_gamma = A.alpha_gamma;
-
-    // phase 1: every target of the tile, then its ring (top and bottom rows,
-    // left and right columns), so that waves of ring targets, which only
-    // feed the few edges into the tile, mostly skip the edge work together
-    for (int idx = tid; idx < NE; idx += 256) {
-        int er, ec;
-        if (idx < NT) {
-            er = 1 + idx / BW;
-            ec = 1 + idx % BW;
-        } else {
-            const int r = idx - NT;
-            if (r < 2 * EW) {
-                er = r < EW ? 0 : EH - 1;
-                ec = r < EW ? r : r - EW;
-            } else {
-                er = 1 + (r - 2 * EW) % BH;
-                ec = r < 2 * EW + BH ? 0 : EW - 1;
-            }
+    for (int j = 0; j < 11; ++j) sveg[wv][j][lane] = 0.0;
+    // each lane touches only its own slots, in program order: no barrier
+    auto veg_add = [&](double fbar, uint32_t cl, float dn, bool on) {
+        if (on) {
+            double& slot = sveg[wv][cl][lane];
+            slot += fbar * (1.0 + (double)dn);
         }
-        const int gi = td.r0 - 1 + er, gj = td.c0 - 1 + ec;
-        if (gi < 0 || gi >= H || gj < 0 || gj >= W) continue;
-        const int64_t v = ed.offset + (int64_t)gi * W + gj;
-        const int a = er + 1, b = ec + 1;  // staged coordinates of v
-        const double Uv = U[v];
-        const double gU = gU1[v], gB = gB1[v];
+    };
+
+    // this step's per-env wind; the exponent of direction k is
+    // (alpha_w1 - alpha_w2) V + cos_k alpha_w2 Vx + sin_k alpha_w2 Vy
+    const float3 wenv = env_wind_of(ed, env_wind, td.env);
+    const float wA0 = (A.alpha_w1 - A.alpha_w2) * wenv.x, wA1 = A.alpha_w2 * wenv.y, wA2 = A.alpha_w2 * wenv.z;
+    const float gp = A.alpha_gamma * A.p_base;
+
+    // Bbar terms that neighbouring tiles added to this tile's cells in the
+    // previous step: for the first and last row one per lane (xt, xb, corners
+    // included), for the first and last column one per row (lanes 0 and 63,
+    // fetched by lanes 0..15 and 32..47 into LDS)
+    double xt = 0.0, xb = 0.0;
+    if (Xin) {
+        const bool up = tb > 0, dn = tb + 1 < tg.rows;
+        if (act && up) xt = Xin[tile_of(tb - 1, ts) + kXBot + lane];
+        if (act && dn) xb = Xin[tile_of(tb + 1, ts) + kXTop + lane];
+        if (lane == 0 && ts > 0) {
+            if (up) xt += Xin[tile_of(tb - 1, ts - 1) + kXRight + AR + 1];
+            if (dn) xb += Xin[tile_of(tb + 1, ts - 1) + kXRight];
+        }
+        if (lane == 63 && ts + 1 < tg.cols) {
+            if (up) xt += Xin[tile_of(tb - 1, ts + 1) + kXLeft + AR + 1];
+            if (dn) xb += Xin[tile_of(tb + 1, ts + 1) + kXLeft];
+        }
+        const int side = lane >> 5, ii = lane & 31;
+        double x = 0.0;
+        if (ii < rows) {
+            if (side == 0 && ts > 0) x = Xin[tile_of(tb, ts - 1) + kXRight + ii + 1];
+            if (side == 1 && ts + 1 < tg.cols) x = Xin[tile_of(tb, ts + 1) + kXLeft + ii + 1];
+        }
+        if (ii < AR) sxc[wv][ii][side] = x;
+        // the wave reads what its own lanes wrote: order the LDS accesses
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+
+    // the window: own column (X) and ghost column (G, lanes 0 and 63) of
+    // source rows r - 1 (a), r (m), r + 1 (b)
+    AdjCell X0 = load_adj_cell<WC>(P, at(r0 - 1, c), act && r0 > 0);
+    AdjCell X1 = load_adj_cell<WC>(P, at(r0, c), act);
+    AdjCell X2 = load_adj_cell<WC>(P, at(r0 + 1, c), act && r0 + 1 < H);
+    AdjCell G0 = load_adj_cell<WC>(P, at(r0 - 1, cg), ghost && r0 > 0);
+    AdjCell G1 = load_adj_cell<WC>(P, at(r0, cg), ghost);
+    AdjCell G2 = load_adj_cell<WC>(P, at(r0 + 1, cg), ghost && r0 + 1 < H);
+
+    // running sums (c, d) of the own column and the ghost column (lanes 0 and
+    // 63) for source rows r - 1 (a), r (m), r + 1 (b): slots below
+    double gB_prev = 0.0;
+    // sums of t0 = phibar dphi/dp_base and of t0 S; per-cell wind: of t0 V
+    // and t0 ((cos Vx + sin Vy) - V) of the source (acc_w1, acc_w2); per-env
+    // wind: of t0 cos_k and t0 sin_k
+    double acc_pb = 0.0, acc_w1 = 0.0, acc_w2 = 0.0, acc_s = 0.0, acc_gw = 0.0, acc_pc = 0.0;
+    const double p_c = A.p_continue;
+
+    // loaded one row ahead: the target's U, Ubar, Bbar, and the class and
+    // density of the source row finished next (own and ghost column)
+    double nU = 0.0, ngU = 0.0, ngB = 0.0;
+    if (act) {
+        nU = ld_at(P.U, at(r0, c));
+        ngU = ld_at(P.gU1, at(r0, c));
+        ngB = ld_at(P.gB1, at(r0, c));
+    }
+    uint32_t fcl = 0, gcl = 0;
+    float fdn = 0.0f, gdn = 0.0f;
+    if (act && r0 > 0) {
+        fcl = ld_at(P.cls, at(r0 - 1, c));
+        fdn = ld_at(P.den, at(r0 - 1, c));
+    }
+    if (ghost && r0 > 0) {
+        gcl = ld_at(P.cls, at(r0 - 1, cg));
+        gdn = ld_at(P.den, at(r0 - 1, cg));
+    }
+
+    CD acc_a{0.0, 0.0}, acc_m{0.0, 0.0}, acc_b{0.0, 0.0};
+    CD gh_a{0.0, 0.0}, gh_m{0.0, 0.0}, gh_b{0.0, 0.0};
+    AdjCell Xa = X0, Xm = X1, Xb = X2, Ga = G0, Gm = G1, Gb = G2;
+#pragma unroll 1
+    for (int i = 0; i < rows; ++i) {
+        const int r = r0 + i;
+        const uint32_t v = at(r, c);
+        // the target's adjoint inputs, and what other tiles added to Bbar_{t+1}
+        // of this cell in the previous step
+        const double Uv = nU, gU = ngU;
+        double gB = ngB;
+        if (act && Xin)
+            gB += ((i == 0 ? xt : 0.0) + (i == rows - 1 ? xb : 0.0)) +
+                  (lane == 0 ? sxc[wv][i][0] : (lane == 63 ? sxc[wv][i][1] : 0.0));
+        const uint32_t cl_a = fcl, gcl_a = gcl;  // row r - 1
+        const float dn_a = fdn, gdn_a = gdn;
+        if (act && i + 1 < rows) {
+            nU = ld_at(P.U, v + W);
+            ngU = ld_at(P.gU1, v + W);
+            ngB = ld_at(P.gB1, v + W);
+        }
+        if (act) {
+            fcl = ld_at(P.cls, v);
+            fdn = ld_at(P.den, v);
+        }
+        if (ghost) {
+            gcl = ld_at(P.cls, at(r, cg));
+            gdn = ld_at(P.den, at(r, cg));
+        }
+        // next window row (r + 2)
+        const bool more = i + 1 < rows && r + 2 < H;
+        const AdjCell Xn = load_adj_cell<WC>(P, at(r + 2, c), act && more);
+        const AdjCell Gn = load_adj_cell<WC>(P, at(r + 2, cg), ghost && more);
+
+        // ---- the target v = (r, c); its source in direction k is u_k = v - D_k
+        const AdjCell La = left_of<WC>(Xa, Ga), Lm = left_of<WC>(Xm, Gm), Lb = left_of<WC>(Xb, Gb);
+        const AdjCell Ra = right_of<WC>(Xa, Ga), Rm = right_of<WC>(Xm, Gm), Rb = right_of<WC>(Xb, Gb);
+        const double sB[8] = {Lm.B, Lb.B, Xb.B, Rb.B, Rm.B, Ra.B, Xa.B, La.B};
+        const float sg[8] = {Lm.g, Lb.g, Xb.g, Rb.g, Rm.g, Ra.g, Xa.g, La.g};
+        const float sE[8] = {Lm.E, Lb.E, Xb.E, Rb.E, Rm.E, Ra.E, Xa.E, La.E};
+        const float sV[8] = {Lm.V, Lb.V, Xb.V, Rb.V, Rm.V, Ra.V, Xa.V, La.V};
+        const float sVx[8] = {Lm.Vx, Lb.Vx, Xb.Vx, Rb.Vx, Rm.Vx, Ra.Vx, Xa.Vx, La.Vx};
+        const float sVy[8] = {Lm.Vy, Lb.Vy, Xb.Vy, Rb.Vy, Rm.Vy, Ra.Vy, Xa.Vy, La.Vy};
         const double nbar = gB - gU;
         const double Pbar = nbar * Uv;
-        const float gv = sg[a * XW + b], Ev = sE[a * XW + b];
-        const float gam = A.alpha_gamma * gv;
+        const float gv = Xm.g, Ev = Xm.E;
+        const float gam = A.alpha_gamma * gv, gpe = gp * gv;  // gamma(v), gamma(v) p_base
+        const double gam64 = gam;
+        // per-cell wind: the wind term (cos Vx + sin Vy) - V of direction k at the source
+        auto wterm = [&](int k) -> float { return (kCos[k] * sVx[k] + kSin[k] * sVy[k]) - sV[k]; };
+        auto slope_k = [&](int k) {
+            const float rr = (Ev - sE[k]) * ((k & 1) ? A.inv_diag : A.inv_orth);
+            return SL ? atanf(rr) : rr;
+        };
         float q[8], em[8], ex[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-            const int s = (a - kDRow[k]) * XW + (b - kDCol[k]);
-            // Off-grid sources are staged with zero fuel and zero B, so their
-            // q, c and phibar vanish without a bounds check; the exponent is
-            // capped below fp32 overflow so that their elevation term cannot
-            // turn 0 x e^x into 0 x inf.
-            const float x = staged_wind<WC>(k, ew, sW, s, NX, A) +
-                            A.alpha_s * slope_of((Ev - sE[s]) * ((k & 1) ? A.inv_diag : A.inv_orth), A);
+            // the exponent sums onto the slope term first, so that the
+            // per-env wind constants are not kept per direction
+            float x = A.alpha_s * slope_k(k);
+            if constexpr (WC) {
+                x = x + (A.alpha_w1 * sV[k] + A.alpha_w2 * wterm(k));
+            } else {
+                x = x + wA0;
+                if (kCos[k] != 0.0f) x = x + kCos[k] * wA1;
+                if (kSin[k] != 0.0f) x = x + kSin[k] * wA2;
+            }
+            // off-grid sources have zero fuel and zero B, so their terms
+            // vanish; the exponent is capped so that 0 x e^x stays 0
             ex[k] = hexp(fminf(x, 88.0f));
             if constexpr (FORM == 0) {
-                const float2 qe = q_and_survival(gam * (A.p_base * sg[s] * ex[k]));
+                const float2 qe = q_and_survival(gam * (A.p_base * (sg[k] * ex[k])));
                 q[k] = qe.x;
                 em[k] = qe.y;
             }
         }
-        // The later loops read B, g (and E) of the sources from LDS again
-        // instead of keeping them in registers across the loops.
-        asm volatile("" ::: "memory");
-        // FORM 0: exclusive products from stored prefixes and a running suffix
-        double pre[8];
-        double P, gam_bar = 0.0, lbar = 0.0;
+        // the terms of edge k from ybar_k = phibar_k / gamma: the gradient
+        // sums, then c_k and d_k into the running sums of source u_k (own
+        // column now, neighbouring lanes by DPP; lane 0 also keeps its k = 7,
+        // 0, 1 terms for the ghost column on its left, lane 63 its k = 5, 4, 3
+        // terms for the one on its right)
+        double gam_w = 0.0;  // sum_k ybar_k dphi_k/dp_base (gammabar / p_base)
+        auto emit = [&](int k, double cterm, double ybar) {
+            const double yw = ybar * (double)(sg[k] * ex[k]);
+            gam_w += yw;
+            const double t0 = yw * gam64;  // phibar dphi/dp_base
+            acc_pb += t0;
+            acc_s += t0 * (double)slope_k(k);
+            if constexpr (WC) {
+                acc_w1 += t0 * (double)sV[k];
+                acc_w2 += t0 * (double)wterm(k);
+            } else {  // the env's wind is applied at the end
+                if (kCos[k] != 0.0f) acc_w1 += t0 * (double)kCos[k];
+                if (kSin[k] != 0.0f) acc_w2 += t0 * (double)kSin[k];
+            }
+            const CD o{cterm, ybar * (double)(gpe * ex[k])};  // d = phibar p_base e^x
+            switch (k) {
+            case 0: acc_m = cd_add(acc_m, cd_from_right(o)); gh_m = cd_fma(o, mL, gh_m); break;
+            case 1: acc_b = cd_add(acc_b, cd_from_right(o)); gh_b = cd_fma(o, mL, gh_b); break;
+            case 2: acc_b = cd_add(acc_b, o); break;
+            case 3: acc_b = cd_add(acc_b, cd_from_left(o)); gh_b = cd_fma(o, mR, gh_b); break;
+            case 4: acc_m = cd_add(acc_m, cd_from_left(o)); gh_m = cd_fma(o, mR, gh_m); break;
+            case 5: acc_a = cd_add(acc_a, cd_from_left(o)); gh_a = cd_fma(o, mR, gh_a); break;
+            case 6: acc_a = cd_add(acc_a, o); break;
+            default: acc_a = cd_add(acc_a, cd_from_right(o)); gh_a = cd_fma(o, mL, gh_a); break;
+            }
+        };
+        double Pv;
         if constexpr (FORM == 0) {
-            double run = 1.0;
+            double pre[8], run = 1.0;
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
                 pre[k] = run;
-                run = run * (1.0 - (double)q[k] * sB[(a - kDRow[k]) * XW + (b - kDCol[k])]);
+                run = run * (1.0 - (double)q[k] * sB[k]);
             }
-            P = 1.0 - run;
+            Pv = 1.0 - run;
+            double suf = 1.0;
+#pragma unroll
+            for (int k = 7; k >= 0; --k) {
+                const double excl = pre[k] * suf;  // prod over j != k, no division
+                suf = suf * (1.0 - (double)q[k] * sB[k]);
+                const double pe = Pbar * excl;
+                emit(k, pe * (double)q[k], (pe * sB[k]) * (double)em[k]);  // ybar = qbar dq/dy
+            }
         } else {
             double lam = 0.0;
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const int s = (a - kDRow[k]) * XW + (b - kDCol[k]);
-                lam = lam + (double)(A.p_base * sg[s] * ex[k]) * sB[s];
-            }
+            for (int k = 0; k < 8; ++k) lam = lam + (double)(A.p_base * (sg[k] * ex[k])) * sB[k];
             const double surv = exp(-(double)gam * lam);
-            P = -expm1(-(double)gam * lam);
-            lbar = Pbar * (double)gam * surv;
-            gam_bar = Pbar * lam * surv;
-        }
-        const bool interior = idx < NT;
-        double suf = 1.0;
-        asm volatile("" ::: "memory");
+            Pv = -expm1(-(double)gam * lam);
+            const double lbar = Pbar * gam64 * surv;  // phibar_k = lbar B_k, ybar_k = phibar_k / gamma
+            const double ls = Pbar * surv;
 #pragma unroll
-        for (int k = 7; k >= 0; --k) {
-            const int s = (a - kDRow[k]) * XW + (b - kDCol[k]);
-            const double Bu = sB[s];
-            // the source u = v - D_k in tile coordinates
-            const int tr = er - 1 - kDRow[k], tc = ec - 1 - kDCol[k];
-            const bool to_tile = tr >= 0 && tr < BH && tc >= 0 && tc < BW;
-            double excl = 0.0;
-            if constexpr (FORM == 0) {
-                excl = pre[k] * suf;
-                suf = suf * (1.0 - (double)q[k] * Bu);
-            }
-            // a ring target only feeds the edges whose source is in the tile
-            if (!interior && !to_tile) continue;
-            const float ph = A.p_base * sg[s] * ex[k];
-            double c, phibar;
-            if constexpr (FORM == 0) {
-                const double pe = Pbar * excl;
-                const double ybar = pe * Bu * (double)em[k];  // qbar dq/dy
-                c = pe * (double)q[k];
-                phibar = ybar * (double)gam;
-                gam_bar += ybar * (double)ph;
-            } else {
-                c = lbar * (double)ph;
-                phibar = lbar * Bu;
-            }
-            const double d = phibar * (p_base * (double)ex[k]);  // -> gbar(source)
-            if (to_tile) {
-                const int t = tr * BW + tc;
-                lds_add(&sBbar[t], c);
-                lds_add(&sFbar[t], d);
-            }
-            if (interior) {
-                const double gu = sg[s];
-                const double xbar = d * gu;  // phibar dphi/dx
-                acc[0] += phibar * (gu * (double)ex[k]);
-                if constexpr (WC) {
-                    const float V = sW[s], Vx = sW[NX + s], Vy = sW[2 * NX + s];
-                    acc[1] += xbar * (double)V;
-                    acc[2] += xbar * (double)((kCos[k] * Vx + kSin[k] * Vy) - V);
-                } else {  // the env's wind is common to the tile: factored out below
-                    acc[1] += xbar;
-                    acc[2] += xbar * (double)kCos[k];
-                    xbar_sin += xbar * (double)kSin[k];
-                }
-                acc[3] += xbar * (double)slope_of((Ev - sE[s]) * ((k & 1) ? A.inv_diag : A.inv_orth), A);
-            }
+            for (int k = 7; k >= 0; --k) emit(k, lbar * (double)(A.p_base * (sg[k] * ex[k])), ls * sB[k]);
         }
-        if (interior) {
-            gU0[v] = gU + nbar * P;
-            acc[4] += gam_bar * (double)gv;
-            acc[5] += gB * sB[a * XW + b];
-            lds_add(&sFbar[(er - 1) * BW + (ec - 1)], gam_bar * a_gamma);
-        }
-    }
-    __syncthreads();
+        // gammabar = p_base gam_w; gamma(v) = alpha_gamma g(v)
+        const double gam_bar = (double)A.p_base * gam_w;
+        acc_gw += gam_w * (double)gv;
+        acc_pc += gB * Xm.B;
+        acc_m.d += gam_bar * (double)A.alpha_gamma;
+        if (act) st_at(P.gU0, v, gU + nbar * Pv);
 
-    // phase 2: the tile's own cells
-    for (int idx = tid; idx < NT; idx += 256) {
-        const int rr = idx / BW, cc = idx % BW;
-        const int gi = td.r0 + rr, gj = td.c0 + cc;
-        if (gi >= H || gj >= W) continue;
-        const int64_t u = ed.offset + (int64_t)gi * W + gj;
-        gB0[u] = (double)A.p_continue * gB1[u] + sBbar[idx];
-        const double gb = sFbar[idx] * (1.0 + (double)den[u]);
-        const int c = cls[u];
+        // ---- source row r - 1 is complete
+        if (i == 0) {  // the row above the tile: the band above owns it
+            if (r0 > 0) {
+                if (act) Xout[xrec + kXTop + lane] = acc_a.c;
+                veg_add(acc_a.d, cl_a, dn_a, act);
+                if (ghost) Xout[xrec + (lane == 0 ? kXLeft : kXRight)] = gh_a.c;
+                veg_add(gh_a.d, gcl_a, gdn_a, ghost);
+            }
+        } else {
+            if (act) st_at(P.gB0, v - W, p_c * gB_prev + acc_a.c);
+            veg_add(acc_a.d, cl_a, dn_a, act);
+            if (ghost) Xout[xrec + (lane == 0 ? kXLeft : kXRight) + i] = gh_a.c;
+            veg_add(gh_a.d, gcl_a, gdn_a, ghost);
+        }
+        acc_a = acc_m;
+        acc_m = acc_b;
+        acc_b = CD{0.0, 0.0};
+        gh_a = gh_m;
+        gh_m = gh_b;
+        gh_b = CD{0.0, 0.0};
+        gB_prev = gB;
+        Xa = Xm;
+        Xm = Xb;
+        Xb = Xn;
+        Ga = Gm;
+        Gm = Gb;
+        Gb = Gn;
+        }
+    // the tile's last row, and the row below it (owned by the band below)
+    const int rl = r0 + rows - 1;
+    if (act) st_at(P.gB0, at(rl, c), p_c * gB_prev + acc_a.c);
+    veg_add(acc_a.d, fcl, fdn, act);
+    if (ghost) Xout[xrec + (lane == 0 ? kXLeft : kXRight) + rows] = gh_a.c;
+    veg_add(gh_a.d, gcl, gdn, ghost);
+    if (rl + 1 < H) {
+        const bool on = act, gon = ghost;
+        const uint32_t cl = on ? (uint32_t)ld_at(P.cls, at(rl + 1, c)) : 0u;
+        const float dn = on ? ld_at(P.den, at(rl + 1, c)) : 0.0f;
+        const uint32_t gc = gon ? (uint32_t)ld_at(P.cls, at(rl + 1, cg)) : 0u;
+        const float gd = gon ? ld_at(P.den, at(rl + 1, cg)) : 0.0f;
+        if (act) Xout[xrec + kXBot + lane] = acc_m.c;
+        veg_add(acc_m.d, cl, dn, on);
+        if (ghost) Xout[xrec + (lane == 0 ? kXLeft : kXRight) + rows + 1] = gh_m.c;
+        veg_add(gh_m.d, gc, gd, gon);
+    }
+
+    // ---- the tile's 17 gradient terms (fixed order), added to its gsum row.
+    // dphi/dx = phi = p_base dphi/dp_base, so the wind and slope terms are
+    // p_base times sums of t0
+    const double p_base = A.p_base;
+    double acc[17];
+    acc[0] = acc_pb;
+    if constexpr (WC) {
+        acc[1] = p_base * acc_w1;
+        acc[2] = p_base * acc_w2;
+    } else {
+        acc[1] = p_base * ((double)wenv.x * acc_pb);
+        acc[2] = p_base * (((double)wenv.y * acc_w1 + (double)wenv.z * acc_w2) - (double)wenv.x * acc_pb);
+    }
+    acc[3] = p_base * acc_s;
+    acc[4] = p_base * acc_gw;  // sum gammabar g(v)
+    acc[5] = acc_pc;
 #pragma unroll
-        for (int j = 0; j < 11; ++j) acc[6 + j] += (c == j) ? gb : 0.0;
-    }
-
-    if constexpr (!WC) {
-        // acc[1] and acc[2] hold the sums of xbar and xbar cos(k pi / 4)
-        const double V = wenv.x, Vx = wenv.y, Vy = wenv.z, s0 = acc[1];
-        acc[1] = s0 * V;
-        acc[2] = (acc[2] * Vx + xbar_sin * Vy) - s0 * V;
-    }
-
-    // workgroup reduction of the 17 partial sums, then one fp64 stripe
-    wave_sum17(acc, tid & 63, sred[tid >> 6]);
-    __syncthreads();
-    if (tid < 17) {
-        const double total = sred[0][tid] + sred[1][tid] + sred[2][tid] + sred[3][tid];
-        if (total != 0.0) unsafeAtomicAdd(stripes + (blockIdx.x % kGradStripes) * 17 + tid, total);
+    for (int j = 0; j < 11; ++j) acc[6 + j] = sveg[wv][j][lane];
+#pragma unroll
+    for (int j = 0; j < 17; ++j) acc[j] = wave_sum(acc[j]);
+    if (lane == 0) {
+        double* row = gsum + (int64_t)tix * 17;
+#pragma unroll
+        for (int j = 0; j < 17; ++j) row[j] += acc[j];
     }
 }
 
-__global__ void stripes_sum_kernel(const double* __restrict__ stripes, double* __restrict__ grad)
+// grad[j] = sum over tiles of gsum[tile][j], one workgroup per j, in a fixed order.
+__global__ __launch_bounds__(256) void gsum_reduce_kernel(const double* __restrict__ gsum, int32_t n_tiles,
+                                                          double* __restrict__ grad)
 {
-    const int j = threadIdx.x;
-    if (j >= 17) return;
-    double s = 0.0;
-    for (int r = 0; r < kGradStripes; ++r) s += stripes[r * 17 + j];
-    grad[j] = s;
+    __shared__ double red[4];
+    const int j = blockIdx.x;
+    double a = 0.0;
+    for (int t = threadIdx.x; t < n_tiles; t += 256) a += gsum[(int64_t)t * 17 + j];
+    a = wave_sum(a);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) grad[j] = ((red[0] + red[1]) + red[2]) + red[3];
 }
-
 // ---------------------------------------------------------------- losses
 // Every reduction below runs in a fixed order (lane-strided partial sums,
 // xor butterflies, then the four wave sums in order), so the losses, the
 // objective and the seed are the same bits on every call.
-
-// Sum over the 64 lanes of a wave (every lane receives it).
-__device__ __forceinline__ double wave_sum(double v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    return v;
-}
 
 // Sum over a 256-lane workgroup, returned to every lane.
 __device__ __forceinline__ double block_sum256(double v, double* red)
@@ -803,12 +1047,12 @@ hipError_t fill_f64(hipStream_t s, double* p, int64_t n, double v)
 
 // Workspace layout (all offsets 256-byte aligned).
 struct WsLayout {
-    size_t g, ckpt, seg, fwd, adj, stripes, total;
+    size_t g, ckpt, seg, fwd, adj, xchg, gsum, total;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-WsLayout layout(int64_t n, int32_t T, int32_t k)
+WsLayout layout(int64_t n, int64_t n_adj_tiles, int32_t T, int32_t k)
 {
     const size_t d = 8 * (size_t)n;
     const size_t n_ckpt = T > 0 ? (size_t)((T + k - 1) / k) : 1;
@@ -824,8 +1068,10 @@ WsLayout layout(int64_t n, int32_t T, int32_t k)
     o = align256(o + 2 * d);
     L.adj = o;
     o = align256(o + 4 * d);
-    L.stripes = o;
-    o = align256(o + sizeof(double) * kGradStripes * 17);
+    L.xchg = o;  // two exchange records per adjoint tile (steps of either parity)
+    o = align256(o + sizeof(double) * 2 * (size_t)n_adj_tiles * kXTile);
+    L.gsum = o;  // 17 gradient partial sums per adjoint tile
+    o = align256(o + sizeof(double) * 17 * (size_t)n_adj_tiles);
     L.total = o;
     return L;
 }
@@ -868,16 +1114,27 @@ hipError_t fwd_step(hipStream_t s, const RelaxedInputs& in, const RelaxedArgs& A
 }
 
 template <bool WC, int FORM>
-void launch_bwd(hipStream_t s, const RelaxedInputs& in, const RelaxedState& R, const RelaxedArgs& A,
+void launch_adj(hipStream_t s, const RelaxedInputs& in, const RelaxedState& R, const RelaxedArgs& A,
                 const float* g, const double* U, const double* B, const double* gU1, const double* gB1,
-                double* gU0, double* gB0, double* stripes, const int32_t* integ, int32_t step)
+                double* gU0, double* gB0, const double* Xin, double* Xout, double* gsum, const int32_t* integ,
+                int32_t step)
 {
-    hipLaunchKernelGGL((relaxed_bwd_kernel<WC, FORM>), dim3(R.n_btiles), dim3(256), 0, s, R.d_btiles,
-                       in.envs, g, in.E, in.wind, in.cls, in.den, in.n_cells, A, U, B, gU1, gB1, gU0,
-                       gB0, stripes, in.env_wind, R.d_tgrid, integ, step);
+    const int32_t groups = (R.n_btiles + 3) / 4;
+    const int32_t per_xcd = (groups + 7) / 8;
+    auto kernel = A.slope_mode ? relaxed_adj_kernel<WC, FORM, 1> : relaxed_adj_kernel<WC, FORM, 0>;
+    hipLaunchKernelGGL(kernel, dim3(8 * per_xcd), dim3(256), 0, s, R.d_btiles, R.n_btiles, per_xcd, R.d_tgrid,
+                       in.envs, g, in.E, in.wind, in.cls, in.den, in.n_cells, A, U, B, gU1, gB1, gU0, gB0, Xin,
+                       Xout, gsum, in.env_wind, integ, step);
 }
 
 }  // namespace
+
+int64_t relaxed_adj_tiles(const std::vector<sim_env>& envs)
+{
+    int64_t n = 0;
+    for (const sim_env& v : envs) n += (int64_t)((v.H + AR - 1) / AR) * ((v.W + AW - 1) / AW);
+    return n;
+}
 
 int relaxed_prepare(RelaxedState& R, const std::vector<sim_env>& envs)
 {
@@ -888,9 +1145,9 @@ int relaxed_prepare(RelaxedState& R, const std::vector<sim_env>& envs)
     for (int32_t e = 0; e < (int32_t)envs.size(); ++e) {
         for (int r0 = 0; r0 < envs[e].H; r0 += TH)
             for (int c0 = 0; c0 < envs[e].W; c0 += TW) tiles.push_back(RelaxedTile{e, r0, c0, 0});
-        TileGrid tg{(int32_t)btiles.size(), (envs[e].H + BH - 1) / BH, (envs[e].W + BW - 1) / BW, (int32_t)ioff};
-        for (int r0 = 0; r0 < envs[e].H; r0 += BH)
-            for (int c0 = 0; c0 < envs[e].W; c0 += BW) btiles.push_back(RelaxedTile{e, r0, c0, 0});
+        TileGrid tg{(int32_t)btiles.size(), (envs[e].H + AR - 1) / AR, (envs[e].W + AW - 1) / AW, (int32_t)ioff};
+        for (int r0 = 0; r0 < envs[e].H; r0 += AR)
+            for (int c0 = 0; c0 < envs[e].W; c0 += AW) btiles.push_back(RelaxedTile{e, r0, c0, 0});
         const int64_t img = (int64_t)(tg.rows + 1) * (tg.cols + 1);
         ioff += img;
         max_img = std::max(max_img, img);
@@ -904,16 +1161,15 @@ int relaxed_prepare(RelaxedState& R, const std::vector<sim_env>& envs)
     if (hipMemcpy(R.d_btiles, btiles.data(), btiles.size() * sizeof(RelaxedTile),
                   hipMemcpyHostToDevice) != hipSuccess)
         return -1;
+    if (hipMalloc(&R.d_tgrid, grids.size() * sizeof(TileGrid)) != hipSuccess) return -1;
+    if (hipMemcpy(R.d_tgrid, grids.data(), grids.size() * sizeof(TileGrid), hipMemcpyHostToDevice) != hipSuccess)
+        return -1;
     R.n_tiles = (int32_t)tiles.size();
     R.n_btiles = (int32_t)btiles.size();
     R.n_env = (int32_t)envs.size();
     if (ioff < INT32_MAX && 4 * max_img <= 64 * 1024) {
-        if (hipMalloc(&R.d_tgrid, grids.size() * sizeof(TileGrid)) != hipSuccess ||
-            hipMalloc(&R.d_tmass, btiles.size() * sizeof(int32_t)) != hipSuccess ||
+        if (hipMalloc(&R.d_tmass, btiles.size() * sizeof(int32_t)) != hipSuccess ||
             hipMalloc(&R.d_tinteg, (size_t)ioff * sizeof(int32_t)) != hipSuccess)
-            return -1;
-        if (hipMemcpy(R.d_tgrid, grids.data(), grids.size() * sizeof(TileGrid), hipMemcpyHostToDevice) !=
-            hipSuccess)
             return -1;
         R.sparse_lds = (int32_t)(4 * max_img);
     }
@@ -961,9 +1217,9 @@ void relaxed_free(RelaxedState& R)
     R = RelaxedState{};
 }
 
-size_t relaxed_workspace_bytes(int64_t n_cells, int32_t T, int32_t ckpt_every)
+size_t relaxed_workspace_bytes(int64_t n_cells, int64_t n_adj_tiles, int32_t T, int32_t ckpt_every)
 {
-    return layout(n_cells, T, ckpt_every).total;
+    return layout(n_cells, n_adj_tiles, T, ckpt_every).total;
 }
 
 hipError_t launch_relaxed_init(hipStream_t s, const uint8_t* init_states, int64_t n, double* U, double* B)
@@ -983,7 +1239,7 @@ hipError_t relaxed_forward(hipStream_t s, const RelaxedInputs& in, const sim_par
     R.last_segment_ws = nullptr;
     if (T == 0) return hipSuccess;
     const int64_t n = in.n_cells;
-    const WsLayout L = layout(n, T, k);
+    const WsLayout L = layout(n, R.n_btiles, T, k);
     char* ws = static_cast<char*>(workspace);
     float* g = reinterpret_cast<float*>(ws + L.g);
     double* ckpt = reinterpret_cast<double*>(ws + L.ckpt);
@@ -1075,15 +1331,20 @@ hipError_t relaxed_backward(hipStream_t s, const RelaxedInputs& in, const sim_pa
                             void* workspace, double* grad, RelaxedState& R)
 {
     const int64_t n = in.n_cells;
-    const WsLayout L = layout(n, T, k);
+    const WsLayout L = layout(n, R.n_btiles, T, k);
     char* ws = static_cast<char*>(workspace);
     float* g = reinterpret_cast<float*>(ws + L.g);
     double* ckpt = reinterpret_cast<double*>(ws + L.ckpt);
     double* seg = reinterpret_cast<double*>(ws + L.seg);
     double* adj = reinterpret_cast<double*>(ws + L.adj);
-    double* stripes = reinterpret_cast<double*>(ws + L.stripes);
+    double* xchg = reinterpret_cast<double*>(ws + L.xchg);
+    double* gsum = reinterpret_cast<double*>(ws + L.gsum);
+    const int64_t xrecs = (int64_t)R.n_btiles * kXTile;
     const RelaxedArgs A = relaxed_args(p);
-    hipError_t e = fill_f64(s, stripes, (int64_t)kGradStripes * 17, 0.0);
+    hipError_t e = fill_f64(s, gsum, (int64_t)R.n_btiles * 17, 0.0);
+    // exchange records start at zero: a tile that the sparse adjoint skips
+    // leaves finite values for its neighbours to read
+    if (e == hipSuccess) e = fill_f64(s, xchg, 2 * xrecs, 0.0);
     if (e == hipSuccess) e = fuel(s, in, p, g);
     double* cu = adj;  // adjoint at t+1: (Ubar, Bbar)
     double* cb = adj + n;
@@ -1123,19 +1384,22 @@ hipError_t relaxed_backward(hipStream_t s, const RelaxedInputs& in, const sim_pa
             const int32_t j = t - t0;
             const double *Ut = state_u(j), *Bt = state_b(j);
             const RelaxedInputs it = at_step(in, t);
+            // step t writes the exchange record of parity t; step t - 1 adds it
+            const double* Xin = t == T - 1 ? nullptr : xchg + ((t + 1) & 1) * xrecs;
+            double* Xout = xchg + (t & 1) * xrecs;
             if (it.wind)
-                it.form ? launch_bwd<true, 1>(s, it, R, A, g, Ut, Bt, cu, cb, nu, nb, stripes, integ, t)
-                        : launch_bwd<true, 0>(s, it, R, A, g, Ut, Bt, cu, cb, nu, nb, stripes, integ, t);
+                it.form ? launch_adj<true, 1>(s, it, R, A, g, Ut, Bt, cu, cb, nu, nb, Xin, Xout, gsum, integ, t)
+                        : launch_adj<true, 0>(s, it, R, A, g, Ut, Bt, cu, cb, nu, nb, Xin, Xout, gsum, integ, t);
             else
-                it.form ? launch_bwd<false, 1>(s, it, R, A, g, Ut, Bt, cu, cb, nu, nb, stripes, integ, t)
-                        : launch_bwd<false, 0>(s, it, R, A, g, Ut, Bt, cu, cb, nu, nb, stripes, integ, t);
+                it.form ? launch_adj<false, 1>(s, it, R, A, g, Ut, Bt, cu, cb, nu, nb, Xin, Xout, gsum, integ, t)
+                        : launch_adj<false, 0>(s, it, R, A, g, Ut, Bt, cu, cb, nu, nb, Xin, Xout, gsum, integ, t);
             e = hipGetLastError();
             std::swap(cu, nu);
             std::swap(cb, nb);
         }
     }
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(stripes_sum_kernel, dim3(1), dim3(64), 0, s, stripes, grad);
+        hipLaunchKernelGGL(gsum_reduce_kernel, dim3(17), dim3(256), 0, s, gsum, R.n_btiles, grad);
         e = hipGetLastError();
     }
     return e;

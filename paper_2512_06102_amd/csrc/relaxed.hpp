@@ -11,18 +11,22 @@
 
 namespace firesim {
 
-// Tiles of the relaxed kernels: forward 32 x 16 cells, adjoint 32 x 20 cells.
+// Tiles of the relaxed kernels: forward 32 x 16 cells, adjoint 64 x 16 cells
+// (one wave, one column per lane).
 constexpr int kRelaxTW = 32, kRelaxTH = 16;
-constexpr int kRelaxBW = 32, kRelaxBH = 20;
-constexpr int kGradStripes = 64;  // fp64 partial-sum rows of the parameter gradient
+constexpr int kAdjW = 64, kAdjR = 32;
+// Exchange record of an adjoint tile (doubles): Bbar terms for the rows
+// just above and below the tile (64 each) and the columns just left and
+// right of it (kAdjR + 2 each, corners included).
+constexpr int kXTile = 200;
 
 struct RelaxedTile {
     int32_t env, r0, c0, pad;
 };
 
 // The adjoint tiles of one env form a rows x cols grid starting at tile
-// `first`; its (rows + 1) x (cols + 1) integral image of tiles holding
-// initial burning mass starts at `ioff` (sparse adjoint).
+// `first` (row-major); its (rows + 1) x (cols + 1) integral image of tiles
+// holding initial burning mass starts at `ioff` (sparse adjoint).
 struct TileGrid {
     int32_t first, rows, cols, ioff;
 };
@@ -40,9 +44,10 @@ struct RelaxedState {
     int32_t* d_env_blocks = nullptr;  // [n_env][2]: first block, number of blocks
     double* d_pool_vals = nullptr;    // [4][n_pool]: block means of S and Y, BCE sum, squared error
     double* d_bce_loss = nullptr;     // [n_env]: per-env loss in fp64
-    // sparse adjoint: per-env tile grids, per-tile initial-mass flags and
-    // their integral images (sparse_lds: bytes of the largest image; 0 when
-    // an image would not fit in LDS, and the adjoint then stays dense)
+    // per-env grids of the adjoint tiles; sparse adjoint: per-tile
+    // initial-mass flags and their integral images (sparse_lds: bytes of the
+    // largest image; 0 when an image would not fit in LDS, and the adjoint
+    // then stays dense)
     TileGrid* d_tgrid = nullptr;
     int32_t* d_tmass = nullptr;
     int32_t* d_tinteg = nullptr;
@@ -71,7 +76,9 @@ struct RelaxedInputs {
 int relaxed_prepare(RelaxedState& R, const std::vector<sim_env>& envs);
 int relaxed_prepare_pool(RelaxedState& R, const std::vector<sim_env>& envs, int pool);
 void relaxed_free(RelaxedState& R);
-size_t relaxed_workspace_bytes(int64_t n_cells, int32_t T, int32_t ckpt_every);
+// Number of adjoint tiles of a batch (they size the workspace).
+int64_t relaxed_adj_tiles(const std::vector<sim_env>& envs);
+size_t relaxed_workspace_bytes(int64_t n_cells, int64_t n_adj_tiles, int32_t T, int32_t ckpt_every);
 
 hipError_t launch_relaxed_init(hipStream_t s, const uint8_t* init_states, int64_t n, double* U,
                                double* B);

@@ -395,3 +395,33 @@ def test_backward_repeats_and_other_workspaces(k):
     scale = np.max(np.abs(g1))
     for g in (g2, g3):
         assert np.allclose(g, g1, rtol=1e-9, atol=1e-12 * scale)
+
+
+@pytest.mark.parametrize("per_cell_wind,form", [(False, "product"), (True, "product"), (True, "exp")])
+def test_gradient_across_adjoint_tiles_and_repeatable(per_cell_wind, form):
+    """Fires that cross many adjoint tiles (64 columns x 16 rows: the Bbar
+    terms of edges between tiles go through the exchange records, corners
+    included) against the fp64 adjoint; and the gradient is the same bits on
+    every run, on the same handle and on a fresh one."""
+    batch = firegen.landscape_batch(23, [(150, 200), (17, 130), (64, 129)], per_cell_wind=per_cell_wind,
+                                    elev_max=60.0)
+    # ignitions on tile corners and edges
+    batch.ignitions = np.array([(0, 15, 63), (0, 16, 64), (0, 47, 128), (0, 120, 190), (1, 8, 64),
+                                (2, 31, 127), (2, 48, 0)], np.int32)
+    params = _params(8, p_base=0.9)
+    T, k = 40, 7
+    Y = _target(batch, params, T, 5)
+    _, _, _, g1, _ = _gpu_loss_grad(batch, params, Y, T, k, form)
+    L64, g64, _ = _oracle(batch, params, Y, T, form)
+    _check_grad(g1, g64)
+    sim = fs.FireSim.from_batch(batch, params, seed=0)
+    sim.set_plan(sparse=0)
+    p = fs.make_params(params)
+    p.unburnable_mask = batch.unburnable_mask
+    U, B = sim.relaxed_init()
+    ws = sim.relaxed_workspace(T, k)
+    sim.relaxed_fwd(p, U, B, T, k, ws, form)
+    _, gU, _ = sim.relaxed_loss(U, torch.from_numpy(Y).cuda(), scale=1.0 / batch.n_env)
+    grads = [sim.relaxed_bwd(p, gU, None, T, k, ws, form).cpu().numpy() for _ in range(3)]
+    for g in grads:
+        assert np.array_equal(g, g1)
