@@ -830,8 +830,8 @@ static RelaxedInputs relaxed_inputs(const sim_handle* h, int32_t form = 0)
 {
     RelaxedInputs in;
     in.form = form;
-    in.tiles = h->relaxed.d_tiles;
-    in.n_tiles = h->relaxed.n_tiles;
+    in.tiles = h->relaxed.d_btiles;
+    in.n_tiles = h->relaxed.n_btiles;
     in.envs = h->d_envs;
     in.n_env = h->n_env;
     in.cls = h->d_cls;

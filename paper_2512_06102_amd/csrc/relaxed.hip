@@ -66,12 +66,6 @@ __device__ __forceinline__ float3 env_wind_of(const EnvDev& ed, const float* env
     return make_float3(ed.V, ed.Vx, ed.Vy);
 }
 
-// S of Eq. 2 from the rise over the run (or its angle).
-__device__ __forceinline__ float slope_of(float rise_over_run, const RelaxedArgs& A)
-{
-    return A.slope_mode ? atanf(rise_over_run) : rise_over_run;
-}
-
 RelaxedArgs relaxed_args(const sim_params& p)
 {
     RelaxedArgs a;
@@ -116,7 +110,6 @@ __device__ __forceinline__ float2 q_and_survival(float y)
     return y < 0.0625f ? make_float2(qt, 1.0f - qt) : make_float2(1.0f - el, el);
 }
 
-constexpr int TW = kRelaxTW, TH = kRelaxTH;  // forward tile
 
 __global__ __launch_bounds__(256) void relaxed_init_kernel(const uint8_t* __restrict__ st, int64_t n,
                                                            double* __restrict__ U, double* __restrict__ B)
@@ -171,69 +164,6 @@ __device__ __forceinline__ float source_wind(int k, const float* ew, const float
         return ew[k];
 }
 
-// One relaxed forward step on a 32 x 16 tile.  FORM 0: p_ignite = 1 -
-// prod_k (1 - q_k B_k); FORM 1: p_ignite = 1 - exp(-gamma sum_k B_k phi_k).
-template <bool WC, int FORM>
-__global__ __launch_bounds__(256) void relaxed_fwd_kernel(
-    const RelaxedTile* __restrict__ tiles, const EnvDev* __restrict__ envs, const float* __restrict__ g,
-    const float* __restrict__ E, const float* __restrict__ wind, int64_t n_cells, RelaxedArgs A,
-    const double* __restrict__ U, const double* __restrict__ B, double* __restrict__ Uo,
-    double* __restrict__ Bo, const float* __restrict__ env_wind)
-{
-    constexpr int EW = TW + 2, EH = TH + 2;
-    __shared__ double sB[EH * EW];
-    __shared__ float sg[EH * EW], sE[EH * EW];
-    __shared__ float ew[8];
-    const RelaxedTile td = tiles[blockIdx.x];
-    const EnvDev ed = envs[td.env];
-    const int H = ed.H, W = ed.W, tid = threadIdx.x;
-    for (int idx = tid; idx < EH * EW; idx += 256) {
-        const int gi = td.r0 - 1 + idx / EW, gj = td.c0 - 1 + idx % EW;
-        const bool in = gi >= 0 && gi < H && gj >= 0 && gj < W;
-        const int64_t v = ed.offset + (int64_t)gi * W + gj;
-        sB[idx] = in ? B[v] : 0.0;
-        sg[idx] = in ? g[v] : 0.0f;
-        sE[idx] = in ? E[v] : 0.0f;
-    }
-    if (!WC && tid < 8) {
-        const float3 w = env_wind_of(ed, env_wind, td.env);
-        ew[tid] = wind_exponent(tid, A.alpha_w1, A.alpha_w2, w.x, w.y, w.z);
-    }
-    __syncthreads();
-    for (int idx = tid; idx < TW * TH; idx += 256) {
-        const int rr = idx / TW, cc = idx % TW;
-        const int gi = td.r0 + rr, gj = td.c0 + cc;
-        if (gi >= H || gj >= W) continue;
-        const int64_t v = ed.offset + (int64_t)gi * W + gj;
-        const int a = rr + 1, b = cc + 1;
-        const double Uv = U[v], Bv = sB[a * EW + b];
-        double P = 0.0;
-        if (Uv != 0.0) {
-            const float gam = A.alpha_gamma * sg[a * EW + b];
-            const float Ev = sE[a * EW + b];
-            double prod = 1.0, lam = 0.0;
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const int s = (a - kDRow[k]) * EW + (b - kDCol[k]);
-                const double Bu = sB[s];
-                if (Bu == 0.0) continue;  // off-grid sources read 0
-                const int64_t u = v - (int64_t)kDRow[k] * W - kDCol[k];
-                const float x = source_wind<WC>(k, ew, wind, n_cells, u, A) +
-                                A.alpha_s * slope_of((Ev - sE[s]) * ((k & 1) ? A.inv_diag : A.inv_orth), A);
-                const float phi = A.p_base * sg[s] * hexp(x);
-                if constexpr (FORM == 0)
-                    prod = prod * (1.0 - (double)one_minus_exp_neg(gam * phi) * Bu);
-                else
-                    lam = lam + (double)phi * Bu;
-            }
-            P = FORM == 0 ? 1.0 - prod : -expm1(-(double)gam * lam);
-        }
-        const double N = Uv * P;
-        Uo[v] = Uv - N;
-        Bo[v] = N + (double)A.p_continue * Bv;
-    }
-}
-
 // ---------------------------------------------------------------- adjoint
 // Adjoint tiles are AW = 64 columns (one wave, one column per lane) by AR
 // rows.  A wave walks its tile's rows top to bottom with the target row r in
@@ -255,6 +185,8 @@ __global__ __launch_bounds__(256) void relaxed_fwd_kernel(
 // land-cover class and density of the foreign cell.  No atomics: Bbar, Ubar
 // and the gradient are the same bits on every run.
 constexpr int AW = kAdjW, AR = kAdjR;
+constexpr int kFwdSplit = 4;  // row bands (waves) per tile in the forward
+static_assert(AR % kFwdSplit == 0, "forward row bands");
 constexpr int kXTop = 0, kXBot = AW, kXLeft = 2 * AW, kXRight = 2 * AW + AR + 2;
 static_assert(kXRight + AR + 2 <= kXTile, "exchange record");
 
@@ -812,6 +744,120 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void r
     }
 }
 
+// One relaxed forward step on the adjoint's 64 x AR tiles, each cut into
+// kFwdSplit row bands of one wave (four per workgroup, so that enough loads
+// are in flight): lanes own columns and walk the rows with the same
+// window as the adjoint (left and right sources by DPP from the neighbouring
+// lanes, the ghost columns for lanes 0 and 63), so each cell is loaded once.
+// FORM 0: p_ignite = 1 - prod_k (1 - q_k B_k); FORM 1: p_ignite = 1 -
+// exp(-gamma sum_k B_k phi_k).  Rows where no lane sees burning mass skip the
+// edge terms (P = 0 exactly there).
+template <bool WC, int FORM, int SL>
+__global__ __launch_bounds__(256) void relaxed_fwd_kernel(
+    const RelaxedTile* __restrict__ tiles, int32_t n_tiles, int32_t groups_per_xcd,
+    const EnvDev* __restrict__ envs, const float* __restrict__ g, const float* __restrict__ E,
+    const float* __restrict__ wind, int64_t n_cells, RelaxedArgs A, const double* __restrict__ U,
+    const double* __restrict__ B, double* __restrict__ Uo, double* __restrict__ Bo,
+    const float* __restrict__ env_wind)
+{
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int b = blockIdx.x;
+    const int wix = (((b & 7) * groups_per_xcd + (b >> 3)) << 2) + wv;
+    if (wix >= n_tiles * kFwdSplit) return;
+    const RelaxedTile td = tiles[wix / kFwdSplit];
+    const EnvDev ed = envs[td.env];
+    const int H = ed.H, W = ed.W, r0 = td.r0 + (wix % kFwdSplit) * (AR / kFwdSplit);
+    if (r0 >= H) return;
+    const int rows = min(AR / kFwdSplit, H - r0);
+    const int c = td.c0 + lane;
+    const bool act = c < W;
+    const int cg = lane == 0 ? td.c0 - 1 : td.c0 + AW;
+    const bool ghost = (lane == 0 && td.c0 > 0) || (lane == 63 && td.c0 + AW < W);
+    const int64_t base = ed.offset;
+    AdjEnv P{};
+    P.U = U + base;
+    P.B = B + base;
+    P.g = g + base;
+    P.E = E + base;
+    if constexpr (WC) {
+        P.V = wind + base;
+        P.Vx = wind + n_cells + base;
+        P.Vy = wind + 2 * n_cells + base;
+    }
+    double* const Uoe = Uo + base;
+    double* const Boe = Bo + base;
+    auto at = [&](int r, int col) { return (uint32_t)(r * W + col); };
+    const float3 wenv = env_wind_of(ed, env_wind, td.env);
+    const float wA0 = (A.alpha_w1 - A.alpha_w2) * wenv.x, wA1 = A.alpha_w2 * wenv.y, wA2 = A.alpha_w2 * wenv.z;
+    const double p_c = A.p_continue;
+
+    AdjCell Xa = load_adj_cell<WC>(P, at(r0 - 1, c), act && r0 > 0);
+    AdjCell Xm = load_adj_cell<WC>(P, at(r0, c), act);
+    AdjCell Xb = load_adj_cell<WC>(P, at(r0 + 1, c), act && r0 + 1 < H);
+    AdjCell Ga = load_adj_cell<WC>(P, at(r0 - 1, cg), ghost && r0 > 0);
+    AdjCell Gm = load_adj_cell<WC>(P, at(r0, cg), ghost);
+    AdjCell Gb = load_adj_cell<WC>(P, at(r0 + 1, cg), ghost && r0 + 1 < H);
+    double nU = act ? ld_at(P.U, at(r0, c)) : 0.0;
+
+#pragma unroll 1
+    for (int i = 0; i < rows; ++i) {
+        const int r = r0 + i;
+        const uint32_t v = at(r, c);
+        const double Uv = nU;
+        if (act && i + 1 < rows) nU = ld_at(P.U, v + W);
+        const bool more = i + 1 < rows && r + 2 < H;
+        const AdjCell Xn = load_adj_cell<WC>(P, at(r + 2, c), act && more);
+        const AdjCell Gn = load_adj_cell<WC>(P, at(r + 2, cg), ghost && more);
+
+        double Pv = 0.0;
+        const bool any_burning = Xa.B != 0.0 || Xm.B != 0.0 || Xb.B != 0.0 || Ga.B != 0.0 || Gm.B != 0.0 ||
+                                 Gb.B != 0.0;
+        if (__any(any_burning)) {  // wave-uniform
+            const AdjCell La = left_of<WC>(Xa, Ga), Lm = left_of<WC>(Xm, Gm), Lb = left_of<WC>(Xb, Gb);
+            const AdjCell Ra = right_of<WC>(Xa, Ga), Rm = right_of<WC>(Xm, Gm), Rb = right_of<WC>(Xb, Gb);
+            const double sB[8] = {Lm.B, Lb.B, Xb.B, Rb.B, Rm.B, Ra.B, Xa.B, La.B};
+            const float sg[8] = {Lm.g, Lb.g, Xb.g, Rb.g, Rm.g, Ra.g, Xa.g, La.g};
+            const float sE[8] = {Lm.E, Lb.E, Xb.E, Rb.E, Rm.E, Ra.E, Xa.E, La.E};
+            const float sV[8] = {Lm.V, Lb.V, Xb.V, Rb.V, Rm.V, Ra.V, Xa.V, La.V};
+            const float sVx[8] = {Lm.Vx, Lb.Vx, Xb.Vx, Rb.Vx, Rm.Vx, Ra.Vx, Xa.Vx, La.Vx};
+            const float sVy[8] = {Lm.Vy, Lb.Vy, Xb.Vy, Rb.Vy, Rm.Vy, Ra.Vy, Xa.Vy, La.Vy};
+            const float Ev = Xm.E, gam = A.alpha_gamma * Xm.g;
+            double prod = 1.0, lam = 0.0;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const float rr = (Ev - sE[k]) * ((k & 1) ? A.inv_diag : A.inv_orth);
+                float x = A.alpha_s * (SL ? atanf(rr) : rr);
+                if constexpr (WC) {
+                    x = x + (A.alpha_w1 * sV[k] + A.alpha_w2 * ((kCos[k] * sVx[k] + kSin[k] * sVy[k]) - sV[k]));
+                } else {
+                    x = x + wA0;
+                    if (kCos[k] != 0.0f) x = x + kCos[k] * wA1;
+                    if (kSin[k] != 0.0f) x = x + kSin[k] * wA2;
+                }
+                // off-grid sources read 0: no fuel, no burning mass
+                const float phi = A.p_base * (sg[k] * hexp(fminf(x, 88.0f)));
+                if constexpr (FORM == 0)
+                    prod = prod * (1.0 - (double)one_minus_exp_neg(gam * phi) * sB[k]);
+                else
+                    lam = lam + (double)phi * sB[k];
+            }
+            Pv = FORM == 0 ? 1.0 - prod : -expm1(-(double)gam * lam);
+        }
+        if (act) {
+            const double N = Uv * Pv;
+            st_at(Uoe, v, Uv - N);
+            st_at(Boe, v, N + p_c * Xm.B);
+        }
+        Xa = Xm;
+        Xm = Xb;
+        Xb = Xn;
+        Ga = Gm;
+        Gm = Gb;
+        Gb = Gn;
+    }
+}
+
 // grad[j] = sum over tiles of gsum[tile][j], one workgroup per j, in a fixed order.
 __global__ __launch_bounds__(256) void gsum_reduce_kernel(const double* __restrict__ gsum, int32_t n_tiles,
                                                           double* __restrict__ grad)
@@ -1099,8 +1145,11 @@ template <bool WC, int FORM>
 void launch_fwd(hipStream_t s, const RelaxedInputs& in, const RelaxedArgs& A, const float* g,
                 const double* U, const double* B, double* Uo, double* Bo)
 {
-    hipLaunchKernelGGL((relaxed_fwd_kernel<WC, FORM>), dim3(in.n_tiles), dim3(256), 0, s, in.tiles,
-                       in.envs, g, in.E, in.wind, in.n_cells, A, U, B, Uo, Bo, in.env_wind);
+    const int32_t groups = (in.n_tiles * kFwdSplit + 3) / 4;
+    const int32_t per_xcd = (groups + 7) / 8;
+    auto kernel = A.slope_mode ? relaxed_fwd_kernel<WC, FORM, 1> : relaxed_fwd_kernel<WC, FORM, 0>;
+    hipLaunchKernelGGL(kernel, dim3(8 * per_xcd), dim3(256), 0, s, in.tiles, in.n_tiles, per_xcd, in.envs, g,
+                       in.E, in.wind, in.n_cells, A, U, B, Uo, Bo, in.env_wind);
 }
 
 hipError_t fwd_step(hipStream_t s, const RelaxedInputs& in, const RelaxedArgs& A, const float* g,
@@ -1138,13 +1187,11 @@ int64_t relaxed_adj_tiles(const std::vector<sim_env>& envs)
 
 int relaxed_prepare(RelaxedState& R, const std::vector<sim_env>& envs)
 {
-    if (R.d_tiles) return 0;
-    std::vector<RelaxedTile> tiles, btiles;
+    if (R.d_btiles) return 0;
+    std::vector<RelaxedTile> btiles;
     std::vector<TileGrid> grids;
     int64_t ioff = 0, max_img = 0;
     for (int32_t e = 0; e < (int32_t)envs.size(); ++e) {
-        for (int r0 = 0; r0 < envs[e].H; r0 += TH)
-            for (int c0 = 0; c0 < envs[e].W; c0 += TW) tiles.push_back(RelaxedTile{e, r0, c0, 0});
         TileGrid tg{(int32_t)btiles.size(), (envs[e].H + AR - 1) / AR, (envs[e].W + AW - 1) / AW, (int32_t)ioff};
         for (int r0 = 0; r0 < envs[e].H; r0 += AR)
             for (int c0 = 0; c0 < envs[e].W; c0 += AW) btiles.push_back(RelaxedTile{e, r0, c0, 0});
@@ -1153,10 +1200,6 @@ int relaxed_prepare(RelaxedState& R, const std::vector<sim_env>& envs)
         max_img = std::max(max_img, img);
         grids.push_back(tg);
     }
-    if (hipMalloc(&R.d_tiles, tiles.size() * sizeof(RelaxedTile)) != hipSuccess) return -1;
-    if (hipMemcpy(R.d_tiles, tiles.data(), tiles.size() * sizeof(RelaxedTile), hipMemcpyHostToDevice) !=
-        hipSuccess)
-        return -1;
     if (hipMalloc(&R.d_btiles, btiles.size() * sizeof(RelaxedTile)) != hipSuccess) return -1;
     if (hipMemcpy(R.d_btiles, btiles.data(), btiles.size() * sizeof(RelaxedTile),
                   hipMemcpyHostToDevice) != hipSuccess)
@@ -1164,7 +1207,6 @@ int relaxed_prepare(RelaxedState& R, const std::vector<sim_env>& envs)
     if (hipMalloc(&R.d_tgrid, grids.size() * sizeof(TileGrid)) != hipSuccess) return -1;
     if (hipMemcpy(R.d_tgrid, grids.data(), grids.size() * sizeof(TileGrid), hipMemcpyHostToDevice) != hipSuccess)
         return -1;
-    R.n_tiles = (int32_t)tiles.size();
     R.n_btiles = (int32_t)btiles.size();
     R.n_env = (int32_t)envs.size();
     if (ioff < INT32_MAX && 4 * max_img <= 64 * 1024) {
@@ -1210,7 +1252,7 @@ int relaxed_prepare_pool(RelaxedState& R, const std::vector<sim_env>& envs, int 
 
 void relaxed_free(RelaxedState& R)
 {
-    for (void* p : {(void*)R.d_tiles, (void*)R.d_btiles, (void*)R.d_pool,
+    for (void* p : {(void*)R.d_btiles, (void*)R.d_pool,
                     (void*)R.d_env_blocks, (void*)R.d_pool_vals, (void*)R.d_bce_loss, (void*)R.d_tgrid,
                     (void*)R.d_tmass, (void*)R.d_tinteg})
         if (p) (void)hipFree(p);

@@ -11,9 +11,8 @@
 
 namespace firesim {
 
-// Tiles of the relaxed kernels: forward 32 x 16 cells, adjoint 64 x 16 cells
-// (one wave, one column per lane).
-constexpr int kRelaxTW = 32, kRelaxTH = 16;
+// Tiles of the relaxed kernels (forward and adjoint): 64 x 32 cells, one wave
+// each, one column per lane.
 constexpr int kAdjW = 64, kAdjR = 32;
 // Exchange record of an adjoint tile (doubles): Bbar terms for the rows
 // just above and below the tile (64 each) and the columns just left and
@@ -33,9 +32,7 @@ struct TileGrid {
 
 // Per-handle state of the relaxed path (built on first use).
 struct RelaxedState {
-    RelaxedTile* d_tiles = nullptr;   // forward / loss tiles
-    int32_t n_tiles = 0;
-    RelaxedTile* d_btiles = nullptr;  // adjoint tiles
+    RelaxedTile* d_btiles = nullptr;  // tiles of the forward and the adjoint
     int32_t n_btiles = 0;
     int32_t n_env = 0;
     // pooled blocks of the BCE + pooled-MSE loss (built for one pool size)
