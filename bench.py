@@ -18,7 +18,11 @@ Reported beside it, each in its own object:
                 setting, the RL layer on 65536 envs of 20 x 20, the 4096-env
                 uneven batch with drops, and 8 envs of 2048 x 2048 with
                 per-cell wind (1000 steps);
-  copy_probe  - a 1 GiB device copy: the attainable HBM bandwidth;
+  product_plan - the same workload under the library's default plan (fuel
+                read at fronts, quiet tiles skipped), with counter-measured HBM
+                bytes;
+  stream_probe - the library's HBM streaming probe (read, write, copy of
+                1 GiB) and torch's copy: the attainable bandwidth;
   cpu_baseline - the CPU oracle on the same stochastic workload.
 
 Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -44,6 +48,11 @@ STOCH_WIND_CELL_BYTES = 12     # per-cell wind adds V, Vx, Vy (3 x 4 B) per cell
 # elevation 8) and adjoint 61 B (U,B 16, adjoint r/w 32, fuel, elevation,
 # density 12, class 1); per-cell wind adds V, Vx, Vy (12 B) to each pass
 RELAXED_FWD_BYTES, RELAXED_ADJ_BYTES, RELAXED_WIND_BYTES = 40, 61, 12
+# the same accounting for an fp32 state (what the method must move): forward
+# 24 B (U,B r/w 16 + fuel, elevation 8), adjoint 32 B (U,B 8, adjoint r/w 16,
+# fuel, elevation 8); forward + recompute + adjoint = 80 B per cell-step
+RELAXED_ALG_FWD_BYTES, RELAXED_ALG_ADJ_BYTES = 24, 32
+RELAXED_ALG_BYTES = 2 * RELAXED_ALG_FWD_BYTES + RELAXED_ALG_ADJ_BYTES
 
 
 def relaxed_bytes_per_cell_step(T: int, k: int, wind_cell: bool) -> float:
@@ -75,34 +84,54 @@ def kernel_hash() -> str:
 
 
 def stored_traffic(plan_key: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source and plan."""
+    """HBM bytes per launch from the committed rocprofv3 counter records, if
+    one was taken on the current kernel source and this plan."""
     try:
-        rec = json.load(open(TRAFFIC_FILE))
+        recs = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_hash") != kernel_hash() or rec.get("plan") != plan_key:
-        return None
-    return rec.get("bytes_per_launch")
+    for rec in recs.get("records", []):
+        if rec.get("kernel_hash") == kernel_hash() and rec.get("plan") == plan_key:
+            return rec.get("bytes_per_launch")
+    return None
 
 
-def copy_probe(torch):
-    """Attainable HBM bandwidth on this GPU: a 1 GiB device-to-device copy
-    (read + write bytes per second, best of 5)."""
+def plan_key_of(plan: dict) -> str:
+    return "tile_rows=%d,tile_width=%d,skip_static=%d,sparse=%d" % (
+        plan["tile_rows"], plan["tile_width"], plan["skip_static"], plan["sparse"])
+
+
+def stream_probe(torch, fs):
+    """Attainable HBM bandwidth on this GPU: the library's streaming probe
+    (16-byte accesses, nontemporal stores) reading, writing and copying 1 GiB,
+    and torch's 1 GiB device copy beside it."""
     a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
     b = torch.empty_like(a)
-    b.copy_(a)
     stream = torch.cuda.current_stream()
-    best = float("inf")
-    for _ in range(5):
-        with StepTimer(torch, stream) as tm:
-            b.copy_(a)
-        best = min(best, tm.ms())
-    gbs = 2 * a.numel() / (best / 1e3) / 1e9
-    log("[bench] copy probe: 1 GiB in %.3f ms = %.0f GB/s (read + write)" % (best, gbs))
+
+    def best_ms(fn):
+        fn()
+        best = float("inf")
+        for _ in range(5):
+            with StepTimer(torch, stream) as tm:
+                fn()
+            best = min(best, tm.ms())
+        return best
+
+    out = {"kind": "1 GiB streams; best of 5 at each of 16384, 32768 and 65536 workgroups"}
+    for name, mode, moved in (("read", 0, 1), ("write", 1, 1), ("copy", 2, 2)):
+        ms, blocks = min((best_ms(lambda: fs.debug_stream(mode, None if mode == 1 else a, b, blocks=nb)), nb)
+                         for nb in (16384, 32768, 65536))
+        gbs = moved * a.numel() / (ms / 1e3) / 1e9
+        out[name] = {"ms": round(ms, 4), "GBs": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
+                     "workgroups": blocks}
+        log("[bench] stream probe %s: 1 GiB in %.3f ms = %.0f GB/s" % (name, ms, gbs))
+    ms = best_ms(lambda: b.copy_(a))
+    gbs = 2 * a.numel() / (ms / 1e3) / 1e9
+    out["torch_copy"] = {"ms": round(ms, 4), "GBs": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4)}
+    log("[bench] torch copy_: 1 GiB in %.3f ms = %.0f GB/s (read + write)" % (ms, gbs))
     del a, b
-    return {"kind": "1 GiB device copy (torch copy_), best of 5", "ms": round(best, 4), "GBs": round(gbs, 1),
-            "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4)}
+    return out
 
 
 def cpu_baseline(batch, params, T, seed):
@@ -182,13 +211,16 @@ def bench_stochastic(args, torch, fs, firegen):
     cells = float(batch.n_cells)
     value = cells * T / (ms / 1e3)
     achieved = STOCH_BYTES_PER_CELL * cells / (launch_ms / 1e3) / 1e9
-    plan_key = "tile_rows=%d,tile_width=%d,skip_static=%d,sparse=%d" % (
-        sim.plan()["tile_rows"], sim.plan()["tile_width"], args.skip_static, args.sparse)
+    plan_key = plan_key_of(sim.plan())
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": stored_traffic(plan_key),
             "kernel": "stoch_step_kernel", "launch_ms": round(launch_ms, 5),
-            "algorithmic_bytes_per_launch": STOCH_BYTES_PER_CELL * int(cells)}
+            "algorithmic_bytes_per_launch": STOCH_BYTES_PER_CELL * int(cells),
+            "note": "one step per tile load with every cell's state, fuel and elevation streamed (the "
+                    "k=1 roofline probe); front cells read their neighbours' fuel and elevation again "
+                    "through the cache, so the fuel and elevation of non-front cells are loaded unused; "
+                    "the library's default plan skips them (product_plan)"}
     log("[bench] stochastic: %.3f ms/step, %.3e cell-updates/s, kernel %.4f ms = %.0f GB/s (wall %.2fs)"
         % (ms, value, launch_ms, achieved, wall))
     sim.states.copy_(init)
@@ -196,6 +228,36 @@ def bench_stochastic(args, torch, fs, firegen):
     burning = int(sim.step(T, counts=True).sum())
     return dict(batch=batch, params=params, T=T, seed=seed, value=value, ms=ms, roof=roof, plan=plan,
                 burning=burning, sim=sim, init=init)
+
+
+# the library's default launch plan (what sim_init sets), graph-replayed here
+PRODUCT_PLAN = dict(tile_rows=4, tile_width=64, skip_static=1, sparse=1, graph=1)
+
+
+def bench_product_plan(args, torch, fs, st):
+    """The default plan on the same workload: fuel and elevation read only at
+    front cells, tiles with no fire in reach skipped.  Its roofline uses the
+    HBM bytes the counters measured for it (an effective rate: it moves fewer
+    than the 10 B per cell-update the dense probe streams)."""
+    sim, init, T = st["sim"], st["init"], st["T"]
+    cells = float(st["batch"].n_cells)
+    stream = torch.cuda.current_stream()
+    sim.set_plan(**PRODUCT_PLAN)
+    ms, launch_ms = timed_runs(torch, stream, sim, init, T, args.steps, 1)
+    traffic = stored_traffic(plan_key_of(sim.plan()))
+    roof = {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None,
+            "traffic": traffic, "kernel": "stoch_step_kernel", "launch_ms": round(launch_ms, 5),
+            "bytes_per_cell_update": None if traffic is None else round(traffic / cells, 3)}
+    if traffic is not None:
+        roof["achieved"] = round(traffic / (launch_ms / 1e3) / 1e9, 1)
+        roof["frac"] = round(roof["achieved"] / HBM_PEAK_GBS, 4)
+    out = {"plan": PRODUCT_PLAN, "ms_per_step": round(ms, 4), "value": cells * T / (ms / 1e3),
+           "unit": "cell-updates/s", "roofline": roof,
+           "note": "the library's default plan; bit-identical states; achieved = counter-measured HBM bytes "
+                   "per launch / launch time"}
+    log("[bench] product plan: %.3f ms/step, %.3e cell-updates/s, launch %.4f ms, traffic %s"
+        % (ms, out["value"], launch_ms, traffic))
+    return out
 
 
 def bench_variants(args, torch, fs, st):
@@ -445,52 +507,89 @@ def bench_large(args, torch, fs, firegen):
     return out
 
 
-def relaxed_case(args, torch, fs, firegen, batch, params, T, k, label):
+def relaxed_case(args, torch, fs, firegen, batch, params, T, k, label, roofline):
     sim = fs.FireSim.from_batch(batch, params, seed=0)
     sim.step(T)   # target scar: a stochastic run at the known parameters
-    sim.set_plan(sparse=0)  # the dense adjoint: every tile, every step
     Y = ((sim.states == firegen.BURNING) | (sim.states == firegen.BURNT)).to(torch.uint8)
+    sim.set_plan(sparse=0)  # the dense adjoint: every tile, every step
     theta = fs.params_with_theta(sim.params, [params.p_base * 1.2, params.alpha_w1 * 1.2,
                                               params.alpha_w2 * 1.2, params.alpha_s * 1.2,
                                               params.alpha_gamma, params.p_continue, *params.veg])
-    ws = sim.relaxed_workspace(T, k)
     stream = torch.cuda.current_stream()
+    wind = batch.wind_cell is not None
 
-    def fwd_bwd():
+    def fwd_bwd(T, k, ws):
         U, B = sim.relaxed_init()
         sim.relaxed_fwd(theta, U, B, T, k, ws)
         loss, gU, _ = sim.relaxed_loss(U, Y, scale=1.0 / batch.n_env)
-        return loss, sim.relaxed_bwd(theta, gU, None, T, k, ws)
+        return loss, gU, sim.relaxed_bwd(theta, gU, None, T, k, ws)
 
-    def timed():
-        fwd_bwd()
+    def timed(fn):
+        fn()
         torch.cuda.synchronize()
         reps = max(1, args.relaxed_reps)
         with StepTimer(torch, stream) as tm:
             for _ in range(reps):
-                loss, grad = fwd_bwd()
-        return tm.ms() / reps, loss, grad
+                out = fn()
+        return tm.ms() / reps, out
 
-    ms, loss, grad = timed()   # dense adjoint: the roofline figure
+    ws = sim.relaxed_workspace(T, k)
+    ms, (loss, _, grad) = timed(lambda: fwd_bwd(T, k, ws))   # dense adjoint
     cs = float(batch.n_cells) * T / (ms / 1e3)
-    bpc = round(relaxed_bytes_per_cell_step(T, k, batch.wind_cell is not None), 2)
-    gbs = cs * bpc / 1e9
-    log("[bench] relaxed %s: %.2f ms per fwd+bwd, %.3e cell-steps/s, %.0f GB/s, loss %.4f"
-        % (label, ms, cs, gbs, float(loss.mean())))
+    bpc = round(relaxed_bytes_per_cell_step(T, k, wind), 2)
+    log("[bench] relaxed %s: %.2f ms per fwd+bwd, %.3e cell-steps/s (%.1f%% of HBM at %d B, %.1f%% at the "
+        "fp64 state's %.1f B), loss %.4f" % (label, ms, cs, 100 * cs * RELAXED_ALG_BYTES / 1e9 / HBM_PEAK_GBS,
+                                          RELAXED_ALG_BYTES, 100 * cs * bpc / 1e9 / HBM_PEAK_GBS, bpc,
+                                          float(loss.mean())))
     out = {"value": cs, "unit": "cell-steps/s", "ms_per_fwd_bwd": round(ms, 3), "workload": label,
-           "algorithmic_bytes_per_cell_step": bpc, "achieved_GBs": round(gbs, 1),
-           "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "loss": round(float(loss.mean()), 6)}
+           "loss": round(float(loss.mean()), 6), "gradient_norm": float(grad.norm())}
+    if roofline:
+        out["hbm_frac_at_80B"] = round(cs * RELAXED_ALG_BYTES / 1e9 / HBM_PEAK_GBS, 4)
+        out["fp64_state"] = {"bytes_per_cell_step": bpc, "achieved_GBs": round(cs * bpc / 1e9, 1),
+                             "hbm_frac": round(cs * bpc / 1e9 / HBM_PEAK_GBS, 4)}
+        # per kernel: every step checkpointed (no recompute); the difference
+        # of T- and T/2-step calls removes the fixed costs, leaving T/2 launches
+        half = T // 2
+        ws1 = sim.relaxed_workspace(T, 1)
+        launches = {}
+        for name, T_ in (("full", T), ("half", half)):
+            U0, B0 = sim.relaxed_init()
+            t_f, _ = timed(lambda: sim.relaxed_fwd(theta, U0.clone(), B0.clone(), T_, 1, ws1))
+            U, B = sim.relaxed_init()
+            sim.relaxed_fwd(theta, U, B, T_, 1, ws1)
+            _, gU, _ = sim.relaxed_loss(U, Y, scale=1.0 / batch.n_env)
+            t_b, _ = timed(lambda: sim.relaxed_bwd(theta, gU, None, T_, 1, ws1))
+            launches[name] = (t_f, t_b)
+        del ws1
+        kern = {}
+        w = RELAXED_WIND_BYTES if wind else 0
+        for i, (kname, fp64_b, alg_b) in enumerate((("relaxed_fwd_kernel", RELAXED_FWD_BYTES + w,
+                                                      RELAXED_ALG_FWD_BYTES + w),
+                                                     ("relaxed_adj_kernel", RELAXED_ADJ_BYTES + w,
+                                                      RELAXED_ALG_ADJ_BYTES + w))):
+            us = (launches["full"][i] - launches["half"][i]) / (T - half) * 1e3
+            kern[kname] = {"launch_us": round(us, 2), "bytes_per_cell": fp64_b,
+                           "achieved_GBs": round(batch.n_cells * fp64_b / us / 1e3, 1),
+                           "frac": round(batch.n_cells * fp64_b / us / 1e3 / HBM_PEAK_GBS, 4),
+                           "frac_at_fp32_state_bytes": round(batch.n_cells * alg_b / us / 1e3 / HBM_PEAK_GBS, 4),
+                           "fp32_state_bytes_per_cell": alg_b}
+            log("[bench] relaxed %s %s: %.1f us per launch, %.0f GB/s at %d B (fp64 state)"
+                % (label.split(":")[0], kname, us, kern[kname]["achieved_GBs"], fp64_b))
+        out["kernels"] = kern
+    else:
+        out["note"] = "the whole working set fits the 256 MB Infinity Cache: not an HBM roofline configuration"
     if args.relaxed_sparse:
         # sparse adjoint (tiles beyond the reach of the initial fire skipped):
         # an effective rate, same gradient
         sim.set_plan(sparse=1)
-        ms_sp, _, grad_sp = timed()
+        ms_sp, (_, _, grad_sp) = timed(lambda: fwd_bwd(T, k, ws))
         sim.set_plan(sparse=0)
-        rel = float((grad_sp - grad).abs().max() / grad.abs().max())
-        log("[bench] relaxed %s, sparse adjoint: %.2f ms (gradient max rel. difference %.1e)" % (label, ms_sp, rel))
+        same = bool(torch.equal(grad_sp, grad))
+        log("[bench] relaxed %s, sparse adjoint: %.2f ms (gradient %s)" % (label, ms_sp,
+                                                                         "bit-identical" if same else "DIFFERS"))
         out["sparse_adjoint"] = {"ms_per_fwd_bwd": round(ms_sp, 3),
                                  "value": float(batch.n_cells) * T / (ms_sp / 1e3),
-                                 "grad_max_rel_difference": rel,
+                                 "gradient_bit_identical": same,
                                  "note": "effective rate: adjoint tiles beyond the reach of the initial "
                                          "burning mass are skipped"}
     return out
@@ -499,16 +598,19 @@ def relaxed_case(args, torch, fs, firegen, batch, params, T, k, label):
 def bench_relaxed(args, torch, fs, firegen):
     batch, params, T, k = firegen.workload_relaxed()
     small = relaxed_case(args, torch, fs, firegen, batch, params, T, k,
-                         "relaxed128: 256 envs x 128x128, T=100, checkpoint every 10, fp64 state")
+                         "relaxed128: 256 envs x 128x128, T=100, checkpoint every 10, fp64 state", False)
     del batch
     batch, params, T, k = firegen.workload_relaxed_large()
     large = relaxed_case(args, torch, fs, firegen, batch, params, T, k,
                          "relaxed2048: 1 env 2048x2048, per-cell wind, T=100, checkpoint every 10, "
-                         "fp64 state")
-    large["roofline"] = {"bound": "hbm", "achieved": large["achieved_GBs"], "peak": HBM_PEAK_GBS,
-                         "unit": "GB/s", "frac": large["hbm_frac"],
-                         "note": "whole fwd+bwd (forward, recompute, adjoint, loss) at the "
-                                 "algorithmic bytes per cell-step"}
+                         "fp64 state", True)
+    adj = large["kernels"]["relaxed_adj_kernel"]
+    large["roofline"] = {"bound": "hbm", "achieved": round(large["value"] * RELAXED_ALG_BYTES / 1e9, 1),
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": large["hbm_frac_at_80B"],
+                         "bytes_per_cell_step": RELAXED_ALG_BYTES,
+                         "dominant_kernel": "relaxed_adj_kernel", "dominant_launch_us": adj["launch_us"],
+                         "note": "whole fwd+bwd (forward, recompute, adjoint, loss) at the method's 80 B per "
+                                 "cell-step (fp32 state); the adjoint is VALU-bound, see the kernel profiles"}
     return {"relaxed128": small, "relaxed2048": large}
 
 
@@ -551,6 +653,7 @@ def main():
         sys.exit(1)
     fs.lib()
     st = bench_stochastic(args, torch, fs, firegen)
+    product = bench_product_plan(args, torch, fs, st) if st["value"] is not None else None
     variants = None if args.no_variants else bench_variants(args, torch, fs, st)
     dense = None if args.no_dense_front else bench_dense_front(args, torch, fs, firegen, st)
     st.pop("sim")
@@ -566,7 +669,7 @@ def main():
         for _ in range(3):
             b.copy_(a)
         torch.cuda.synchronize()
-    probe = copy_probe(torch)
+    probe = stream_probe(torch, fs)
     cpu = None if args.no_cpu else cpu_baseline(st["batch"], st["params"], st["T"], st["seed"])
     batch = st["batch"]
     out = {"metric": "cell-updates/s stochastic step + relaxed fwd+bwd cell-steps/s, % HBM peak",
@@ -577,8 +680,8 @@ def main():
                                   "11-class land cover, fractal terrain, per-env wind, 1-5 ignitions",
                       "n_env": int(batch.n_env), "H": 256, "W": 256, "T": st["T"], "plan": st["plan"],
                       "burning_cell_steps": st["burning"]},
-           "roofline": st["roof"], "variants": variants, "dense_front": dense, "relaxed": relaxed,
-           "paper_setting": paper, "rl": rl, "uneven": uneven, "large": large, "copy_probe": probe,
+           "roofline": st["roof"], "product_plan": product, "variants": variants, "dense_front": dense, "relaxed": relaxed,
+           "paper_setting": paper, "rl": rl, "uneven": uneven, "large": large, "stream_probe": probe,
            "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
 

@@ -407,6 +407,15 @@ int sim_debug_atan(const float* x, float* y, int64_t n, void* stream);
 int sim_debug_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int64_t n,
                      void* stream);
 
+/* HBM streaming probe, the attainable-bandwidth reference for the roofline
+ * figures: mode 0 reads src, 1 writes dst, 2 copies src to dst, with 16-byte
+ * accesses by `blocks` workgroups of 256 lanes (grid-stride).
+ *  src, dst   device, 16-byte aligned; bytes a multiple of 16.  Mode 0 writes
+ *             nothing (it only may, for an xor of the data no real input has,
+ *             write dst[blocks * 256] words); mode 1 ignores src.
+ * Returns SIM_EINVAL for a bad mode, size, alignment or block count. */
+int sim_debug_stream(int32_t mode, const void* src, void* dst, int64_t bytes, int32_t blocks, void* stream);
+
 const char* sim_last_error(const sim_handle* h);
 void sim_destroy(sim_handle* h);
 

@@ -41,7 +41,7 @@ EXPORTED = ("sim_init", "sim_step", "sim_get_step", "sim_set_step", "sim_set_pla
             "sim_autotune", "sim_set_wind_series", "sim_step_history", "sim_set_drop",
             "sim_rl_reset", "sim_rl_step",
             "sim_relaxed_init", "sim_relaxed_workspace_bytes", "sim_step_relaxed_fwd",
-            "sim_relaxed_loss", "sim_relaxed_loss_noalloc", "sim_relaxed_loss_bce", "sim_step_relaxed_bwd", "sim_debug_exp", "sim_debug_atan", "sim_debug_philox",
+            "sim_relaxed_loss", "sim_relaxed_loss_noalloc", "sim_relaxed_loss_bce", "sim_step_relaxed_bwd", "sim_debug_exp", "sim_debug_atan", "sim_debug_philox", "sim_debug_stream",
             "sim_last_error", "sim_destroy")
 
 
@@ -110,6 +110,7 @@ def lib() -> ctypes.CDLL:
         L.sim_debug_exp.argtypes = [P, P, I64, P]
         L.sim_debug_atan.argtypes = [P, P, I64, P]
         L.sim_debug_philox.argtypes = [P, P, P, I64, P]
+        L.sim_debug_stream.argtypes = [I32, P, P, I64, I32, P]
         L.sim_last_error.argtypes = [P]
         L.sim_last_error.restype = ctypes.c_char_p
         L.sim_destroy.argtypes = [P]
@@ -176,6 +177,13 @@ def debug_exp(x: torch.Tensor) -> torch.Tensor:
     y = torch.empty_like(x)
     _check(lib().sim_debug_exp(_ptr(x), _ptr(y), x.numel(), ctypes.c_void_p(_stream(x.device))))
     return y
+
+
+def debug_stream(mode: int, src: Optional[torch.Tensor], dst: torch.Tensor, blocks: int = 8192):
+    """The library's HBM streaming probe (0 read src, 1 write dst, 2 copy) on
+    the current stream; src and dst are byte-sized views of device memory."""
+    n = dst.numel() * dst.element_size() if src is None else src.numel() * src.element_size()
+    _check(lib().sim_debug_stream(int(mode), _ptr(src), _ptr(dst), int(n), int(blocks), _stream(dst.device)))
 
 
 def debug_philox(ctr: torch.Tensor, key: torch.Tensor) -> torch.Tensor:

@@ -984,6 +984,16 @@ int sim_debug_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out, in
     return launch_debug_philox((hipStream_t)stream, ctr, key, out, n) == hipSuccess ? SIM_OK : SIM_EHIP;
 }
 
+int sim_debug_stream(int32_t mode, const void* src, void* dst, int64_t bytes, int32_t blocks, void* stream)
+{
+    CallScope scope("sim_debug_stream", nullptr);
+    if (mode < 0 || mode > 2 || bytes < 16 || bytes % 16 != 0 || blocks < 1 || blocks > (1 << 20))
+        return SIM_EINVAL;
+    if ((mode != 1 && (!src || (uintptr_t)src % 16)) || !dst || (uintptr_t)dst % 16) return SIM_EINVAL;
+    return launch_stream_probe((hipStream_t)stream, mode, src, dst, bytes / 16, blocks) == hipSuccess ? SIM_OK
+                                                                                                     : SIM_EHIP;
+}
+
 const char* sim_last_error(const sim_handle* h)
 {
     return h ? h->err.c_str() : g_init_error.c_str();

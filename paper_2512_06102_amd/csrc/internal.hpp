@@ -106,6 +106,8 @@ hipError_t launch_stoch_tb(hipStream_t s, const StepLaunch& L, int K, int tile_w
 hipError_t launch_set_u32(hipStream_t s, uint32_t* p, uint32_t v);
 
 hipError_t launch_debug_exp(hipStream_t s, const float* x, float* y, int64_t n);
+// HBM streaming probe over n16 16-byte words with `blocks` workgroups of 256.
+hipError_t launch_stream_probe(hipStream_t s, int mode, const void* src, void* dst, int64_t n16, int blocks);
 hipError_t launch_debug_atan(hipStream_t s, const float* x, float* y, int64_t n);
 hipError_t launch_debug_philox(hipStream_t s, const uint32_t* ctr, const uint32_t* key,
                                uint32_t* out, int64_t n);
