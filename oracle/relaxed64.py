@@ -305,7 +305,19 @@ def _param_chain(env: Env64, theta, terms, phibar, gamma_bar) -> np.ndarray:
 def adjoint(env: Env64, theta, Us, Bs, terms, gU_T, gB_T=None, form="product") -> np.ndarray:
     """Reverse-mode gradient of a scalar loss with dL/dU_T = gU_T (and dL/dB_T
     = gB_T, default 0) with respect to THETA.  With per-step edge terms (a
-    wind series) the parameter chain is applied step by step."""
+    wind series) the parameter chain is applied step by step.
+
+    Every gradient term carries a factor B: of the source (qbar = Pbar B(u)
+    prod_{w != u}(1 - q B(w)), phibar = lambdabar B(u)) or of the target
+    (the p_continue term Bbar' B).  Where that factor is 0 the term is 0.  It
+    is evaluated so: far ahead of the fire (B = 0, U = 1) the adjoint state
+    grows by about p_c + sum_k q_k per step backward and can pass the fp64
+    range, and inf x 0 would otherwise make the sum NaN."""
+    with np.errstate(over="ignore", invalid="ignore"):
+        return _adjoint(env, theta, Us, Bs, terms, gU_T, gB_T, form)
+
+
+def _adjoint(env, theta, Us, Bs, terms, gU_T, gB_T, form):
     T = len(Us) - 1
     p_c = theta[5]
     per_step = isinstance(terms, list)
@@ -338,7 +350,8 @@ def adjoint(env: Env64, theta, Us, Bs, terms, gU_T, gB_T=None, form="product") -
             for k in range(8):
                 excl = pre[k] * suf[k + 1]
                 gB_new = gB_new + scatter_to_source(Pbar * q[k] * excl, k)
-                ybar = Pbar * Bsrc[k] * excl * (1.0 - q[k])   # qbar dq/dy, y = gamma phi
+                # qbar dq/dy, y = gamma phi; 0 where the source has no burning mass
+                ybar = np.where(Bsrc[k] == 0.0, 0.0, Pbar * Bsrc[k] * excl * (1.0 - q[k]))
                 phibar[k] += ybar * gamma
                 gamma_bar += ybar * phi_k[k]
         else:
@@ -349,11 +362,11 @@ def adjoint(env: Env64, theta, Us, Bs, terms, gU_T, gB_T=None, form="product") -
             nbar = gB - gU
             Pbar = nbar * U
             lbar = Pbar * gamma * (1.0 - P)               # dP/dlambda = gamma exp(-gamma lambda)
-            gamma_bar += Pbar * lam * (1.0 - P)
+            gamma_bar += np.where(lam == 0.0, 0.0, Pbar * lam * (1.0 - P))
             for k in range(8):
                 gB_new = gB_new + scatter_to_source(lbar * phi_k[k], k)
-                phibar[k] += lbar * Bsrc[k]
-        grad[5] += float(np.sum(gB * B))  # B' = newly + p_c B
+                phibar[k] += np.where(Bsrc[k] == 0.0, 0.0, lbar * Bsrc[k])
+        grad[5] += float(np.sum(np.where(B == 0.0, 0.0, gB * B)))  # B' = newly + p_c B
         if per_step:
             grad += _param_chain(env, theta, tt, phibar, gamma_bar)
         gU, gB = gU + nbar * P, gB_new

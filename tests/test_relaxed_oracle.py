@@ -255,3 +255,38 @@ def test_wind_series_adjoint(per_cell):
     scale = np.max(np.abs(fd))
     for i in range(theta.size):
         assert abs(grad[i] - fd[i]) <= 1e-6 * scale + 1e-6 * abs(fd[i]), (relaxed64.THETA_NAMES[i], grad[i], fd[i])
+
+
+@pytest.mark.parametrize("form", ["product", "exp"])
+def test_far_field_adjoint_overflow_keeps_the_light_cone_gradient(form):
+    """A 3 x 1000 strip burning from its west end with nearly saturated q:
+    ahead of the fire (B = 0, U = 1) the adjoint state grows by at least
+    p_c + sum_k q_k per step backward, past the fp64 range within 450 steps.
+    It only ever meets B = 0, so the gradient must stay finite and equal that
+    of the same strip cut at 460 columns, where no cell lies beyond the reach
+    of the burning mass (light cone: after T steps it has spread T columns)."""
+    T = 450
+    params = firegen.Params(p_base=8.0, alpha_gamma=1.0, alpha_w1=0.0, alpha_w2=0.0, alpha_s=0.0,
+                            p_continue=0.5)
+    theta = relaxed64.theta_from_params(params)
+    grads = []
+    for W in (1000, 460):
+        batch = firegen.uniform_batch(3, W, ignitions=[(0, 1, 0)])
+        env = relaxed64.from_batch(batch, 0, params.cell_size)
+        U0, B0, burnable = relaxed64.initial_state(batch, 0)
+        Us, Bs, terms = relaxed64.forward(env, theta, U0, B0, T, form)
+        Y = np.zeros((3, W), bool)
+        Y[:, :300] = True
+        L, gU = relaxed64.soft_iou_loss(Us[-1], Y, burnable)
+        if W == 1000:
+            # the regime: an interior cell of the middle row gains more than
+            # 10^(308/T) per step, so its adjoint passes 1e308 within T steps
+            gain = params.p_continue + sum(float(terms["q"][k][1, 700]) for k in range(8))
+            assert T * math.log10(gain) > 320
+            # nothing burns beyond column T
+            assert np.all(Bs[-1][:, T + 1:] == 0.0) and np.all(Us[-1][:, T + 1:] == 1.0)
+        grads.append((L, relaxed64.adjoint(env, theta, Us, Bs, terms, gU, form=form)))
+    (L_full, g_full), (L_cut, g_cut) = grads
+    assert np.all(np.isfinite(g_full))
+    assert abs(L_full - L_cut) <= 1e-12
+    assert np.allclose(g_full, g_cut, rtol=1e-9, atol=1e-12 * np.max(np.abs(g_cut)))
