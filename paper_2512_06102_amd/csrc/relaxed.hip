@@ -387,7 +387,14 @@ __device__ __forceinline__ bool adj_tile_in_reach(int i, int j, const TileGrid& 
 //           gammabar = sum_k ybar_k phi_k, c_k = Pbar q_k E_k;
 //   FORM 1: lambdabar = Pbar gamma (1 - P), phibar_k = lambdabar B_k,
 //           gammabar = Pbar lambda (1 - P), c_k = lambdabar phi_k;
-// d_k = phibar_k p_base exp(x_k) (dphi/dg of the source).  Four tiles (waves)
+// d_k = phibar_k p_base exp(x_k) (dphi/dg of the source).  Far ahead of the
+// fire (B = 0, U = 1) the adjoint state grows by about p_c + sum_k q_k per
+// step backward and can pass the fp64 range after a few hundred steps.  It
+// only ever meets B = 0 there: every gradient term it enters carries a factor
+// B of a source or of the target, so those terms are 0.  The kernel takes a
+// non-finite Pbar as 0 and adds the p_continue term only where B != 0, so the
+// overflow never turns into inf x 0 = NaN.
+// Four tiles (waves)
 // per workgroup, dealt to the XCDs in contiguous runs of the tile list.
 // SL: slope S = rise / run (0) or atan(rise / run) (1).
 template <bool WC, int FORM, int SL>
@@ -573,7 +580,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void r
         const float sVx[8] = {Lm.Vx, Lb.Vx, Xb.Vx, Rb.Vx, Rm.Vx, Ra.Vx, Xa.Vx, La.Vx};
         const float sVy[8] = {Lm.Vy, Lb.Vy, Xb.Vy, Rb.Vy, Rm.Vy, Ra.Vy, Xa.Vy, La.Vy};
         const double nbar = gB - gU;
-        const double Pbar = nbar * Uv;
+        // a non-finite Pbar comes only from an overflowed far-field adjoint
+        // (see above), whose terms all carry B = 0: they are 0, not inf x 0
+        const double Pbar = __builtin_isfinite(nbar * Uv) ? nbar * Uv : 0.0;
         const float gv = Xm.g, Ev = Xm.E;
         const float gam = A.alpha_gamma * gv, gpe = gp * gv;  // gamma(v), gamma(v) p_base
         const double gam64 = gam;
@@ -667,7 +676,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void r
         // gammabar = p_base gam_w; gamma(v) = alpha_gamma g(v)
         const double gam_bar = (double)A.p_base * gam_w;
         acc_gw += gam_w * (double)gv;
-        acc_pc += gB * Xm.B;
+        if (Xm.B != 0.0) acc_pc += gB * Xm.B;
         acc_m.d += gam_bar * (double)A.alpha_gamma;
         if (act) st_at(P.gU0, v, gU + nbar * Pv);
 

@@ -425,3 +425,22 @@ def test_gradient_across_adjoint_tiles_and_repeatable(per_cell_wind, form):
     grads = [sim.relaxed_bwd(p, gU, None, T, k, ws, form).cpu().numpy() for _ in range(3)]
     for g in grads:
         assert np.array_equal(g, g1)
+
+
+@pytest.mark.parametrize("form", ["product", "exp"])
+def test_far_field_adjoint_overflow(form):
+    """A 3 x 1000 strip burning from its west end with nearly saturated q,
+    T = 450: the adjoint state ahead of the fire passes the fp64 range but
+    meets only B = 0; the gradient is finite and within tolerance of the fp64
+    oracle (dense adjoint, every tile every step)."""
+    T, k = 450, 50
+    params = firegen.Params(p_base=8.0, alpha_gamma=1.0, alpha_w1=0.0, alpha_w2=0.0, alpha_s=0.0,
+                            p_continue=0.5)
+    batch = firegen.uniform_batch(3, 1000, ignitions=[(0, 1, 0)])
+    Y = np.zeros(3 * 1000, np.uint8)
+    Y.reshape(3, 1000)[:, :300] = 1
+    _, _, _, g, obj = _gpu_loss_grad(batch, params, Y, T, k, form)
+    L64, g64, _ = _oracle(batch, params, Y, T, form)
+    assert np.all(np.isfinite(g))
+    assert abs(obj - L64) <= 1e-5
+    _check_grad(g, g64)
