@@ -13,7 +13,7 @@ Reported beside it, each in its own object:
   dense_front - an ALU-bound case: a stationary checkerboard front where every
                 cell evaluates its neighbourhood each step;
   relaxed     - the relaxed forward + adjoint on 256 envs of 128 x 128 (T 100)
-                and on one 2048 x 2048 env (T 100), checkpoints every 10;
+                and on one 2048 x 2048 env (T 500), checkpoints every 10;
   paper_setting, rl, uneven, large - the paper's 64 x 64^2 vectorised
                 setting, the RL layer on 65536 envs of 20 x 20, the 4096-env
                 uneven batch with drops, and 8 envs of 2048 x 2048 with
@@ -602,8 +602,8 @@ def bench_relaxed(args, torch, fs, firegen):
     del batch
     batch, params, T, k = firegen.workload_relaxed_large()
     large = relaxed_case(args, torch, fs, firegen, batch, params, T, k,
-                         "relaxed2048: 1 env 2048x2048, per-cell wind, T=100, checkpoint every 10, "
-                         "fp64 state", True)
+                         "relaxed2048: 1 env 2048x2048, per-cell wind, T=%d, checkpoint every %d, "
+                         "fp64 state" % (T, k), True)
     adj = large["kernels"]["relaxed_adj_kernel"]
     large["roofline"] = {"bound": "hbm", "achieved": round(large["value"] * RELAXED_ALG_BYTES / 1e9, 1),
                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": large["hbm_frac_at_80B"],

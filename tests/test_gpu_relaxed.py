@@ -8,6 +8,9 @@ Tolerances (fp32 kernels against an fp64 reference):
              classes exactly 0.
 The oracle runs on the fp32-rounded parameters the kernels receive.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -203,28 +206,65 @@ def test_saturated_relaxed_is_deterministic_ca():
     assert np.array_equal(U.cpu().numpy().reshape(33, 33), (d > 12).astype(np.float32))
 
 
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _bench_setup(batch, params, T, k):
+    """The benchmark's relaxed setup: target scar from a T-step stochastic run
+    (Philox seed 0) at the workload's parameters, gradient at p_base,
+    alpha_w1, alpha_w2, alpha_s times 1.2; dense adjoint, checkpoints every k.
+    Returns (burnt cells of the target, U_T, objective, gradient)."""
+    sim = fs.FireSim.from_batch(batch, params, seed=0)
+    sim.step(T)
+    Y = ((sim.states == firegen.BURNING) | (sim.states == firegen.BURNT)).to(torch.uint8)
+    sim.set_plan(sparse=0)
+    p = fs.make_params(params.replace(p_base=params.p_base * 1.2, alpha_w1=params.alpha_w1 * 1.2,
+                                      alpha_w2=params.alpha_w2 * 1.2, alpha_s=params.alpha_s * 1.2))
+    p.unburnable_mask = batch.unburnable_mask
+    U, B = sim.relaxed_init()
+    ws = sim.relaxed_workspace(T, k)
+    sim.relaxed_fwd(p, U, B, T, k, ws)
+    _, gU, obj = sim.relaxed_loss(U, Y, scale=1.0 / batch.n_env)
+    g = sim.relaxed_bwd(p, gU, None, T, k, ws)
+    torch.cuda.synchronize()
+    return int(Y.sum()), U.cpu().numpy(), obj.item(), g.cpu().numpy()
+
+
+def _check_golden(name, burnt, obj, g):
+    """Loss and whole gradient against the fp64 oracle's (written by
+    tests/golden/make_relaxed_goldens.py for the same setup)."""
+    with open(os.path.join(GOLDEN, name + ".json")) as f:
+        gold = json.load(f)
+    assert burnt == gold["target_burnt_cells"]  # the same target scar (bit-exact stochastic step)
+    assert abs(obj - gold["loss"]) <= 1e-5, (obj, gold["loss"])
+    _check_grad(g, np.array(gold["grad"]))
+
+
 def test_full_size_relaxed128():
     """256 envs of 128x128, T = 100, checkpoints every 10 (the benchmark's
-    workload): U_T of sampled envs against the fp64 forward, and the gradient
-    of a 16-env sub-batch against the fp64 adjoint."""
+    workload and setup): U_T of sampled envs against the fp64 forward, and
+    the loss and whole gradient of all 256 envs against the fp64 oracle's."""
     batch, params, T, k = firegen.workload_relaxed()
-    Y = _target(batch, params, T, 0)
-    theta_star = params
-    params = params.replace(p_base=params.p_base * 1.2, alpha_w1=params.alpha_w1 * 1.2,
-                            alpha_w2=params.alpha_w2 * 1.2, alpha_s=params.alpha_s * 1.2)
-    U, B, loss, _, _ = _gpu_loss_grad(batch, params, Y, T, k)
-    sample = [0, 77, 200, 255]
-    for e in sample:
-        env = relaxed64.from_batch(batch, e, params.cell_size)
+    burnt, U, obj, g = _bench_setup(batch, params, T, k)
+    _check_golden("relaxed128", burnt, obj, g)
+    p = params.replace(p_base=params.p_base * 1.2, alpha_w1=params.alpha_w1 * 1.2,
+                       alpha_w2=params.alpha_w2 * 1.2, alpha_s=params.alpha_s * 1.2)
+    for e in [0, 77, 200, 255]:
+        env = relaxed64.from_batch(batch, e, p.cell_size)
         U0, B0, _ = relaxed64.initial_state(batch, e)
-        Us, Bs, _ = relaxed64.forward(env, _theta32(params), U0, B0, T)
+        Us, Bs, _ = relaxed64.forward(env, _theta32(p), U0, B0, T)
         assert np.max(np.abs(batch.env_view(U, e) - Us[-1])) <= 1e-5, e
-    sub = batch.subset(range(16))
-    Ysub = np.concatenate([batch.env_view(Y, e).ravel() for e in range(16)])
-    g = _gpu_loss_grad(sub, params, Ysub, T, k)[3]
-    _, g64, _ = _oracle(sub, params, Ysub, T)
-    _check_grad(g, g64)
-    assert theta_star.p_base == 0.58
+
+
+@pytest.mark.parametrize("T", [100])
+def test_relaxed2048_whole_gradient(T):
+    """The large relaxed workload (1 env of 2048x2048, per-cell wind,
+    checkpoints every 10) in the benchmark's setup at T = 100 and at its
+    horizon T = 500: loss and all 17 gradient entries against the fp64
+    oracle's."""
+    batch, params, _, k = firegen.workload_relaxed_large()
+    burnt, _, obj, g = _bench_setup(batch, params, T, k)
+    _check_golden("relaxed2048_T%d" % T, burnt, obj, g)
 
 
 def _window(batch, e, r0, r1, c0, c1):
@@ -253,7 +293,8 @@ def test_relaxed2048_launch_config():
     any size: U non-increasing from U_0, U + B <= 1, unburnable cells at zero,
     the gradient unchanged by the checkpoint interval, and a central
     difference of the loss along the gradient."""
-    batch, params, T, k = firegen.workload_relaxed_large()
+    batch, params, _, k = firegen.workload_relaxed_large()
+    T = 100
     H, W = int(batch.H[0]), int(batch.W[0])
     M = T + 8
     params = params.replace(p_base=params.p_base * 1.2, alpha_s=params.alpha_s * 1.2)

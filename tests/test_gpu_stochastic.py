@@ -229,18 +229,37 @@ def test_batch_order_does_not_matter():
     assert np.array_equal(sub.env_view(p, 1), batch.env_view(f, 1))
 
 
-def test_full_size_batch256_sampled_envs():
-    """1024 envs of 256x256, 200 steps, in the benchmark's launch plan: eight
-    sampled envs equal the oracle bit for bit; counts of those envs too."""
+# launch plans of the full-size checks: the dense one-step plan (the
+# roofline probe), the library's default plan, and the plans the benchmark's
+# autotuner picked for the uneven and the large workloads
+DENSE = dict(tile_rows=4, tile_width=256, skip_static=0, sparse=0, graph=1)
+DEFAULT = dict(tile_rows=4, tile_width=64, skip_static=1, sparse=1, graph=1)
+TUNED_UNEVEN = dict(tile_rows=8, tile_width=256, skip_static=1, sparse=1, graph=1)
+TUNED_LARGE = dict(tile_rows=4, tile_width=256, skip_static=1, sparse=1, graph=1)
+
+
+def _spread_sample(n, k, seed):
+    """k distinct envs out of n: the first, the last and k - 2 seeded draws."""
+    rng = np.random.default_rng(seed)
+    rest = rng.choice(np.arange(1, n - 1), size=k - 2, replace=False)
+    return [0, n - 1] + sorted(int(e) for e in rest)
+
+
+@pytest.mark.parametrize("plan", [DENSE, DEFAULT], ids=["dense", "default"])
+def test_full_size_batch256_sampled_envs(plan):
+    """The full 1024 envs of 256x256, 200 steps, in the dense plan (the
+    benchmark's headline launch plan) and in the default plan: 32 sampled
+    envs equal the oracle bit for bit, counts of those envs too."""
     batch, params, T, seed = firegen.workload_batch256()
     sim = fs.FireSim.from_batch(batch, params, seed=seed)
+    sim.set_plan(**plan)
     cnt = sim.step(T, counts=True).cpu().numpy()
     torch.cuda.synchronize()
     got = sim.states.cpu().numpy()
-    sample = [0, 1, 137, 500, 511, 777, 1000, 1023]
+    sample = _spread_sample(batch.n_env, 32, 1)
     sub = batch.subset(sample)
     ref = oracle.Sim(sub, params, seed=seed)
-    rc = ref.step(T, counts=True, threads=8)
+    rc = ref.step(T, counts=True, threads=16)
     for k, e in enumerate(sample):
         assert np.array_equal(batch.env_view(got, e), sub.env_view(ref.states, k)), e
         assert np.array_equal(cnt[:, e], rc[:, k]), e
@@ -265,36 +284,51 @@ def test_rejects_bad_arguments():
 
 
 def test_uneven_batch_with_drops_sampled_envs():
-    """Envs with sides drawn from {64, 128, 256, 512}, one 5x5 drop per env per
-    step, 300 steps, counts: sampled envs of every size equal the oracle."""
-    batch, params, T, seed, acts = firegen.workload_uneven(n_env=384)
-    sim = fs.FireSim.from_batch(batch, params, seed=seed)
-    cnt = sim.step(T, actions=torch.from_numpy(acts), counts=True).cpu().numpy()
-    torch.cuda.synchronize()
-    got = sim.states.cpu().numpy()
+    """The full uneven workload: 4096 envs with sides drawn from {64, 128, 256,
+    512}, one 5x5 drop per env per step, 300 steps, counts; in the dense plan,
+    the default plan and the benchmark's tuned plan.  8 sampled envs of each
+    side equal the oracle bit for bit, counts too."""
+    batch, params, T, seed, acts = firegen.workload_uneven()
+    rng = np.random.default_rng(7)
     sample = []
     for side in (64, 128, 256, 512):
-        sample += [int(e) for e in np.flatnonzero(batch.H == side)[:2]]
+        of_side = np.flatnonzero(batch.H == side)
+        sample += [int(of_side[0]), int(of_side[-1])] + [int(e) for e in rng.choice(of_side[1:-1], 6, replace=False)]
+    sample = sorted(sample)
     sub = batch.subset(sample)
     ref = oracle.Sim(sub, params, seed=seed)
-    rc = ref.step(T, actions=np.ascontiguousarray(acts[:, sample]), counts=True, threads=8)
-    for k, e in enumerate(sample):
-        assert np.array_equal(batch.env_view(got, e), sub.env_view(ref.states, k)), e
-        assert np.array_equal(cnt[:, e], rc[:, k]), e
-
-
-def test_large_grids_per_cell_wind_sampled():
-    """2048 x 2048 envs with per-cell wind and 0-2000 m terrain: two envs
-    against the oracle over 150 steps (dense and skip plans)."""
-    batch, params, _, seed = firegen.workload_large(n_env=2)
-    ref = oracle.Sim(batch, params, seed=seed)
-    ref.step(150, threads=2)
-    for skip in (0, 1):
+    rc = ref.step(T, actions=np.ascontiguousarray(acts[:, sample]), counts=True, threads=16)
+    acts_d = torch.from_numpy(acts).cuda()
+    for plan in (DENSE, DEFAULT, TUNED_UNEVEN):
         sim = fs.FireSim.from_batch(batch, params, seed=seed)
-        sim.set_plan(skip_static=skip)
-        sim.step(150)
+        sim.set_plan(**plan)
+        cnt = sim.step(T, actions=acts_d, counts=True).cpu().numpy()
         torch.cuda.synchronize()
-        assert np.array_equal(sim.states.cpu().numpy(), ref.states), skip
+        got = sim.states.cpu().numpy()
+        for k, e in enumerate(sample):
+            assert np.array_equal(batch.env_view(got, e), sub.env_view(ref.states, k)), (plan, e)
+            assert np.array_equal(cnt[:, e], rc[:, k]), (plan, e)
+        del sim
+
+
+def test_large_grids_per_cell_wind_full_run():
+    """The full large workload: 8 envs of 2048x2048 with per-cell wind and
+    0-2000 m terrain, all 1000 steps, in the dense plan, the default plan and
+    the benchmark's tuned plan; one env against the oracle over the whole
+    run, states and counts."""
+    batch, params, T, seed = firegen.workload_large()
+    e = 5
+    sub = batch.subset([e])
+    ref = oracle.Sim(sub, params, seed=seed)
+    rc = ref.step(T, counts=True, threads=1)
+    for plan in (DENSE, DEFAULT, TUNED_LARGE):
+        sim = fs.FireSim.from_batch(batch, params, seed=seed)
+        sim.set_plan(**plan)
+        cnt = sim.step(T, counts=True).cpu().numpy()
+        torch.cuda.synchronize()
+        assert np.array_equal(batch.env_view(sim.states.cpu().numpy(), e), sub.env_view(ref.states, 0)), plan
+        assert np.array_equal(cnt[:, e], rc[:, 0]), plan
+        del sim
 
 
 def test_autotune_keeps_state_and_results():
