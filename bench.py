@@ -279,7 +279,7 @@ def bench_variants(args, torch, fs, st):
     sim.t = 0
     tuned = sim.autotune(T_probe=T, allow_skip=True, allow_sparse=True)
     best = sim.plan()
-    keys = ("tile_rows", "tile_width", "temporal", "skip_static", "sparse")
+    keys = ("tile_rows", "tile_width", "temporal", "skip_static", "sparse", "resident")
     sim.set_plan(**{k: best[k] for k in keys}, graph=1)
     ms, launch_ms = timed_runs(torch, stream, sim, init, T, args.steps, 1)
     out["autotuned"] = {"plan": {k: best[k] for k in keys},
@@ -364,7 +364,7 @@ def bench_paper_config(args, torch, fs, firegen):
     sim.t = 0
     sim.autotune(T_probe=T, allow_skip=True, allow_sparse=True)
     best = sim.plan()
-    keys = ("tile_rows", "tile_width", "temporal", "skip_static", "sparse")
+    keys = ("tile_rows", "tile_width", "temporal", "skip_static", "sparse", "resident")
     sim.set_plan(**{k: best[k] for k in keys}, graph=1)
     ms, _ = timed_runs(torch, stream, sim, init, T, args.steps, 2)
     out["autotuned"] = {"plan": {k: best[k] for k in keys}, "ms_per_200_steps": round(ms, 4),
@@ -410,7 +410,7 @@ def bench_uneven(args, torch, fs, firegen):
     sim.t = 0
     sim.autotune(T_probe=50, allow_skip=True, allow_sparse=True)
     best = sim.plan()
-    keys = ("tile_rows", "tile_width", "temporal", "skip_static", "sparse")
+    keys = ("tile_rows", "tile_width", "temporal", "skip_static", "sparse", "resident")
     sim.set_plan(**{k: best[k] for k in keys}, graph=1)
     run(1)
     torch.cuda.synchronize()
@@ -493,7 +493,7 @@ def bench_large(args, torch, fs, firegen):
     sim.t = 0
     sim.autotune(T_probe=50, allow_skip=True, allow_sparse=True)
     best = sim.plan()
-    keys = ("tile_rows", "tile_width", "temporal", "skip_static", "sparse")
+    keys = ("tile_rows", "tile_width", "temporal", "skip_static", "sparse", "resident")
     sim.set_plan(**{k: best[k] for k in keys}, graph=1)
     run()
     torch.cuda.synchronize()

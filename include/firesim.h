@@ -254,9 +254,9 @@ int sim_set_step(sim_handle* h, uint64_t t);
 /* Launch plan of sim_step, and of sim_step_relaxed_bwd for `sparse` (results
  * never depend on it, up to the summation order of the relaxed gradient).
  * A new handle starts with {tile_rows 4, tile_width 64, temporal 1,
- * skip_static 1, sparse 1, graph 0}: fuel and elevation are read only at
+ * skip_static 1, sparse 1, graph 0, resident 0}: fuel and elevation are read only at
  * front cells and tiles with no fire in reach are skipped.  The dense plan
- * {4, 256, 1, 0, 0, 0} streams every cell's state, fuel and elevation each
+ * {4, 256, 1, 0, 0, 0, 0} streams every cell's state, fuel and elevation each
  * step (the HBM roofline reference).
  *  tile_rows    rows of 4-cell groups each lane owns in its tile (1, 2, 4 or 8),
  *               0 = default (4)
@@ -282,9 +282,21 @@ int sim_set_step(sim_handle* h, uint64_t t);
  *               it only sums terms carrying B_s, which is zero there.
  *  graph        1: capture the T launches of a call into a HIP graph and
  *               replay it (re-captured when T, the pointers or the plan
- *               change); 0: launch directly */
+ *               change); 0: launch directly
+ *  resident     0: off; 256, 512 or 1024: sim_step runs all T steps of a
+ *               call in ONE launch, one workgroup of that many lanes per env
+ *               holding the env's state in LDS for the whole call (fuel,
+ *               elevation and wind read at front cells only), with results
+ *               bit-identical to the other plans.  For batches of small envs:
+ *               needs W % 4 == 0 and offset % 4 == 0 in every env, at most
+ *               65536 cells and (H + 2)(W/4 + 2) 8 + 9 H W <= 65536 bytes per
+ *               env (a 64 x 64 env takes 46368), and temporal 1 (else
+ *               SIM_EINVAL); tile_rows, tile_width and skip_static are then
+ *               unused by the stochastic step (sparse still applies to
+ *               sim_step_relaxed_bwd).  sim_step_history runs it one step per
+ *               launch. */
 typedef struct {
-    int32_t tile_rows, tile_width, temporal, skip_static, sparse, graph;
+    int32_t tile_rows, tile_width, temporal, skip_static, sparse, graph, resident;
 } sim_plan;
 int sim_set_plan(sim_handle* h, const sim_plan* plan);
 int sim_get_plan(const sim_handle* h, sim_plan* plan);
@@ -292,7 +304,8 @@ int sim_get_plan(const sim_handle* h, sim_plan* plan);
 /* Autotuner: times every candidate plan (tile_rows 1/2/4/8 x tile_width
  * 64/256, with skip_static 0 and, if allow_skip, 1; sparse = allow_sparse;
  * and, if allow_skip and every env has W % 4 == 0, temporal 2/4/8 x
- * tile_width 64/128)
+ * tile_width 64/128; and, if allow_skip and the batch fits it, resident
+ * 256/512/1024)
  * for T_probe steps of this batch starting from `states` (device, read only)
  * at the handle's step counter, and makes the fastest the handle's plan
  * (graph flag kept).

@@ -62,7 +62,7 @@ class SimEnv(ctypes.Structure):
 class SimPlan(ctypes.Structure):
     _fields_ = [("tile_rows", ctypes.c_int32), ("tile_width", ctypes.c_int32),
                 ("temporal", ctypes.c_int32), ("skip_static", ctypes.c_int32),
-                ("sparse", ctypes.c_int32), ("graph", ctypes.c_int32)]
+                ("sparse", ctypes.c_int32), ("graph", ctypes.c_int32), ("resident", ctypes.c_int32)]
 
 
 class SimTuneResult(ctypes.Structure):
@@ -324,8 +324,8 @@ class FireSim:
     def t(self, value: int):
         _check(lib().sim_set_step(self.handle, int(value)), self.handle)
 
-    def set_plan(self, tile_rows=0, tile_width=0, temporal=0, skip_static=0, sparse=0, graph=0):
-        p = SimPlan(tile_rows, tile_width, temporal, skip_static, sparse, graph)
+    def set_plan(self, tile_rows=0, tile_width=0, temporal=0, skip_static=0, sparse=0, graph=0, resident=0):
+        p = SimPlan(tile_rows, tile_width, temporal, skip_static, sparse, graph, resident)
         _check(lib().sim_set_plan(self.handle, ctypes.byref(p)), self.handle)
 
     def plan(self) -> dict:
@@ -333,7 +333,7 @@ class FireSim:
         _check(lib().sim_get_plan(self.handle, ctypes.byref(p)), self.handle)
         return {"tile_rows": p.tile_rows, "tile_width": p.tile_width, "temporal": p.temporal,
                 "sparse": p.sparse,
-                "skip_static": p.skip_static, "graph": p.graph}
+                "skip_static": p.skip_static, "graph": p.graph, "resident": p.resident}
 
     def autotune(self, T_probe: int = 10, allow_skip: bool = True, allow_sparse: bool = False) -> list:
         """Time every candidate plan on this batch (states and step counter
@@ -346,7 +346,8 @@ class FireSim:
         for i in range(n.value):
             p = res[i].plan
             out.append(({"tile_rows": p.tile_rows, "tile_width": p.tile_width,
-                         "skip_static": p.skip_static, "sparse": p.sparse, "temporal": p.temporal},
+                         "skip_static": p.skip_static, "sparse": p.sparse, "temporal": p.temporal,
+                         "resident": p.resident},
                         float(res[i].ms_per_step)))
         return out
 

@@ -18,6 +18,7 @@
 #include "rl.hpp"
 #include "internal.hpp"
 #include "relaxed.hpp"
+#include "resident.hpp"
 
 using namespace firesim;
 
@@ -76,7 +77,7 @@ struct sim_handle {
     // default launch plan: fuel and elevation read only at front cells, and
     // tiles with no fire in reach skipped (the dense plan, which streams every
     // cell's 10 bytes each step, is {4, 256, 1, 0, 0, 0})
-    sim_plan plan{4, 64, 1, 1, 1, 0};
+    sim_plan plan{4, 64, 1, 1, 1, 0, 0};
     // wind series (caller-owned device memory, indexed by the absolute step)
     const float* series_env = nullptr;   // [series_T][n_env][3]
     const float* series_cell = nullptr;  // [series_T][3][n_cells]
@@ -88,6 +89,7 @@ struct sim_handle {
     int32_t* d_rl_drop = nullptr;
     int32_t* d_rl_counts = nullptr;
     RlFusedShape rl_shape;  // the fused RL step's LDS layout (fits: every env fits it)
+    ResidentShape res_shape;  // the resident multi-step kernel's LDS layout
 
     EnvDev* d_envs = nullptr;
     int32_t* d_chunk_env = nullptr;    // env of every loss chunk (kLossChunk cells)
@@ -305,6 +307,22 @@ hipError_t enqueue_steps(sim_handle* h, hipStream_t s, uint8_t* states, const in
     }
     uint8_t* cur = states;
     uint8_t* nxt = history ? history : h->d_tmp;
+    if (h->plan.resident) {
+        // all T steps in one launch, in place (one launch per step with a history)
+        if (!history)
+            return launch_stoch_resident(s, h->d_envs, h->n_env, L.fields, L.args, h->res_shape,
+                                         h->plan.resident, states, states, h->d_t, 0u, T, actions, counts);
+        for (int32_t k = 0; k < T; ++k) {
+            e = launch_stoch_resident(s, h->d_envs, h->n_env, L.fields, L.args, h->res_shape, h->plan.resident,
+                                      cur, nxt, h->d_t, (uint32_t)k, 1,
+                                      actions ? actions + (int64_t)k * h->n_env : nullptr,
+                                      counts ? counts + (int64_t)k * h->n_env : nullptr);
+            if (e != hipSuccess) return e;
+            cur = nxt;
+            nxt = history + (int64_t)(k + 1) * h->n_cells;
+        }
+        return launch_copy_u8(s, states, cur, h->n_cells);
+    }
     if (h->plan.temporal > 1) {
         // temporal blocking: K steps per launch (one per launch with a history)
         const int K = h->plan.temporal;
@@ -352,7 +370,8 @@ hipError_t enqueue_steps(sim_handle* h, hipStream_t s, uint8_t* states, const in
 bool same_plan(const sim_plan& a, const sim_plan& b)
 {
     return a.tile_rows == b.tile_rows && a.tile_width == b.tile_width && a.temporal == b.temporal &&
-           a.skip_static == b.skip_static && a.sparse == b.sparse && a.graph == b.graph;
+           a.skip_static == b.skip_static && a.sparse == b.sparse && a.graph == b.graph &&
+           a.resident == b.resident;
 }
 
 int validate_plan(sim_handle* h, sim_plan& p)
@@ -375,6 +394,16 @@ int validate_plan(sim_handle* h, sim_plan& p)
     if (p.skip_static != 0 && p.skip_static != 1) return fail(h, SIM_EINVAL, "skip_static must be 0 or 1");
     if (p.sparse != 0 && p.sparse != 1) return fail(h, SIM_EINVAL, "sparse must be 0 or 1");
     if (p.graph != 0 && p.graph != 1) return fail(h, SIM_EINVAL, "graph must be 0 or 1");
+    if (p.resident != 0) {
+        if (!(p.resident == 256 || p.resident == 512 || p.resident == 1024))
+            return fail(h, SIM_EINVAL, "resident must be 0, 256, 512 or 1024");
+        if (p.temporal > 1) return fail(h, SIM_EINVAL, "resident and temporal blocking do not combine");
+        if (!h->res_shape.fits)
+            return fail(h, SIM_EINVAL,
+                        "resident plan needs W %% 4 == 0 and 4-aligned offsets in every env, at most 65536 "
+                        "cells and (H + 2)(W/4 + 2) 8 + 9 H W <= %d bytes per env",
+                        (int)kResidentMaxLds);
+    }
     return SIM_OK;
 }
 
@@ -463,6 +492,12 @@ int sim_init(sim_handle** out, const sim_params* p, int32_t n_env, const sim_env
             rs.frame_cap = (int32_t)((max_frame + 3) & ~3);
             rs.cell_cap = (int32_t)max_cells;
             rs.fits = rl_fused_lds_bytes(rs) <= kRlFusedMaxLds;
+        }
+        ResidentShape& ts = h->res_shape;
+        if (max_cells <= 65536 && max_frame <= (int64_t)kResidentMaxLds) {
+            ts.frame_cap = (int32_t)((max_frame + 3) & ~3);
+            ts.cell_cap = (int32_t)max_cells;
+            ts.fits = resident_lds_bytes(ts) <= kResidentMaxLds;
         }
     }
 
@@ -765,10 +800,13 @@ int sim_autotune(sim_handle* h, const uint8_t* states, int32_t T_probe, int32_t 
     std::vector<sim_plan> cands;
     for (int skip = 0; skip <= (allow_skip ? 1 : 0); ++skip)
         for (int width : {64, 256})
-            for (int rows : {1, 2, 4, 8}) cands.push_back(sim_plan{rows, width, 1, skip, allow_sparse ? 1 : 0, 0});
+            for (int rows : {1, 2, 4, 8})
+                cands.push_back(sim_plan{rows, width, 1, skip, allow_sparse ? 1 : 0, 0, 0});
     if (allow_skip && h->aligned)  // temporal blocking reads fuel and elevation only at fronts, like skip
         for (int width : {64, 128})
-            for (int k : {2, 4, 8}) cands.push_back(sim_plan{4, width, k, 1, 0, 0});
+            for (int k : {2, 4, 8}) cands.push_back(sim_plan{4, width, k, 1, 0, 0, 0});
+    if (allow_skip && h->res_shape.fits)  // so does the resident kernel
+        for (int nt : {256, 512, 1024}) cands.push_back(sim_plan{4, 64, 1, 1, allow_sparse ? 1 : 0, 0, nt});
     for (const sim_plan& cand : cands) {
         {
                 if (rc != SIM_OK) break;

@@ -14,6 +14,7 @@
 //                   window of the new state around each agent.
 // rl_reset_kernel redraws the fire and the agent of selected envs.
 #include "devmath.hpp"
+#include "framed.hpp"
 #include "internal.hpp"
 #include "rl.hpp"
 #include "stepcell.hpp"
@@ -130,24 +131,6 @@ __global__ __launch_bounds__(256) void rl_obs_kernel(const EnvDev* __restrict__ 
         o[i] = (gi >= 0 && gi < ed.H && gj >= 0 && gj < ed.W) ? states[ed.offset + (int64_t)gi * ed.W + gj]
                                                               : kOutside;
     }
-}
-
-// q / d by one fp32 multiply, inv_d = fl(1 / d): the rounding error of
-// (q + 1/2) inv_d stays below the 1/(2d) distance of (q + 1/2)/d from an
-// integer.  Exact for 0 <= q < 2^14 and 1 <= d <= 2^14 (checked over every
-// pair); here q is a dword index (an env has at most 2^16 cells) or an
-// observation index (side at most 63).
-__device__ __forceinline__ int small_div(int q, int d, float inv_d) { return (int)(((float)q + 0.5f) * inv_d); }
-
-// Cells of the 4-cell group at framed position m (row stride SW) with a
-// burning Moore neighbour, bits 0-3.
-__device__ __forceinline__ uint32_t near_burning(const uint32_t* m, int SW)
-{
-    const uint32_t up6 = row_window(m[-SW - 1], m[-SW], m[-SW + 1]);
-    const uint32_t md6 = row_window(m[-1], m[0], m[1]);
-    const uint32_t dn6 = row_window(m[SW - 1], m[SW], m[SW + 1]);
-    const uint32_t ud = up6 | dn6;
-    return (ud | (ud >> 1) | (ud >> 2) | md6 | (md6 >> 2)) & 0xFu;
 }
 
 // One whole RL step of one env per 64-lane workgroup, the env's state
