@@ -283,15 +283,16 @@ int sim_set_step(sim_handle* h, uint64_t t);
  *  graph        1: capture the T launches of a call into a HIP graph and
  *               replay it (re-captured when T, the pointers or the plan
  *               change); 0: launch directly
- *  resident     0: off; 256, 512 or 1024: sim_step runs all T steps of a
- *               call in ONE launch, one workgroup of that many lanes per env
- *               holding the env's state in LDS for the whole call (fuel,
- *               elevation and wind read at front cells only), with results
- *               bit-identical to the other plans.  For batches of small envs:
- *               needs W % 4 == 0 and offset % 4 == 0 in every env, at most
- *               65536 cells and (H + 2)(W/4 + 2) 8 + 9 H W <= 65536 bytes per
- *               env (a 64 x 64 env takes 46368), and temporal 1 (else
- *               SIM_EINVAL); tile_rows, tile_width and skip_static are then
+ *  resident     0: off; 64, 256, 512 or 1024: sim_step runs all T steps
+ *               of a call in ONE launch, one workgroup of that many lanes per
+ *               env holding the env's state, fuel and elevation in LDS for
+ *               the whole call (per-cell wind read from HBM at front cells),
+ *               with results bit-identical to the other plans.  For batches
+ *               of small envs: needs W % 4 == 0 and offset % 4 == 0 in every
+ *               env, at most 65536 cells and (H + 2)(W/4 + 2) 8 + 16 H W
+ *               bytes of LDS per env within the device's LDS per workgroup
+ *               less 2.5 KiB (160 KiB on MI355X: up to 92 x 92; a 64 x 64
+ *               env takes 75040), and temporal 1 (else SIM_EINVAL); tile_rows, tile_width and skip_static are then
  *               unused by the stochastic step (sparse still applies to
  *               sim_step_relaxed_bwd).  sim_step_history runs it one step per
  *               launch. */
@@ -305,7 +306,7 @@ int sim_get_plan(const sim_handle* h, sim_plan* plan);
  * 64/256, with skip_static 0 and, if allow_skip, 1; sparse = allow_sparse;
  * and, if allow_skip and every env has W % 4 == 0, temporal 2/4/8 x
  * tile_width 64/128; and, if allow_skip and the batch fits it, resident
- * 256/512/1024)
+ * 64/256/512/1024)
  * for T_probe steps of this batch starting from `states` (device, read only)
  * at the handle's step counter, and makes the fastest the handle's plan
  * (graph flag kept).

@@ -395,14 +395,14 @@ int validate_plan(sim_handle* h, sim_plan& p)
     if (p.sparse != 0 && p.sparse != 1) return fail(h, SIM_EINVAL, "sparse must be 0 or 1");
     if (p.graph != 0 && p.graph != 1) return fail(h, SIM_EINVAL, "graph must be 0 or 1");
     if (p.resident != 0) {
-        if (!(p.resident == 256 || p.resident == 512 || p.resident == 1024))
-            return fail(h, SIM_EINVAL, "resident must be 0, 256, 512 or 1024");
+        if (!(p.resident == 64 || p.resident == 256 || p.resident == 512 || p.resident == 1024))
+            return fail(h, SIM_EINVAL, "resident must be 0, 64, 256, 512 or 1024");
         if (p.temporal > 1) return fail(h, SIM_EINVAL, "resident and temporal blocking do not combine");
         if (!h->res_shape.fits)
             return fail(h, SIM_EINVAL,
                         "resident plan needs W %% 4 == 0 and 4-aligned offsets in every env, at most 65536 "
-                        "cells and (H + 2)(W/4 + 2) 8 + 9 H W <= %d bytes per env",
-                        (int)kResidentMaxLds);
+                        "cells and (H + 2)(W/4 + 2) 8 + 16 H W bytes of LDS per env within the device's "
+                        "LDS per workgroup less 2.5 KiB");
     }
     return SIM_OK;
 }
@@ -494,10 +494,19 @@ int sim_init(sim_handle** out, const sim_params* p, int32_t n_env, const sim_env
             rs.fits = rl_fused_lds_bytes(rs) <= kRlFusedMaxLds;
         }
         ResidentShape& ts = h->res_shape;
-        if (max_cells <= 65536 && max_frame <= (int64_t)kResidentMaxLds) {
+        int max_lds = 0;
+        if (max_cells <= 65536 &&
+            hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device) == hipSuccess &&
+            max_frame <= max_lds) {
             ts.frame_cap = (int32_t)((max_frame + 3) & ~3);
             ts.cell_cap = (int32_t)max_cells;
-            ts.fits = resident_lds_bytes(ts) <= kResidentMaxLds;
+            // the kernel's own static LDS (under 2.5 KiB) comes on top of the dynamic part
+            const size_t need = resident_lds_bytes(ts);
+            ts.fits = need + 2560 <= (size_t)max_lds;
+            if (ts.fits && resident_set_lds_limit((int)need) != hipSuccess) {
+                (void)hipGetLastError();  // not sticky: the batch just does not take the plan
+                ts.fits = false;
+            }
         }
     }
 
@@ -806,7 +815,7 @@ int sim_autotune(sim_handle* h, const uint8_t* states, int32_t T_probe, int32_t 
         for (int width : {64, 128})
             for (int k : {2, 4, 8}) cands.push_back(sim_plan{4, width, k, 1, 0, 0, 0});
     if (allow_skip && h->res_shape.fits)  // so does the resident kernel
-        for (int nt : {256, 512, 1024}) cands.push_back(sim_plan{4, 64, 1, 1, allow_sparse ? 1 : 0, 0, nt});
+        for (int nt : {64, 256, 512, 1024}) cands.push_back(sim_plan{4, 64, 1, 1, allow_sparse ? 1 : 0, 0, nt});
     for (const sim_plan& cand : cands) {
         {
                 if (rc != SIM_OK) break;

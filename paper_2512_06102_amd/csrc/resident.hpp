@@ -12,23 +12,25 @@ namespace firesim {
 // Shape of the resident kernel over a batch whose envs all have W % 4 == 0
 // and 4-aligned offsets: the largest framed state, (H + 2)(W/4 + 2) dwords
 // rounded up to a multiple of 4, and the largest env in cells (at most
-// 65536).  It fits when its dynamic LDS is at most kResidentMaxLds.
+// 65536).  It fits when its dynamic LDS is at most the device's LDS per
+// workgroup (160 KiB on gfx950) less the kernel's static LDS (under 2.5 KiB).
 struct ResidentShape {
     bool fits = false;
     int32_t frame_cap = 0;
     int32_t cell_cap = 0;
 };
-constexpr size_t kResidentMaxLds = 64 * 1024;
-// Two framed states, one uniform, one list entry and one decision byte per cell.
+// Two framed states; fuel term, elevation and an 8-byte front-list entry per cell.
 inline size_t resident_lds_bytes(const ResidentShape& s)
 {
-    return 4 * (2 * (size_t)s.frame_cap + 2 * (size_t)s.cell_cap) + (size_t)s.cell_cap;
+    return 8 * (size_t)s.frame_cap + 16 * (size_t)s.cell_cap;
 }
+// Allows every instance of the kernel `bytes` of dynamic LDS.
+hipError_t resident_set_lds_limit(int bytes);
 
 // T steps of every env from src to dst (which may be the same buffer), the
 // first at the absolute step *t_base + step0 (t_base in device memory, so a
 // captured launch serves any starting step), by workgroups of `threads`
-// lanes (256, 512 or 1024); actions and counts point at the rows of the
+// lanes (64, 256, 512 or 1024); actions and counts point at the rows of the
 // first step (n_env entries per step) or are NULL.
 hipError_t launch_stoch_resident(hipStream_t s, const EnvDev* envs, int32_t n_env, const StaticFields& F,
                                  const StepArgs& A, const ResidentShape& shape, int threads, const uint8_t* src,

@@ -14,7 +14,7 @@ pytestmark = pytest.mark.gpu
 
 fs = pytest.importorskip("paper_2512_06102_amd")
 
-THREADS = [256, 512, 1024]
+THREADS = [64, 256, 512, 1024]
 
 
 def _veg(seed):
@@ -66,12 +66,13 @@ def test_many_20x20_envs_with_drops(threads):
     _check(sim, ref, got, want, threads)
 
 
-MIXED = [(64, 64), (20, 20), (8, 8), (36, 52), (4, 4), (76, 76), (12, 100), (1, 4), (5, 8)]
+MIXED = [(64, 64), (20, 20), (8, 8), (36, 52), (4, 4), (92, 92), (12, 100), (1, 4), (5, 8)]
 
 
 @pytest.mark.parametrize("threads", THREADS)
 def test_mixed_small_envs_edges_and_corners(threads):
-    """Envs from 1 x 4 up to the largest that fits (76 x 76), drops at the
+    """Envs from 1 x 4 up to the largest square that fits in 160 KiB of LDS
+    (92 x 92), drops at the
     corners and centres outside the grid, a steep spread probability."""
     batch = firegen.landscape_batch(63, MIXED)
     params = firegen.Params(p_base=0.95, veg=_veg(63))
@@ -153,7 +154,7 @@ def test_static_per_cell_wind_and_slope_angle():
 def test_rejections():
     """Batches the kernel cannot hold and bad plan values raise SimError; the
     handle keeps its previous plan."""
-    for sizes in ([(128, 128)], [(64, 64), (40, 42)], [(1, 30000)]):
+    for sizes in ([(128, 128)], [(96, 96)], [(64, 64), (40, 42)], [(1, 30000)]):
         sim = fs.FireSim.from_batch(firegen.landscape_batch(67, sizes), firegen.Params(), seed=0)
         with pytest.raises(fs.SimError):
             sim.set_plan(resident=256)
