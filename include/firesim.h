@@ -323,6 +323,62 @@ int sim_autotune(sim_handle* h, const uint8_t* states, int32_t T_probe, int32_t 
                  int32_t allow_sparse, sim_tune_result* results, int32_t max_results,
                  int32_t* n_results, void* stream);
 
+/* ----------------------------------------------------------- size classes */
+/* Per-size-class plans.  An env's size class is set by its larger side:
+ * class c holds the envs with 2^(c+4) < max(H, W) <= 2^(c+5), class 0 also
+ * the smaller ones and class SIM_N_SIZE_CLASSES - 1 the larger ones (so
+ * 0: <= 32, 1: <= 64, 2: <= 128, 3: <= 256, 4: <= 512, 5: <= 1024,
+ * 6: <= 2048, 7: above).  With class plans set, sim_step, sim_step_history
+ * and the multi-launch path of sim_rl_step run the envs of each class with
+ * that class's plan, class after class on the caller's stream (the results
+ * stay bit-identical: envs never interact).  The handle-wide graph flag
+ * still applies (the launches of all classes form one graph), and the
+ * handle-wide plan's sparse flag still drives sim_step_relaxed_bwd.
+ * sim_set_plan and sim_autotune drop the class plans (one plan for all envs
+ * again). */
+#define SIM_N_SIZE_CLASSES 8
+typedef struct {
+    int32_t size_class;  /* 0 .. SIM_N_SIZE_CLASSES - 1 */
+    int32_t n_env;       /* envs of the batch in the class */
+    int64_t n_cells;     /* their cells */
+    sim_plan plan;       /* the class's plan (its graph field is not used) */
+    float ms_per_step;   /* the autotuner's time for the class alone; 0 if not timed */
+    int32_t from_cache;  /* 1: sim_autotune_classes took the plan from its cache */
+} sim_class_plan;
+
+/* Set the plan of one size class.  The first call splits the batch into its
+ * classes, each starting from the handle-wide plan.  SIM_EINVAL if the batch
+ * has no env in the class or the plan does not suit its envs (as
+ * sim_set_plan, judged on the class's envs alone: a class of small envs can
+ * take a resident plan that the whole batch cannot). */
+int sim_set_class_plan(sim_handle* h, int32_t size_class, const sim_plan* plan);
+
+/* The size classes present in the batch, in ascending order, with their
+ * plans (the handle-wide plan for each when no class plans are set).
+ *  out      host array of max_out entries (may be NULL if max_out is 0)
+ *  n_out    receives the number of classes present */
+int sim_get_class_plans(const sim_handle* h, sim_class_plan* out, int32_t max_out, int32_t* n_out);
+
+/* Per-size-class autotuner: for each class, times the candidates of
+ * sim_autotune (with the class's own fit for temporal and resident plans)
+ * on the class's envs alone for T_probe steps from `states` at the handle's
+ * step counter, and gives the class its fastest plan.  Neither `states` nor
+ * the step counter change; synchronises `stream`.
+ *  cache_path  a text file of tuned plans, or NULL for none.  Each line
+ *              holds a key -- the GPU architecture, the class, its env
+ *              count, cells and largest H and W, whether all its envs have
+ *              W % 4 == 0 and 4-aligned offsets, the wind kind (per env,
+ *              per cell, per-env series, per-cell series), T_probe,
+ *              allow_skip and allow_sparse -- and a plan.  A class whose key
+ *              is in the file (the last such line wins) takes its plan
+ *              without timing; each class timed is appended as one line.
+ *              SIM_EINVAL if the file exists but cannot be read, or cannot
+ *              be appended to; a malformed line is ignored.
+ *  out, max_out, n_out  as in sim_get_class_plans */
+int sim_autotune_classes(sim_handle* h, const uint8_t* states, int32_t T_probe, int32_t allow_skip,
+                         int32_t allow_sparse, const char* cache_path, sim_class_plan* out,
+                         int32_t max_out, int32_t* n_out, void* stream);
+
 /* ---------------------------------------------------------------- relaxed */
 /* The relaxed (mean-field) state: per cell U = P(unburned), B = P(burning)
  * (the paper's p_un and p_burn; p_bd = 1 - U - B is not carried).  One step:

@@ -38,7 +38,8 @@ THETA_NAMES = ("p_base", "alpha_w1", "alpha_w2", "alpha_s", "alpha_gamma", "p_co
     tuple("veg%d" % c for c in range(N_CLASSES))
 
 EXPORTED = ("sim_init", "sim_step", "sim_get_step", "sim_set_step", "sim_set_plan", "sim_get_plan",
-            "sim_autotune", "sim_set_wind_series", "sim_step_history", "sim_set_drop",
+            "sim_autotune", "sim_set_class_plan", "sim_get_class_plans", "sim_autotune_classes",
+            "sim_set_wind_series", "sim_step_history", "sim_set_drop",
             "sim_rl_reset", "sim_rl_step",
             "sim_relaxed_init", "sim_relaxed_workspace_bytes", "sim_step_relaxed_fwd",
             "sim_relaxed_loss", "sim_relaxed_loss_noalloc", "sim_relaxed_loss_bce", "sim_step_relaxed_bwd", "sim_debug_exp", "sim_debug_atan", "sim_debug_philox", "sim_debug_stream",
@@ -67,6 +68,19 @@ class SimPlan(ctypes.Structure):
 
 class SimTuneResult(ctypes.Structure):
     _fields_ = [("plan", SimPlan), ("ms_per_step", ctypes.c_float)]
+
+
+class SimClassPlan(ctypes.Structure):
+    _fields_ = [("size_class", ctypes.c_int32), ("n_env", ctypes.c_int32), ("n_cells", ctypes.c_int64),
+                ("plan", SimPlan), ("ms_per_step", ctypes.c_float), ("from_cache", ctypes.c_int32)]
+
+
+N_SIZE_CLASSES = 8
+PLAN_KEYS = ("tile_rows", "tile_width", "temporal", "skip_static", "sparse", "resident")
+
+
+def _plan_dict(p) -> dict:
+    return {k: int(getattr(p, k)) for k in PLAN_KEYS}
 
 
 class SimError(RuntimeError):
@@ -98,6 +112,9 @@ def lib() -> ctypes.CDLL:
         L.sim_rl_reset.argtypes = [P, P, P, P, P, U64, P, P, P]
         L.sim_rl_step.argtypes = [P, P, P, P, P, P, P, P, P]
         L.sim_autotune.argtypes = [P, P, I32, I32, I32, P, I32, ctypes.POINTER(I32), P]
+        L.sim_set_class_plan.argtypes = [P, I32, P]
+        L.sim_get_class_plans.argtypes = [P, P, I32, ctypes.POINTER(I32)]
+        L.sim_autotune_classes.argtypes = [P, P, I32, I32, I32, ctypes.c_char_p, P, I32, ctypes.POINTER(I32), P]
         L.sim_relaxed_init.argtypes = [P, P, P, P]
         L.sim_relaxed_workspace_bytes.argtypes = [P, I32, I32]
         L.sim_relaxed_workspace_bytes.restype = SZ
@@ -350,6 +367,40 @@ class FireSim:
                          "resident": p.resident},
                         float(res[i].ms_per_step)))
         return out
+
+    # ---------------------------------------------------------- size classes
+    @staticmethod
+    def _classes(arr, n) -> list:
+        return [{"size_class": int(c.size_class), "n_env": int(c.n_env), "n_cells": int(c.n_cells),
+                 "plan": _plan_dict(c.plan), "ms_per_step": float(c.ms_per_step),
+                 "from_cache": bool(c.from_cache)} for c in arr[:n]]
+
+    def set_class_plan(self, size_class: int, tile_rows=0, tile_width=0, temporal=0, skip_static=0, sparse=0,
+                       resident=0):
+        """Give the envs of one size class (larger side in (2^(c+4), 2^(c+5)])
+        their own plan; sim_step then runs the classes in turn."""
+        p = SimPlan(tile_rows, tile_width, temporal, skip_static, sparse, 0, resident)
+        _check(lib().sim_set_class_plan(self.handle, int(size_class), ctypes.byref(p)), self.handle)
+
+    def class_plans(self) -> list:
+        """The size classes present and their plans."""
+        arr = (SimClassPlan * N_SIZE_CLASSES)()
+        n = ctypes.c_int32(0)
+        _check(lib().sim_get_class_plans(self.handle, arr, N_SIZE_CLASSES, ctypes.byref(n)), self.handle)
+        return self._classes(arr, n.value)
+
+    def autotune_classes(self, T_probe: int = 10, allow_skip: bool = True, allow_sparse: bool = False,
+                         cache_path: str = None) -> list:
+        """Tune a plan per size class (each class timed alone; states and step
+        counter unchanged), looking plans up in / appending them to the text
+        file cache_path when given; returns class_plans()."""
+        arr = (SimClassPlan * N_SIZE_CLASSES)()
+        n = ctypes.c_int32(0)
+        path = None if cache_path is None else os.fsencode(cache_path)
+        _check(lib().sim_autotune_classes(self.handle, _ptr(self.states), int(T_probe), int(allow_skip),
+                                          int(allow_sparse), path, arr, N_SIZE_CLASSES, ctypes.byref(n),
+                                          self._s()), self.handle)
+        return self._classes(arr, n.value)
 
     # ------------------------------------------------------------- relaxed
     def relaxed_init(self):

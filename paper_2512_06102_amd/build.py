@@ -14,7 +14,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfiresim.so")
-SOURCES = ["capi.cpp", "stoch.hip", "relaxed.hip", "rl.hip", "resident.hip", "probe.hip"]
+SOURCES = ["capi.cpp", "stoch.hip", "relaxed.hip", "rl.hip", "resident.hip", "groups.hip", "probe.hip"]
 HEADERS = ["devmath.hpp", "internal.hpp", "stepcell.hpp", "framed.hpp", "relaxed.hpp", "resident.hpp", "rl.hpp"]
 
 HIPCC_FLAGS = [

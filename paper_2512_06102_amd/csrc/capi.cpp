@@ -5,12 +5,15 @@
 #include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
+#include <cerrno>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
 #include <mutex>
 #include <new>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -51,6 +54,39 @@ hipError_t noalloc_scratch(int dev, double** out)
     return hipSuccess;
 }
 
+// A set of envs stepped with one plan: the whole batch, or one size class
+// when class plans are set.  Its tile list is built for its plan.
+struct PlanGroup {
+    std::vector<int32_t> envs;       // global env indices (empty: the whole batch)
+    int32_t* d_list = nullptr;       // device copy of envs (nullptr: the whole batch)
+    int32_t size_class = -1;         // -1: the whole batch
+    int64_t n_cells = 0;             // cells of its envs
+    int32_t max_h = 0, max_w = 0;    // largest H and W among them
+    bool aligned = true;             // every env W % 4 == 0 with a 4-aligned offset
+    ResidentShape res;               // the resident kernel's LDS layout over its envs
+    sim_plan plan{4, 64, 1, 1, 1, 0, 0};
+    float tuned_ms = 0.0f;           // the autotuner's time per step (0: not timed)
+    bool from_cache = false;
+    TileDesc* d_tiles = nullptr;
+    int32_t* d_tile_nbr = nullptr;   // [n_tiles][8] neighbouring tiles (-1 off the env)
+    int32_t* d_tile_burn = nullptr;  // [2][n_tiles] burning cells per tile (sparse plan)
+    int32_t* d_tile_eq = nullptr;    // [n_tiles] both state buffers agree on the tile
+    int32_t n_tiles = 0;
+    int32_t tiles_rt = 0;            // tile_rows the tile list was built for
+    int32_t tiles_tw = 0;            // tile_width the tile list was built for
+};
+
+void free_group(PlanGroup& g)
+{
+    for (void* p : {(void*)g.d_list, (void*)g.d_tiles, (void*)g.d_tile_nbr, (void*)g.d_tile_burn,
+                    (void*)g.d_tile_eq})
+        if (p) (void)hipFree(p);
+    g.d_list = nullptr;
+    g.d_tiles = nullptr;
+    g.d_tile_nbr = g.d_tile_burn = g.d_tile_eq = nullptr;
+    g.n_tiles = g.tiles_rt = g.tiles_tw = 0;
+}
+
 struct GraphCache {
     hipGraphExec_t exec = nullptr;
     int32_t T = -1;
@@ -78,6 +114,9 @@ struct sim_handle {
     // tiles with no fire in reach skipped (the dense plan, which streams every
     // cell's 10 bytes each step, is {4, 256, 1, 0, 0, 0})
     sim_plan plan{4, 64, 1, 1, 1, 0, 0};
+    // the whole batch under `plan`, or (when non-empty) its size classes under their own plans
+    PlanGroup all;
+    std::vector<PlanGroup> classes;
     // wind series (caller-owned device memory, indexed by the absolute step)
     const float* series_env = nullptr;   // [series_T][n_env][3]
     const float* series_cell = nullptr;  // [series_T][3][n_cells]
@@ -89,7 +128,6 @@ struct sim_handle {
     int32_t* d_rl_drop = nullptr;
     int32_t* d_rl_counts = nullptr;
     RlFusedShape rl_shape;  // the fused RL step's LDS layout (fits: every env fits it)
-    ResidentShape res_shape;  // the resident multi-step kernel's LDS layout
 
     EnvDev* d_envs = nullptr;
     int32_t* d_chunk_env = nullptr;    // env of every loss chunk (kLossChunk cells)
@@ -105,13 +143,6 @@ struct sim_handle {
     uint8_t* d_init_states = nullptr;  // initial fire state (for the relaxed initial state)
     uint8_t* d_tmp = nullptr;          // ping-pong state buffer
     uint32_t* d_t = nullptr;           // step counter base read by the step kernels
-    TileDesc* d_tiles = nullptr;
-    int32_t* d_tile_nbr = nullptr;     // [n_tiles][8] neighbouring tiles (-1 off the env)
-    int32_t* d_tile_burn = nullptr;    // [2][n_tiles] burning cells per tile (sparse plan)
-    int32_t* d_tile_eq = nullptr;      // [n_tiles] both state buffers agree on the tile
-    int32_t n_tiles = 0;
-    int32_t tiles_rt = 0;              // tile_rows the tile list was built for
-    int32_t tiles_tw = 0;              // tile_width the tile list was built for
     hipStream_t cap_stream = nullptr;
     GraphCache graph;
     RelaxedState relaxed;
@@ -168,10 +199,11 @@ private:
 void free_all(sim_handle* h)
 {
     void* ptrs[] = {h->d_envs, h->d_chunk_env, h->d_loss_scratch, h->d_g, h->d_E, h->d_cls, h->d_den, h->d_wind, h->d_init_states,
-                    h->d_tmp, h->d_t, h->d_tiles, h->d_tile_nbr, h->d_tile_burn, h->d_tile_eq,
-                    h->d_rl_drop, h->d_rl_counts};
+                    h->d_tmp, h->d_t, h->d_rl_drop, h->d_rl_counts};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
+    free_group(h->all);
+    for (PlanGroup& g : h->classes) free_group(g);
     if (h->graph.exec) (void)hipGraphExecDestroy(h->graph.exec);
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     relaxed_free(h->relaxed);
@@ -204,16 +236,18 @@ int tile_width_for(int W, int max_width)
     return w < max_width ? w : max_width;
 }
 
-// Tile list: env-major, then row band, then column band; with each tile's 8
-// neighbouring tiles (same env) for the sparse plan.
+// Tile list of group g: env-major, then row band, then column band; with
+// each tile's 8 neighbouring tiles (same env) for the sparse plan.
 // rt > 0: one-step tiles (one wave64: 256 / width lane rows of rt rows, width
 // narrowed for narrow envs); rt < 0: temporal-blocking tiles of max_width x
 // kTbTileRows for every env.
-int build_tiles(sim_handle* h, int rt, int max_width)
+int build_tiles(sim_handle* h, PlanGroup& g, int rt, int max_width)
 {
     std::vector<TileDesc> tiles;
     std::vector<int32_t> nbr;
-    for (int32_t e = 0; e < h->n_env; ++e) {
+    const int32_t n_members = g.envs.empty() ? h->n_env : (int32_t)g.envs.size();
+    for (int32_t q = 0; q < n_members; ++q) {
+        const int32_t e = g.envs.empty() ? q : g.envs[q];
         const int H = h->envs[e].H, W = h->envs[e].W;
         const int width = rt < 0 ? max_width : tile_width_for(W, max_width);
         const int th = rt < 0 ? kTbTileRows : (256 / width) * rt;
@@ -230,41 +264,104 @@ int build_tiles(sim_handle* h, int rt, int max_width)
                     }
             }
     }
-    for (void** p : {(void**)&h->d_tiles, (void**)&h->d_tile_nbr, (void**)&h->d_tile_burn,
-                     (void**)&h->d_tile_eq}) {
+    for (void** p : {(void**)&g.d_tiles, (void**)&g.d_tile_nbr, (void**)&g.d_tile_burn, (void**)&g.d_tile_eq}) {
         if (*p) (void)hipFree(*p);
         *p = nullptr;
     }
+    g.n_tiles = g.tiles_rt = g.tiles_tw = 0;
     const size_t nt = tiles.size();
-    if (hipMalloc(&h->d_tiles, nt * sizeof(TileDesc)) != hipSuccess ||
-        hipMalloc(&h->d_tile_nbr, nt * 8 * sizeof(int32_t)) != hipSuccess ||
-        hipMalloc(&h->d_tile_burn, nt * 2 * sizeof(int32_t)) != hipSuccess ||
-        hipMalloc(&h->d_tile_eq, nt * sizeof(int32_t)) != hipSuccess)
+    if (hipMalloc(&g.d_tiles, nt * sizeof(TileDesc)) != hipSuccess ||
+        hipMalloc(&g.d_tile_nbr, nt * 8 * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&g.d_tile_burn, nt * 2 * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&g.d_tile_eq, nt * sizeof(int32_t)) != hipSuccess)
         return fail(h, SIM_ENOMEM, "tile list allocation failed");
-    HIP_OR_FAIL(h, hipMemcpy(h->d_tiles, tiles.data(), nt * sizeof(TileDesc), hipMemcpyHostToDevice));
-    HIP_OR_FAIL(h, hipMemcpy(h->d_tile_nbr, nbr.data(), nt * 8 * sizeof(int32_t), hipMemcpyHostToDevice));
-    h->n_tiles = (int32_t)tiles.size();
-    h->tiles_rt = rt;
-    h->tiles_tw = max_width;
+    HIP_OR_FAIL(h, hipMemcpy(g.d_tiles, tiles.data(), nt * sizeof(TileDesc), hipMemcpyHostToDevice));
+    HIP_OR_FAIL(h, hipMemcpy(g.d_tile_nbr, nbr.data(), nt * 8 * sizeof(int32_t), hipMemcpyHostToDevice));
+    g.n_tiles = (int32_t)tiles.size();
+    g.tiles_rt = rt;
+    g.tiles_tw = max_width;
     return SIM_OK;
 }
 
-int tiles_key(const sim_handle* h) { return h->plan.temporal > 1 ? -1 : h->plan.tile_rows; }
+int tiles_key(const sim_plan& p) { return p.temporal > 1 ? -1 : p.tile_rows; }
 
-// Rebuild the tile list if the plan changed its geometry.
-int ensure_tiles(sim_handle* h)
+// The groups sim_step runs: the size classes if class plans are set, else the whole batch.
+std::vector<PlanGroup*> active_groups(sim_handle* h)
 {
-    if (h->tiles_rt == tiles_key(h) && h->tiles_tw == h->plan.tile_width) return SIM_OK;
-    const int rc = build_tiles(h, tiles_key(h), h->plan.tile_width);
-    h->graph.valid = false;
-    return rc;
+    std::vector<PlanGroup*> out;
+    if (h->classes.empty()) {
+        out.push_back(&h->all);
+    } else {
+        for (PlanGroup& g : h->classes) out.push_back(&g);
+    }
+    return out;
 }
 
-StepLaunch step_launch(const sim_handle* h)
+// Rebuild a group's tile list if its plan changed the geometry.
+int ensure_group_tiles(sim_handle* h, PlanGroup& g)
+{
+    if (g.tiles_rt == tiles_key(g.plan) && g.tiles_tw == g.plan.tile_width) return SIM_OK;
+    h->graph.valid = false;
+    return build_tiles(h, g, tiles_key(g.plan), g.plan.tile_width);
+}
+
+int ensure_tiles(sim_handle* h)
+{
+    for (PlanGroup* g : active_groups(h)) {
+        const int rc = ensure_group_tiles(h, *g);
+        if (rc != SIM_OK) return rc;
+    }
+    return SIM_OK;
+}
+
+// Size class of an env (see SIM_N_SIZE_CLASSES).
+int size_class_of(int H, int W)
+{
+    const int side = std::max(H, W);
+    int c = 0;
+    while (c < SIM_N_SIZE_CLASSES - 1 && side > (32 << c)) ++c;
+    return c;
+}
+
+// Alignment, sizes and the resident kernel's fit over a group's envs.
+void describe_group(sim_handle* h, PlanGroup& g)
+{
+    const int32_t n_members = g.envs.empty() ? h->n_env : (int32_t)g.envs.size();
+    int64_t cells = 0, max_cells = 0, max_frame = 0;
+    g.aligned = !(h->wind_cell && h->n_cells % 4 != 0);
+    g.max_h = g.max_w = 0;
+    for (int32_t q = 0; q < n_members; ++q) {
+        const sim_env& v = h->envs[g.envs.empty() ? q : g.envs[q]];
+        if (v.W % 4 != 0 || v.offset % 4 != 0) g.aligned = false;
+        cells += (int64_t)v.H * v.W;
+        max_cells = std::max<int64_t>(max_cells, (int64_t)v.H * v.W);
+        max_frame = std::max<int64_t>(max_frame, ((int64_t)v.H + 2) * (v.W / 4 + 2));
+        g.max_h = std::max(g.max_h, v.H);
+        g.max_w = std::max(g.max_w, v.W);
+    }
+    g.n_cells = cells;
+    g.res = ResidentShape{};
+    int max_lds = 0;
+    if (g.aligned && max_cells <= 65536 &&
+        hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device) == hipSuccess &&
+        max_frame <= max_lds) {
+        g.res.frame_cap = (int32_t)((max_frame + 3) & ~3);
+        g.res.cell_cap = (int32_t)max_cells;
+        // the kernel's own static LDS (under 2.5 KiB) comes on top of the dynamic part
+        const size_t need = resident_lds_bytes(g.res);
+        g.res.fits = need + 2560 <= (size_t)max_lds;
+        if (g.res.fits && resident_set_lds_limit((int)need) != hipSuccess) {
+            (void)hipGetLastError();  // not sticky: these envs just do not take the plan
+            g.res.fits = false;
+        }
+    }
+}
+
+StepLaunch step_launch(const sim_handle* h, const PlanGroup& g)
 {
     StepLaunch L;
-    L.tiles = h->d_tiles;
-    L.n_tiles = h->n_tiles;
+    L.tiles = g.d_tiles;
+    L.n_tiles = g.n_tiles;
     L.envs = h->d_envs;
     L.n_env = h->n_env;
     L.fields = StaticFields{h->d_g, h->d_E, h->wind_cell ? h->d_wind : nullptr, h->n_cells, 0, nullptr,
@@ -276,59 +373,63 @@ StepLaunch step_launch(const sim_handle* h)
         L.fields.env_wind = h->series_env;
     }
     L.args = step_args(h);
-    L.aligned = h->aligned;
-    L.rows_per_thread = h->plan.tile_rows;
-    L.skip_static = h->plan.skip_static != 0;
+    L.aligned = g.aligned;
+    L.rows_per_thread = g.plan.tile_rows;
+    L.skip_static = g.plan.skip_static != 0;
     return L;
 }
 
-// Enqueue the T launches of one sim_step call (counts cleared first; if T is
-// odd the result is copied back from the ping-pong buffer).  With a history
-// buffer, step k reads row k-1 (states for k = 0) and writes row k, and the
-// last row is copied to states.  drop overrides the handle's drop setting.
-hipError_t enqueue_steps(sim_handle* h, hipStream_t s, uint8_t* states, const int32_t* actions,
-                         int32_t T, int32_t* counts, uint8_t* history = nullptr,
-                         const int32_t* drop = nullptr)
+// Copy the cells of group g from src to dst (all cells for the whole batch).
+hipError_t copy_group(sim_handle* h, hipStream_t s, const PlanGroup& g, uint8_t* dst, const uint8_t* src)
+{
+    if (!g.d_list) return launch_copy_u8(s, dst, src, h->n_cells);
+    return launch_copy_envs(s, h->d_envs, g.d_list, (int32_t)g.envs.size(), dst, src);
+}
+
+// Enqueue the launches of T steps of group g's envs (if T is odd the result
+// is copied back from the ping-pong buffer).  With a history buffer, step k
+// reads row k-1 (states for k = 0) and writes row k, and the last row is
+// copied to states.  drop overrides the handle's drop setting.
+hipError_t enqueue_group(sim_handle* h, PlanGroup& g, hipStream_t s, uint8_t* states, const int32_t* actions,
+                         int32_t T, int32_t* counts, uint8_t* history, const int32_t* drop)
 {
     hipError_t e;
-    if (counts) {
-        e = launch_fill_i32(s, counts, (int64_t)T * h->n_env, 0);
-        if (e != hipSuccess) return e;
-    }
-    StepLaunch L = step_launch(h);
+    StepLaunch L = step_launch(h, g);
     if (drop) {
         L.args.drop_mode = drop[0];
         L.args.drop_radius = drop[1];
     }
-    const bool sparse = h->plan.sparse != 0;
-    if (sparse) {  // nothing is known yet about how the two buffers compare
-        e = launch_fill_i32(s, h->d_tile_eq, h->n_tiles, 0);
-        if (e != hipSuccess) return e;
-    }
+    const sim_plan& plan = g.plan;
+    const int32_t n_members = g.envs.empty() ? h->n_env : (int32_t)g.envs.size();
     uint8_t* cur = states;
     uint8_t* nxt = history ? history : h->d_tmp;
-    if (h->plan.resident) {
+    if (plan.resident) {
         // all T steps in one launch, in place (one launch per step with a history)
         if (!history)
-            return launch_stoch_resident(s, h->d_envs, h->n_env, L.fields, L.args, h->res_shape,
-                                         h->plan.resident, states, states, h->d_t, 0u, T, actions, counts);
+            return launch_stoch_resident(s, h->d_envs, h->n_env, g.d_list, n_members, L.fields, L.args, g.res,
+                                         plan.resident, states, states, h->d_t, 0u, T, actions, counts);
         for (int32_t k = 0; k < T; ++k) {
-            e = launch_stoch_resident(s, h->d_envs, h->n_env, L.fields, L.args, h->res_shape, h->plan.resident,
-                                      cur, nxt, h->d_t, (uint32_t)k, 1,
+            e = launch_stoch_resident(s, h->d_envs, h->n_env, g.d_list, n_members, L.fields, L.args, g.res,
+                                      plan.resident, cur, nxt, h->d_t, (uint32_t)k, 1,
                                       actions ? actions + (int64_t)k * h->n_env : nullptr,
                                       counts ? counts + (int64_t)k * h->n_env : nullptr);
             if (e != hipSuccess) return e;
             cur = nxt;
             nxt = history + (int64_t)(k + 1) * h->n_cells;
         }
-        return launch_copy_u8(s, states, cur, h->n_cells);
+        return copy_group(h, s, g, states, cur);
     }
-    if (h->plan.temporal > 1) {
+    const bool sparse = plan.sparse != 0;
+    if (sparse) {  // nothing is known yet about how the two buffers compare
+        e = launch_fill_i32(s, g.d_tile_eq, g.n_tiles, 0);
+        if (e != hipSuccess) return e;
+    }
+    if (plan.temporal > 1) {
         // temporal blocking: K steps per launch (one per launch with a history)
-        const int K = h->plan.temporal;
+        const int K = plan.temporal;
         for (int32_t k = 0; k < T;) {
             const int32_t ks = history ? 1 : std::min<int32_t>(K, T - k);
-            e = launch_stoch_tb(s, L, K, h->plan.tile_width, cur, nxt, h->d_t, (uint32_t)k, ks,
+            e = launch_stoch_tb(s, L, K, plan.tile_width, cur, nxt, h->d_t, (uint32_t)k, ks,
                                 actions ? actions + (int64_t)k * h->n_env : nullptr,
                                 counts ? counts + (int64_t)k * h->n_env : nullptr);
             if (e != hipSuccess) return e;
@@ -340,17 +441,17 @@ hipError_t enqueue_steps(sim_handle* h, hipStream_t s, uint8_t* states, const in
                 std::swap(cur, nxt);
             }
         }
-        if (cur != states) return launch_copy_u8(s, states, cur, h->n_cells);
+        if (cur != states) return copy_group(h, s, g, states, cur);
         return hipSuccess;
     }
     for (int32_t k = 0; k < T; ++k) {
         SparseArgs sp{nullptr, nullptr, nullptr, nullptr, 0};
         if (sparse) {
             // a history row starts empty: an inactive tile must copy its cells
-            if (history && k > 0 && (e = launch_fill_i32(s, h->d_tile_eq, h->n_tiles, 0)) != hipSuccess)
+            if (history && k > 0 && (e = launch_fill_i32(s, g.d_tile_eq, g.n_tiles, 0)) != hipSuccess)
                 return e;
-            sp = SparseArgs{h->d_tile_burn + (k & 1) * h->n_tiles, h->d_tile_burn + ((k + 1) & 1) * h->n_tiles,
-                            h->d_tile_eq, h->d_tile_nbr, k == 0 ? 1 : 0};
+            sp = SparseArgs{g.d_tile_burn + (k & 1) * g.n_tiles, g.d_tile_burn + ((k + 1) & 1) * g.n_tiles,
+                            g.d_tile_eq, g.d_tile_nbr, k == 0 ? 1 : 0};
         }
         e = launch_stoch_step(s, L, cur, nxt, h->d_t, (uint32_t)k,
                               actions ? actions + (int64_t)k * h->n_env : nullptr,
@@ -363,7 +464,23 @@ hipError_t enqueue_steps(sim_handle* h, hipStream_t s, uint8_t* states, const in
             std::swap(cur, nxt);
         }
     }
-    if (cur != states) return launch_copy_u8(s, states, cur, h->n_cells);
+    if (cur != states) return copy_group(h, s, g, states, cur);
+    return hipSuccess;
+}
+
+// Enqueue one sim_step call: counts cleared, then each active group's steps.
+hipError_t enqueue_steps(sim_handle* h, hipStream_t s, uint8_t* states, const int32_t* actions,
+                         int32_t T, int32_t* counts, uint8_t* history = nullptr,
+                         const int32_t* drop = nullptr)
+{
+    if (counts) {
+        const hipError_t e = launch_fill_i32(s, counts, (int64_t)T * h->n_env, 0);
+        if (e != hipSuccess) return e;
+    }
+    for (PlanGroup* g : active_groups(h)) {
+        const hipError_t e = enqueue_group(h, *g, s, states, actions, T, counts, history, drop);
+        if (e != hipSuccess) return e;
+    }
     return hipSuccess;
 }
 
@@ -374,7 +491,7 @@ bool same_plan(const sim_plan& a, const sim_plan& b)
            a.resident == b.resident;
 }
 
-int validate_plan(sim_handle* h, sim_plan& p)
+int validate_plan(sim_handle* h, const PlanGroup& g, sim_plan& p)
 {
     if (p.tile_rows == 0) p.tile_rows = 4;
     if (p.tile_width == 0) p.tile_width = 256;
@@ -386,7 +503,7 @@ int validate_plan(sim_handle* h, sim_plan& p)
     if (!(p.temporal == 1 || p.temporal == 2 || p.temporal == 4 || p.temporal == 8))
         return fail(h, SIM_EINVAL, "temporal must be 1, 2, 4 or 8");
     if (p.temporal > 1) {
-        if (!h->aligned) return fail(h, SIM_EINVAL, "temporal blocking needs W %% 4 == 0 in every env");
+        if (!g.aligned) return fail(h, SIM_EINVAL, "temporal blocking needs W %% 4 == 0 in every env");
         if (p.sparse) return fail(h, SIM_EINVAL, "temporal blocking and the sparse plan do not combine");
         if (p.tile_width != 64 && p.tile_width != 128)
             return fail(h, SIM_EINVAL, "temporal blocking takes tile_width 64 or 128");
@@ -398,7 +515,7 @@ int validate_plan(sim_handle* h, sim_plan& p)
         if (!(p.resident == 64 || p.resident == 256 || p.resident == 512 || p.resident == 1024))
             return fail(h, SIM_EINVAL, "resident must be 0, 64, 256, 512 or 1024");
         if (p.temporal > 1) return fail(h, SIM_EINVAL, "resident and temporal blocking do not combine");
-        if (!h->res_shape.fits)
+        if (!g.res.fits)
             return fail(h, SIM_EINVAL,
                         "resident plan needs W %% 4 == 0 and 4-aligned offsets in every env, at most 65536 "
                         "cells and (H + 2)(W/4 + 2) 8 + 16 H W bytes of LDS per env within the device's "
@@ -493,22 +610,9 @@ int sim_init(sim_handle** out, const sim_params* p, int32_t n_env, const sim_env
             rs.cell_cap = (int32_t)max_cells;
             rs.fits = rl_fused_lds_bytes(rs) <= kRlFusedMaxLds;
         }
-        ResidentShape& ts = h->res_shape;
-        int max_lds = 0;
-        if (max_cells <= 65536 &&
-            hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device) == hipSuccess &&
-            max_frame <= max_lds) {
-            ts.frame_cap = (int32_t)((max_frame + 3) & ~3);
-            ts.cell_cap = (int32_t)max_cells;
-            // the kernel's own static LDS (under 2.5 KiB) comes on top of the dynamic part
-            const size_t need = resident_lds_bytes(ts);
-            ts.fits = need + 2560 <= (size_t)max_lds;
-            if (ts.fits && resident_set_lds_limit((int)need) != hipSuccess) {
-                (void)hipGetLastError();  // not sticky: the batch just does not take the plan
-                ts.fits = false;
-            }
-        }
     }
+    h->all.plan = h->plan;
+    describe_group(h, h->all);
 
     std::vector<EnvDev> ed(n_env);
     std::vector<int32_t> chunk_env;
@@ -567,7 +671,7 @@ int sim_init(sim_handle** out, const sim_params* p, int32_t n_env, const sim_env
         fail(h, SIM_EHIP, "initialisation kernels failed: %s", hipGetErrorString(e));
         return bail(SIM_EHIP);
     }
-    if ((rc = build_tiles(h, tiles_key(h), h->plan.tile_width)) != SIM_OK) return bail(rc);
+    if ((rc = build_tiles(h, h->all, tiles_key(h->all.plan), h->all.plan.tile_width)) != SIM_OK) return bail(rc);
     if (hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess) {
         fail(h, SIM_EHIP, "stream creation failed");
         return bail(SIM_EHIP);
@@ -705,7 +809,7 @@ int sim_rl_step(sim_handle* h, const sim_rl_config* cfg, uint8_t* states, sim_rl
     if ((rc = ensure_tiles(h)) != SIM_OK) return rc;
     RlAgent* ag = reinterpret_cast<RlAgent*>(agents);
     if (cfg->single_launch && h->rl_shape.fits) {
-        StepLaunch L = step_launch(h);
+        StepLaunch L = step_launch(h, h->all);
         L.args.drop_mode = SIM_DROP_WATER;
         L.args.drop_radius = cfg->drop_radius;
         HIP_OR_FAIL(h, launch_rl_step_fused(s, h->d_envs, h->n_env, L.fields, L.args, h->rl_shape, states, ag,
@@ -767,14 +871,158 @@ int sim_set_step(sim_handle* h, uint64_t t)
     return SIM_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+void drop_classes(sim_handle* h)
+{
+    for (PlanGroup& g : h->classes) free_group(g);
+    h->classes.clear();
+    h->graph.valid = false;
+}
+
+// Split the batch into its size classes, each under the handle-wide plan.
+int make_classes(sim_handle* h)
+{
+    std::vector<PlanGroup> cls(SIM_N_SIZE_CLASSES);
+    for (int32_t e = 0; e < h->n_env; ++e) cls[size_class_of(h->envs[e].H, h->envs[e].W)].envs.push_back(e);
+    drop_classes(h);
+    for (int c = 0; c < SIM_N_SIZE_CLASSES; ++c) {
+        PlanGroup& g = cls[c];
+        if (g.envs.empty()) continue;
+        g.size_class = c;
+        g.plan = h->plan;
+        describe_group(h, g);
+        const size_t bytes = g.envs.size() * sizeof(int32_t);
+        if (hipMalloc(&g.d_list, bytes) != hipSuccess) {
+            for (PlanGroup& x : h->classes) free_group(x);
+            h->classes.clear();
+            return fail(h, SIM_ENOMEM, "size-class env list allocation failed");
+        }
+        h->classes.push_back(g);  // owns d_list from here
+        HIP_OR_FAIL(h, hipMemcpy(h->classes.back().d_list, g.envs.data(), bytes, hipMemcpyHostToDevice));
+    }
+    return SIM_OK;
+}
+
+PlanGroup* find_class(sim_handle* h, int32_t c)
+{
+    for (PlanGroup& g : h->classes)
+        if (g.size_class == c) return &g;
+    return nullptr;
+}
+
+// Time every candidate plan on group g alone (T_probe steps from `states`
+// in `work`) and give g the fastest; `tried` receives the plans, fastest
+// first.  g's graph field is kept.
+int tune_group(sim_handle* h, PlanGroup& g, hipStream_t s, const uint8_t* states, uint8_t* work, int32_t T_probe,
+               int32_t allow_skip, int32_t allow_sparse, std::vector<sim_tune_result>& tried)
+{
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return fail(h, SIM_EHIP, "event creation failed");
+    }
+    const sim_plan saved = g.plan;
+    std::vector<sim_plan> cands;
+    for (int skip = 0; skip <= (allow_skip ? 1 : 0); ++skip)
+        for (int width : {64, 256})
+            for (int rows : {1, 2, 4, 8})
+                cands.push_back(sim_plan{rows, width, 1, skip, allow_sparse ? 1 : 0, 0, 0});
+    if (allow_skip && g.aligned)  // temporal blocking reads fuel and elevation only at fronts, like skip
+        for (int width : {64, 128})
+            for (int k : {2, 4, 8}) cands.push_back(sim_plan{4, width, k, 1, 0, 0, 0});
+    if (allow_skip && g.res.fits)  // so does the resident kernel
+        for (int nt : {64, 256, 512, 1024}) cands.push_back(sim_plan{4, 64, 1, 1, allow_sparse ? 1 : 0, 0, nt});
+    tried.clear();
+    int rc = SIM_OK;
+    for (const sim_plan& cand : cands) {
+        g.plan = cand;
+        if ((rc = ensure_group_tiles(h, g)) != SIM_OK) break;
+        hipError_t e = hipSuccess;
+        float best = 0.0f;
+        for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {  // the first pass warms up
+            e = launch_copy_u8(s, work, states, h->n_cells);
+            if (e == hipSuccess) e = launch_set_u32(s, h->d_t, (uint32_t)h->t);
+            if (e == hipSuccess) e = hipEventRecord(e0, s);
+            if (e == hipSuccess) e = enqueue_group(h, g, s, work, nullptr, T_probe, nullptr, nullptr, nullptr);
+            if (e == hipSuccess) e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            if (e == hipSuccess) e = hipEventElapsedTime(&best, e0, e1);
+        }
+        if (e != hipSuccess) {
+            rc = fail(h, SIM_EHIP, "autotune run failed: %s", hipGetErrorString(e));
+            break;
+        }
+        tried.push_back(sim_tune_result{g.plan, best / (float)T_probe});
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    std::sort(tried.begin(), tried.end(),
+              [](const sim_tune_result& a, const sim_tune_result& b) { return a.ms_per_step < b.ms_per_step; });
+    g.plan = saved;
+    if (rc == SIM_OK && !tried.empty()) {
+        g.plan = tried[0].plan;
+        g.plan.graph = saved.graph;
+        g.tuned_ms = tried[0].ms_per_step;
+    }
+    h->graph.valid = false;
+    const int built = ensure_group_tiles(h, g);
+    return rc == SIM_OK ? built : rc;
+}
+
+int check_tune_args(sim_handle* h, const uint8_t* states, int32_t T_probe)
+{
+    if (!h) return fail(nullptr, SIM_EINVAL, "handle is NULL");
+    if (!states || T_probe < 1) return fail(h, SIM_EINVAL, "need states and T_probe >= 1");
+    if ((h->series_env || h->series_cell) && h->t + (uint64_t)T_probe > (uint64_t)h->series_T)
+        return fail(h, SIM_EINVAL, "T_probe steps from the current step run past the wind series");
+    return SIM_OK;
+}
+
+// The tuning-cache key of a size class (one line of text, no ':').
+std::string class_key(const sim_handle* h, const PlanGroup& g, int32_t T_probe, int32_t allow_skip,
+                      int32_t allow_sparse)
+{
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, h->device) == hipSuccess) arch = prop.gcnArchName;
+    for (char& c : arch)
+        if (c == ' ' || c == ':') c = '_';
+    const char* wind = h->series_cell ? "cell_series" : (h->series_env ? "env_series" : (h->wind_cell ? "cell" : "env"));
+    std::ostringstream k;
+    k << "firesim-plan-v1 arch=" << arch << " class=" << g.size_class << " n_env=" << g.envs.size()
+      << " cells=" << g.n_cells << " max_h=" << g.max_h << " max_w=" << g.max_w << " aligned=" << (g.aligned ? 1 : 0)
+      << " wind=" << wind << " T_probe=" << T_probe << " allow_skip=" << (allow_skip ? 1 : 0)
+      << " allow_sparse=" << (allow_sparse ? 1 : 0);
+    return k.str();
+}
+
+void class_entry(const PlanGroup& g, sim_class_plan& out)
+{
+    out.size_class = g.size_class;
+    out.n_env = (int32_t)g.envs.size();
+    out.n_cells = g.n_cells;
+    out.plan = g.plan;
+    out.ms_per_step = g.tuned_ms;
+    out.from_cache = g.from_cache ? 1 : 0;
+}
+
+}  // namespace
+
+extern "C" {
+
 int sim_set_plan(sim_handle* h, const sim_plan* plan)
 {
     CallScope scope("sim_set_plan", h);
     if (!h || !plan) return SIM_EINVAL;
     sim_plan p = *plan;
-    const int rc = validate_plan(h, p);
+    const int rc = validate_plan(h, h->all, p);
     if (rc != SIM_OK) return rc;
+    drop_classes(h);
     h->plan = p;
+    h->all.plan = p;
     return SIM_OK;
 }
 
@@ -790,72 +1038,146 @@ int sim_autotune(sim_handle* h, const uint8_t* states, int32_t T_probe, int32_t 
                  int32_t* n_results, void* stream)
 {
     CallScope scope("sim_autotune", h);
-    if (!h) return fail(nullptr, SIM_EINVAL, "handle is NULL");
-    if (!states || T_probe < 1 || max_results < 0 || (max_results > 0 && !results))
-        return fail(h, SIM_EINVAL, "need states, T_probe >= 1 and a results array");
-    if ((h->series_env || h->series_cell) && h->t + (uint64_t)T_probe > (uint64_t)h->series_T)
-        return fail(h, SIM_EINVAL, "T_probe steps from the current step run past the wind series");
-    hipStream_t s = (hipStream_t)stream;
-    const sim_plan saved = h->plan;
+    int rc = check_tune_args(h, states, T_probe);
+    if (rc != SIM_OK) return rc;
+    if (max_results < 0 || (max_results > 0 && !results))
+        return fail(h, SIM_EINVAL, "need a results array for max_results > 0");
+    drop_classes(h);
     uint8_t* work = nullptr;
     if (hipMalloc(&work, (size_t)h->n_cells) != hipSuccess)
         return fail(h, SIM_ENOMEM, "autotune scratch allocation failed");
-    hipEvent_t e0 = nullptr, e1 = nullptr;
     std::vector<sim_tune_result> tried;
-    int rc = SIM_OK;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
-        rc = fail(h, SIM_EHIP, "event creation failed");
-    }
-    std::vector<sim_plan> cands;
-    for (int skip = 0; skip <= (allow_skip ? 1 : 0); ++skip)
-        for (int width : {64, 256})
-            for (int rows : {1, 2, 4, 8})
-                cands.push_back(sim_plan{rows, width, 1, skip, allow_sparse ? 1 : 0, 0, 0});
-    if (allow_skip && h->aligned)  // temporal blocking reads fuel and elevation only at fronts, like skip
-        for (int width : {64, 128})
-            for (int k : {2, 4, 8}) cands.push_back(sim_plan{4, width, k, 1, 0, 0, 0});
-    if (allow_skip && h->res_shape.fits)  // so does the resident kernel
-        for (int nt : {64, 256, 512, 1024}) cands.push_back(sim_plan{4, 64, 1, 1, allow_sparse ? 1 : 0, 0, nt});
-    for (const sim_plan& cand : cands) {
-        {
-                if (rc != SIM_OK) break;
-                h->plan = cand;
-                if ((rc = ensure_tiles(h)) != SIM_OK) break;
-                hipError_t e = hipSuccess;
-                float best = 0.0f;
-                for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {  // first pass warms up
-                    e = launch_copy_u8(s, work, states, h->n_cells);
-                    if (e == hipSuccess) e = launch_set_u32(s, h->d_t, (uint32_t)h->t);
-                    if (e == hipSuccess) e = hipEventRecord(e0, s);
-                    if (e == hipSuccess) e = enqueue_steps(h, s, work, nullptr, T_probe, nullptr);
-                    if (e == hipSuccess) e = hipEventRecord(e1, s);
-                    if (e == hipSuccess) e = hipEventSynchronize(e1);
-                    if (e == hipSuccess) e = hipEventElapsedTime(&best, e0, e1);
-                }
-                if (e != hipSuccess) {
-                    rc = fail(h, SIM_EHIP, "autotune run failed: %s", hipGetErrorString(e));
-                    break;
-                }
-                tried.push_back(sim_tune_result{h->plan, best / (float)T_probe});
-        }
-    }
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
+    h->all.plan = h->plan;
+    rc = tune_group(h, h->all, (hipStream_t)stream, states, work, T_probe, allow_skip, allow_sparse, tried);
     (void)hipFree(work);
-    std::sort(tried.begin(), tried.end(),
-              [](const sim_tune_result& a, const sim_tune_result& b) { return a.ms_per_step < b.ms_per_step; });
-    h->plan = saved;
-    if (rc == SIM_OK && !tried.empty()) {
-        h->plan = tried[0].plan;
-        h->plan.graph = saved.graph;
-    }
-    h->graph.valid = false;
-    const int built = ensure_tiles(h);
-    if (rc == SIM_OK) rc = built;
+    h->plan = h->all.plan;
     const int n = std::min<int>((int)tried.size(), max_results);
     for (int i = 0; i < n; ++i) results[i] = tried[i];
     if (n_results) *n_results = n;
     return rc;
+}
+
+int sim_set_class_plan(sim_handle* h, int32_t size_class, const sim_plan* plan)
+{
+    CallScope scope("sim_set_class_plan", h);
+    if (!h || !plan) return fail(h, SIM_EINVAL, "handle and plan are required");
+    int rc;
+    if (h->classes.empty() && (rc = make_classes(h)) != SIM_OK) return rc;
+    PlanGroup* g = find_class(h, size_class);
+    if (!g) return fail(h, SIM_EINVAL, "the batch has no env in size class %d", size_class);
+    sim_plan p = *plan;
+    if ((rc = validate_plan(h, *g, p)) != SIM_OK) return rc;
+    g->plan = p;
+    g->tuned_ms = 0.0f;
+    g->from_cache = false;
+    h->graph.valid = false;
+    return SIM_OK;
+}
+
+int sim_get_class_plans(const sim_handle* h, sim_class_plan* out, int32_t max_out, int32_t* n_out)
+{
+    if (!h || max_out < 0 || (max_out > 0 && !out)) return SIM_EINVAL;
+    std::vector<sim_class_plan> list;
+    if (!h->classes.empty()) {
+        for (const PlanGroup& g : h->classes) {
+            sim_class_plan c{};
+            class_entry(g, c);
+            list.push_back(c);
+        }
+    } else {
+        std::vector<sim_class_plan> all(SIM_N_SIZE_CLASSES);
+        for (const sim_env& v : h->envs) {
+            sim_class_plan& c = all[size_class_of(v.H, v.W)];
+            c.n_env += 1;
+            c.n_cells += (int64_t)v.H * v.W;
+        }
+        for (int c = 0; c < SIM_N_SIZE_CLASSES; ++c)
+            if (all[c].n_env) {
+                all[c].size_class = c;
+                all[c].plan = h->plan;
+                list.push_back(all[c]);
+            }
+    }
+    const int n = std::min<int>((int)list.size(), max_out);
+    for (int i = 0; i < n; ++i) out[i] = list[i];
+    if (n_out) *n_out = (int32_t)list.size();
+    return SIM_OK;
+}
+
+int sim_autotune_classes(sim_handle* h, const uint8_t* states, int32_t T_probe, int32_t allow_skip,
+                         int32_t allow_sparse, const char* cache_path, sim_class_plan* out,
+                         int32_t max_out, int32_t* n_out, void* stream)
+{
+    CallScope scope("sim_autotune_classes", h);
+    int rc = check_tune_args(h, states, T_probe);
+    if (rc != SIM_OK) return rc;
+    if (max_out < 0 || (max_out > 0 && !out)) return fail(h, SIM_EINVAL, "need an out array for max_out > 0");
+    // the cache: key -> plan, the last line of a key winning
+    std::vector<std::pair<std::string, std::string>> cached;
+    if (cache_path) {
+        FILE* f = std::fopen(cache_path, "r");
+        if (!f && errno != ENOENT) return fail(h, SIM_EINVAL, "cannot read the tuning cache %s", cache_path);
+        if (f) {
+            char line[1024];
+            while (std::fgets(line, sizeof line, f)) {
+                const char* sep = std::strstr(line, " : ");
+                if (!sep || std::strncmp(line, "firesim-plan-v1 ", 16) != 0) continue;
+                cached.emplace_back(std::string(line, (size_t)(sep - line)), std::string(sep + 3));
+            }
+            std::fclose(f);
+        }
+    }
+    if ((rc = make_classes(h)) != SIM_OK) return rc;
+    uint8_t* work = nullptr;
+    std::vector<sim_tune_result> tried;
+    std::string appended;
+    for (PlanGroup& g : h->classes) {
+        const std::string key = class_key(h, g, T_probe, allow_skip, allow_sparse);
+        bool hit = false;
+        for (auto it = cached.rbegin(); it != cached.rend() && !hit; ++it) {
+            if (it->first != key) continue;
+            sim_plan p{};
+            float ms = 0.0f;
+            if (std::sscanf(it->second.c_str(), "%d %d %d %d %d %d %f", &p.tile_rows, &p.tile_width, &p.temporal,
+                            &p.skip_static, &p.sparse, &p.resident, &ms) != 7)
+                continue;
+            p.graph = h->plan.graph;
+            const std::string err = h->err;
+            if (validate_plan(h, g, p) != SIM_OK) {  // a line this batch cannot take is skipped
+                h->err = err;
+                continue;
+            }
+            g.plan = p;
+            g.tuned_ms = ms;
+            g.from_cache = true;
+            hit = true;
+        }
+        if (hit) continue;
+        if (!work && hipMalloc(&work, (size_t)h->n_cells) != hipSuccess) {
+            rc = fail(h, SIM_ENOMEM, "autotune scratch allocation failed");
+            break;
+        }
+        if ((rc = tune_group(h, g, (hipStream_t)stream, states, work, T_probe, allow_skip, allow_sparse, tried)) !=
+            SIM_OK)
+            break;
+        char val[160];
+        std::snprintf(val, sizeof val, "%d %d %d %d %d %d %.6g\n", g.plan.tile_rows, g.plan.tile_width,
+                      g.plan.temporal, g.plan.skip_static, g.plan.sparse, g.plan.resident, (double)g.tuned_ms);
+        appended += key + " : " + val;
+    }
+    if (work) (void)hipFree(work);
+    if (rc == SIM_OK && cache_path && !appended.empty()) {
+        FILE* f = std::fopen(cache_path, "a");
+        if (!f || std::fputs(appended.c_str(), f) < 0) rc = fail(h, SIM_EINVAL, "cannot append to the tuning cache %s", cache_path);
+        if (f && std::fclose(f) != 0 && rc == SIM_OK)
+            rc = fail(h, SIM_EINVAL, "cannot append to the tuning cache %s", cache_path);
+    }
+    h->graph.valid = false;
+    if (rc == SIM_OK) rc = ensure_tiles(h);
+    int32_t n = 0;
+    const int rc2 = sim_get_class_plans(h, out, max_out, &n);
+    if (n_out) *n_out = n;
+    return rc != SIM_OK ? rc : rc2;
 }
 
 int sim_relaxed_init(sim_handle* h, double* U, double* B, void* stream)

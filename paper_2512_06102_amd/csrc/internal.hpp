@@ -62,6 +62,9 @@ hipError_t launch_ignite(hipStream_t s, const int32_t* ign, int32_t n_ign, const
                          uint8_t* states);
 hipError_t launch_fill_i32(hipStream_t s, int32_t* p, int64_t n, int32_t v);
 hipError_t launch_copy_u8(hipStream_t s, uint8_t* dst, const uint8_t* src, int64_t n);
+// Copy the cells of envs env_list[0..n_list) from src to dst.
+hipError_t launch_copy_envs(hipStream_t s, const EnvDev* envs, const int32_t* env_list, int32_t n_list,
+                            uint8_t* dst, const uint8_t* src);
 
 struct StepLaunch {
     const TileDesc* tiles;

@@ -75,17 +75,18 @@ constexpr int kChunk = 64;  // steps of drops and wind exponents staged at once
 
 template <int NT, bool WIND_CELL>
 __global__ __launch_bounds__(NT) void stoch_resident_kernel(
-    const EnvDev* __restrict__ envs, StaticFields F0, StepArgs A, const uint8_t* src_states,
-    uint8_t* dst_states, const int32_t* __restrict__ actions, int32_t* __restrict__ counts,
-    int32_t n_env, const uint32_t* __restrict__ t_base, uint32_t step0, int32_t T, int32_t frame_cap,
-    int32_t cell_cap)
+    const EnvDev* __restrict__ envs, const int32_t* __restrict__ env_list, StaticFields F0, StepArgs A,
+    const uint8_t* src_states, uint8_t* dst_states, const int32_t* __restrict__ actions,
+    int32_t* __restrict__ counts, int32_t n_env, const uint32_t* __restrict__ t_base, uint32_t step0, int32_t T,
+    int32_t frame_cap, int32_t cell_cap)
 {
     constexpr int NW = NT / 64;
     extern __shared__ uint4 lds_dyn[];
     __shared__ float s_ew[kChunk][8];  // per-env wind exponents of the chunk's steps
     __shared__ int32_t s_act[kChunk];  // the chunk's drops
     __shared__ uint32_t s_count[2];
-    const int e = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int e = env_list ? env_list[blockIdx.x] : (int)blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const EnvDev ed = envs[e];
     const int H = ed.H, W = ed.W, WD = W >> 2, SW = WD + 2, n_dw = H * WD;
     const float inv_wd = 1.0f / (float)WD;
@@ -278,17 +279,18 @@ hipError_t set_lds_limit(int bytes)
 }
 
 template <int NT>
-hipError_t launch_nt(hipStream_t s, const EnvDev* envs, int32_t n_env, const StaticFields& F, const StepArgs& A,
-                     const ResidentShape& shape, const uint8_t* src, uint8_t* dst, const uint32_t* t_base,
-                     uint32_t step0, int32_t T, const int32_t* actions, int32_t* counts)
+hipError_t launch_nt(hipStream_t s, const EnvDev* envs, int32_t n_env, const int32_t* env_list, int32_t n_list,
+                     const StaticFields& F, const StepArgs& A, const ResidentShape& shape, const uint8_t* src,
+                     uint8_t* dst, const uint32_t* t_base, uint32_t step0, int32_t T, const int32_t* actions,
+                     int32_t* counts)
 {
     const size_t lds = resident_lds_bytes(shape);
     if (F.wind)  // per-cell wind (static or a series)
-        hipLaunchKernelGGL((stoch_resident_kernel<NT, true>), dim3(n_env), dim3(NT), lds, s, envs, F, A, src, dst,
-                           actions, counts, n_env, t_base, step0, T, shape.frame_cap, shape.cell_cap);
+        hipLaunchKernelGGL((stoch_resident_kernel<NT, true>), dim3(n_list), dim3(NT), lds, s, envs, env_list, F, A,
+                           src, dst, actions, counts, n_env, t_base, step0, T, shape.frame_cap, shape.cell_cap);
     else
-        hipLaunchKernelGGL((stoch_resident_kernel<NT, false>), dim3(n_env), dim3(NT), lds, s, envs, F, A, src, dst,
-                           actions, counts, n_env, t_base, step0, T, shape.frame_cap, shape.cell_cap);
+        hipLaunchKernelGGL((stoch_resident_kernel<NT, false>), dim3(n_list), dim3(NT), lds, s, envs, env_list, F, A,
+                           src, dst, actions, counts, n_env, t_base, step0, T, shape.frame_cap, shape.cell_cap);
     return hipGetLastError();
 }
 
@@ -303,19 +305,21 @@ hipError_t resident_set_lds_limit(int bytes)
     return e;
 }
 
-hipError_t launch_stoch_resident(hipStream_t s, const EnvDev* envs, int32_t n_env, const StaticFields& F,
-                                 const StepArgs& A, const ResidentShape& shape, int threads, const uint8_t* src,
-                                 uint8_t* dst, const uint32_t* t_base, uint32_t step0, int32_t T,
-                                 const int32_t* actions, int32_t* counts)
+hipError_t launch_stoch_resident(hipStream_t s, const EnvDev* envs, int32_t n_env, const int32_t* env_list,
+                                 int32_t n_list, const StaticFields& F, const StepArgs& A, const ResidentShape& shape,
+                                 int threads, const uint8_t* src, uint8_t* dst, const uint32_t* t_base,
+                                 uint32_t step0, int32_t T, const int32_t* actions, int32_t* counts)
 {
-    if (!shape.fits || T < 1) return hipErrorInvalidValue;
+    if (!shape.fits || T < 1 || n_list < 1) return hipErrorInvalidValue;
+#define RESIDENT_ARGS s, envs, n_env, env_list, n_list, F, A, shape, src, dst, t_base, step0, T, actions, counts
     switch (threads) {
-    case 64: return launch_nt<64>(s, envs, n_env, F, A, shape, src, dst, t_base, step0, T, actions, counts);
-    case 256: return launch_nt<256>(s, envs, n_env, F, A, shape, src, dst, t_base, step0, T, actions, counts);
-    case 512: return launch_nt<512>(s, envs, n_env, F, A, shape, src, dst, t_base, step0, T, actions, counts);
-    case 1024: return launch_nt<1024>(s, envs, n_env, F, A, shape, src, dst, t_base, step0, T, actions, counts);
+    case 64: return launch_nt<64>(RESIDENT_ARGS);
+    case 256: return launch_nt<256>(RESIDENT_ARGS);
+    case 512: return launch_nt<512>(RESIDENT_ARGS);
+    case 1024: return launch_nt<1024>(RESIDENT_ARGS);
     default: return hipErrorInvalidValue;
     }
+#undef RESIDENT_ARGS
 }
 
 }  // namespace firesim

@@ -27,14 +27,15 @@ inline size_t resident_lds_bytes(const ResidentShape& s)
 // Allows every instance of the kernel `bytes` of dynamic LDS.
 hipError_t resident_set_lds_limit(int bytes);
 
-// T steps of every env from src to dst (which may be the same buffer), the
-// first at the absolute step *t_base + step0 (t_base in device memory, so a
-// captured launch serves any starting step), by workgroups of `threads`
-// lanes (64, 256, 512 or 1024); actions and counts point at the rows of the
-// first step (n_env entries per step) or are NULL.
-hipError_t launch_stoch_resident(hipStream_t s, const EnvDev* envs, int32_t n_env, const StaticFields& F,
-                                 const StepArgs& A, const ResidentShape& shape, int threads, const uint8_t* src,
-                                 uint8_t* dst, const uint32_t* t_base, uint32_t step0, int32_t T,
-                                 const int32_t* actions, int32_t* counts);
+// T steps of the n_list envs env_list[0..n_list) (env_list NULL: envs
+// 0..n_list) from src to dst (which may be the same buffer), the first at the
+// absolute step *t_base + step0 (t_base in device memory, so a captured
+// launch serves any starting step), by workgroups of `threads` lanes (64,
+// 256, 512 or 1024); actions and counts point at the rows of the first step
+// (n_env entries per step, indexed by the global env index) or are NULL.
+hipError_t launch_stoch_resident(hipStream_t s, const EnvDev* envs, int32_t n_env, const int32_t* env_list,
+                                 int32_t n_list, const StaticFields& F, const StepArgs& A, const ResidentShape& shape,
+                                 int threads, const uint8_t* src, uint8_t* dst, const uint32_t* t_base,
+                                 uint32_t step0, int32_t T, const int32_t* actions, int32_t* counts);
 
 }  // namespace firesim

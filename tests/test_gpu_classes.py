@@ -1,0 +1,164 @@
+"""GPU parity of per-size-class plans (sim_set_class_plan,
+sim_autotune_classes): each size class stepped with its own plan, bit-exact
+against the CPU oracle; the tuning cache hit by a second handle on the same
+shapes without re-timing."""
+import numpy as np
+import pytest
+import torch
+
+import firegen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+fs = pytest.importorskip("paper_2512_06102_amd")
+
+# classes: 0 (20 x 20, 8 x 12), 1 (64 x 64, 36 x 52), 2 (100 x 120, ragged 90 x 101),
+# 3 (256 x 200), 4 (300 x 500)
+SIZES = [(20, 20)] * 40 + [(8, 12)] * 3 + [(64, 64)] * 12 + [(36, 52)] * 3 + [(100, 120)] * 3 + \
+        [(90, 101)] * 2 + [(256, 200)] * 2 + [(300, 500)]
+
+HAND = {0: dict(resident=64), 1: dict(resident=1024), 2: dict(tile_rows=2, tile_width=64, skip_static=1, sparse=1),
+        3: dict(tile_width=128, temporal=4, skip_static=1), 4: dict(tile_rows=4, tile_width=256)}
+
+
+def _veg(seed):
+    return tuple(float(v) for v in firegen.veg_table(np.random.default_rng(seed)))
+
+
+def _batch():
+    return firegen.landscape_batch(71, SIZES), firegen.Params(p_base=0.85, veg=_veg(71))
+
+
+def test_size_classes_of_the_batch():
+    batch, params = _batch()
+    sim = fs.FireSim.from_batch(batch, params, seed=0)
+    cls = sim.class_plans()
+    assert [c["size_class"] for c in cls] == [0, 1, 2, 3, 4]
+    assert [c["n_env"] for c in cls] == [43, 15, 5, 2, 1]
+    assert sum(c["n_cells"] for c in cls) == batch.n_cells
+    assert all(c["plan"] == sim.class_plans()[0]["plan"] for c in cls)  # the handle-wide plan
+
+
+@pytest.mark.parametrize("graph", [1, 0])
+def test_hand_set_class_plans_with_drops_and_splits(graph):
+    """Five classes, five different plans (resident, sparse, temporal,
+    dense), drops and counts, an odd T split over two calls."""
+    batch, params = _batch()
+    T = 45
+    act = firegen.random_actions(31, batch, T, p_none=0.3)
+    ref = oracle.Sim(batch, params, seed=21)
+    want = ref.step(T, actions=act, counts=True, threads=8, drop_mode=1, drop_radius=2)
+    sim = fs.FireSim.from_batch(batch, params, seed=21)
+    sim.set_plan(graph=graph)
+    sim.set_drop(1, 2)
+    for c, plan in HAND.items():
+        sim.set_class_plan(c, **plan)
+    got = [sim.step(n, actions=torch.from_numpy(np.ascontiguousarray(a)), counts=True).cpu().numpy()
+           for n, a in ((20, act[:20]), (T - 20, act[20:]))]
+    torch.cuda.synchronize()
+    assert np.array_equal(sim.states.cpu().numpy(), ref.states)
+    assert np.array_equal(np.concatenate(got), want)
+    plans = {c["size_class"]: c["plan"] for c in sim.class_plans()}
+    assert plans[0]["resident"] == 64 and plans[3]["temporal"] == 4 and plans[4]["skip_static"] == 0
+
+
+def test_class_plans_history():
+    batch, params = _batch()
+    T = 12
+    act = firegen.random_actions(32, batch, T, p_none=0.5)
+    ref = oracle.Sim(batch, params, seed=22)
+    rows, want = ref.step(T, actions=act, counts=True, threads=8, history=True)
+    sim = fs.FireSim.from_batch(batch, params, seed=22)
+    for c, plan in HAND.items():
+        sim.set_class_plan(c, **plan)
+    hist, cnt = sim.step_history(T, actions=torch.from_numpy(act), counts=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(hist.cpu().numpy(), rows)
+    assert np.array_equal(cnt.cpu().numpy(), want)
+    assert np.array_equal(sim.states.cpu().numpy(), rows[-1])
+
+
+def test_autotune_classes_and_the_cache(tmp_path):
+    """The first handle times every class and appends one cache line per
+    class; a second handle on the same shapes takes every plan from the cache
+    (no timing); another T_probe misses.  Both step bit-exact."""
+    batch, params = _batch()
+    cache = tmp_path / "plans.txt"
+    T = 30
+    ref = oracle.Sim(batch, params, seed=23)
+    want = ref.step(T, counts=True, threads=8)
+
+    sim = fs.FireSim.from_batch(batch, params, seed=23)
+    first = sim.autotune_classes(T_probe=8, allow_skip=True, allow_sparse=True, cache_path=str(cache))
+    assert [c["size_class"] for c in first] == [0, 1, 2, 3, 4]
+    assert not any(c["from_cache"] for c in first) and all(c["ms_per_step"] > 0 for c in first)
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 5 and all(l.startswith("firesim-plan-v1 arch=") for l in lines)
+    got = sim.step(T, counts=True).cpu().numpy()
+    torch.cuda.synchronize()
+    assert np.array_equal(sim.states.cpu().numpy(), ref.states)
+    assert np.array_equal(got, want)
+
+    sim2 = fs.FireSim.from_batch(batch, params, seed=23)
+    second = sim2.autotune_classes(T_probe=8, allow_skip=True, allow_sparse=True, cache_path=str(cache))
+    assert all(c["from_cache"] for c in second)
+    assert [c["plan"] for c in second] == [c["plan"] for c in first]
+    assert len(cache.read_text().splitlines()) == 5
+    got2 = sim2.step(T, counts=True).cpu().numpy()
+    torch.cuda.synchronize()
+    assert np.array_equal(sim2.states.cpu().numpy(), ref.states)
+    assert np.array_equal(got2, want)
+
+    third = sim2.autotune_classes(T_probe=5, allow_skip=True, allow_sparse=True, cache_path=str(cache))
+    assert not any(c["from_cache"] for c in third)
+    assert len(cache.read_text().splitlines()) == 10
+
+    sim2.set_plan(tile_rows=2, tile_width=64)  # back to one plan for all envs
+    assert all(c["plan"]["tile_rows"] == 2 and c["ms_per_step"] == 0 for c in sim2.class_plans())
+
+
+def test_class_plan_rejections(tmp_path):
+    batch, params = _batch()
+    sim = fs.FireSim.from_batch(batch, params, seed=0)
+    with pytest.raises(fs.SimError):
+        sim.set_class_plan(5, tile_rows=4)          # no env in class 5
+    with pytest.raises(fs.SimError):
+        sim.set_class_plan(2, resident=256)          # class 2 holds a 90 x 101 env
+    with pytest.raises(fs.SimError):
+        sim.set_class_plan(2, temporal=4, tile_width=64)
+    with pytest.raises(fs.SimError):
+        sim.set_plan(resident=256)                   # the whole batch cannot take it
+    sim.set_class_plan(0, resident=256)              # its small envs can
+    with pytest.raises(fs.SimError):
+        sim.autotune_classes(T_probe=2, cache_path=str(tmp_path))  # a directory, not a file
+    bad = tmp_path / "bad.txt"
+    bad.write_text("firesim-plan-v1 garbage : 1 2\nnot a plan line\n")
+    res = sim.autotune_classes(T_probe=2, cache_path=str(bad))
+    assert not any(c["from_cache"] for c in res)
+
+
+def test_uneven_workload_per_class_plans_sampled_envs():
+    """The full uneven workload (4096 envs, sides 64 / 128 / 256 / 512, a 5x5
+    drop per env per step, 300 steps) under per-class autotuned plans: 8
+    sampled envs of each side equal the oracle, counts too."""
+    batch, params, T, seed, acts = firegen.workload_uneven()
+    rng = np.random.default_rng(8)
+    sample = []
+    for side in (64, 128, 256, 512):
+        of_side = np.flatnonzero(batch.H == side)
+        sample += [int(of_side[0]), int(of_side[-1])] + [int(e) for e in rng.choice(of_side[1:-1], 6, replace=False)]
+    sample = sorted(sample)
+    sub = batch.subset(sample)
+    ref = oracle.Sim(sub, params, seed=seed)
+    rc = ref.step(T, actions=np.ascontiguousarray(acts[:, sample]), counts=True, threads=16)
+    sim = fs.FireSim.from_batch(batch, params, seed=seed)
+    sim.set_plan(graph=1)
+    cls = sim.autotune_classes(T_probe=20, allow_skip=True, allow_sparse=True)
+    assert [c["size_class"] for c in cls] == [1, 2, 3, 4]
+    cnt = sim.step(T, actions=torch.from_numpy(acts).cuda(), counts=True).cpu().numpy()
+    torch.cuda.synchronize()
+    got = sim.states.cpu().numpy()
+    for k, e in enumerate(sample):
+        assert np.array_equal(batch.env_view(got, e), sub.env_view(ref.states, k)), e
+        assert np.array_equal(cnt[:, e], rc[:, k]), e
