@@ -380,7 +380,8 @@ def bench_paper_config(args, torch, fs, firegen):
 def bench_uneven(args, torch, fs, firegen):
     """The uneven batch: 4096 envs with sides in {64, 128, 256, 512}, 300
     steps, one 5 x 5 suppression drop per env per step, in-kernel counts; the
-    dense plan and the autotuner's choice."""
+    dense plan, the autotuner's one plan for the batch and its per-size-class
+    plans."""
     batch, params, T, seed, act = firegen.workload_uneven()
     sim = fs.FireSim.from_batch(batch, params, seed=seed)
     acts = torch.from_numpy(act).cuda()
@@ -419,8 +420,20 @@ def bench_uneven(args, torch, fs, firegen):
     ms2 = tm.ms() / 2
     out["autotuned"] = {"plan": {k: best[k] for k in keys}, "ms_per_pass": round(ms2, 3),
                         "value": cells * T / (ms2 / 1e3)}
-    log("[bench] uneven: dense %.2f ms (%.3e cell-updates/s, %.0f GB/s at 10 B), autotuned %s %.2f ms"
-        % (ms, rate, STOCH_BYTES_PER_CELL * rate / 1e9, out["autotuned"]["plan"], ms2))
+    # one plan per size class (sides 64 / 128 / 256 / 512), each class tuned alone
+    sim.states.copy_(init)
+    sim.t = 0
+    cls = sim.autotune_classes(T_probe=50, allow_skip=True, allow_sparse=True)
+    run(1)
+    torch.cuda.synchronize()
+    with StepTimer(torch, stream) as tm:
+        run(2)
+    ms3 = tm.ms() / 2
+    out["per_class"] = {"classes": [{"size_class": c["size_class"], "n_env": c["n_env"], "plan": c["plan"],
+                                     "tuned_ms_per_step": round(c["ms_per_step"], 4)} for c in cls],
+                        "ms_per_pass": round(ms3, 3), "value": cells * T / (ms3 / 1e3)}
+    log("[bench] uneven: dense %.2f ms (%.3e cell-updates/s, %.0f GB/s at 10 B), autotuned %s %.2f ms, "
+        "per-class %.2f ms" % (ms, rate, STOCH_BYTES_PER_CELL * rate / 1e9, out["autotuned"]["plan"], ms2, ms3))
     return out
 
 

@@ -330,8 +330,9 @@ int sim_autotune(sim_handle* h, const uint8_t* states, int32_t T_probe, int32_t 
  * 0: <= 32, 1: <= 64, 2: <= 128, 3: <= 256, 4: <= 512, 5: <= 1024,
  * 6: <= 2048, 7: above).  With class plans set, sim_step, sim_step_history
  * and the multi-launch path of sim_rl_step run the envs of each class with
- * that class's plan, class after class on the caller's stream (the results
- * stay bit-identical: envs never interact).  The handle-wide graph flag
+ * that class's plan, the classes concurrently on streams of the handle's
+ * that fork from the caller's stream and join it again before the call's
+ * later work (the results stay bit-identical: envs never interact).  The handle-wide graph flag
  * still applies (the launches of all classes form one graph), and the
  * handle-wide plan's sparse flag still drives sim_step_relaxed_bwd.
  * sim_set_plan and sim_autotune drop the class plans (one plan for all envs

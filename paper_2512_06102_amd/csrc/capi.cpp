@@ -117,6 +117,10 @@ struct sim_handle {
     // the whole batch under `plan`, or (when non-empty) its size classes under their own plans
     PlanGroup all;
     std::vector<PlanGroup> classes;
+    // the classes run concurrently: one stream each, forked from and joined
+    // to the caller's stream by events (one per class, plus the fork)
+    std::vector<hipStream_t> class_streams;
+    std::vector<hipEvent_t> class_events;
     // wind series (caller-owned device memory, indexed by the absolute step)
     const float* series_env = nullptr;   // [series_T][n_env][3]
     const float* series_cell = nullptr;  // [series_T][3][n_cells]
@@ -204,6 +208,8 @@ void free_all(sim_handle* h)
         if (p) (void)hipFree(p);
     free_group(h->all);
     for (PlanGroup& g : h->classes) free_group(g);
+    for (hipStream_t cs : h->class_streams) (void)hipStreamDestroy(cs);
+    for (hipEvent_t ev : h->class_events) (void)hipEventDestroy(ev);
     if (h->graph.exec) (void)hipGraphExecDestroy(h->graph.exec);
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     relaxed_free(h->relaxed);
@@ -469,17 +475,30 @@ hipError_t enqueue_group(sim_handle* h, PlanGroup& g, hipStream_t s, uint8_t* st
 }
 
 // Enqueue one sim_step call: counts cleared, then each active group's steps.
+// Size classes touch disjoint cells (and count rows), so each runs on its own
+// stream, forked from s after the clear and joined back to s.
 hipError_t enqueue_steps(sim_handle* h, hipStream_t s, uint8_t* states, const int32_t* actions,
                          int32_t T, int32_t* counts, uint8_t* history = nullptr,
                          const int32_t* drop = nullptr)
 {
-    if (counts) {
-        const hipError_t e = launch_fill_i32(s, counts, (int64_t)T * h->n_env, 0);
-        if (e != hipSuccess) return e;
-    }
-    for (PlanGroup* g : active_groups(h)) {
-        const hipError_t e = enqueue_group(h, *g, s, states, actions, T, counts, history, drop);
-        if (e != hipSuccess) return e;
+    hipError_t e;
+    if (counts && (e = launch_fill_i32(s, counts, (int64_t)T * h->n_env, 0)) != hipSuccess) return e;
+    const std::vector<PlanGroup*> groups = active_groups(h);
+    if (groups.size() == 1 || h->class_streams.size() != groups.size())
+        for (PlanGroup* g : groups) {
+            if ((e = enqueue_group(h, *g, s, states, actions, T, counts, history, drop)) != hipSuccess) return e;
+        }
+    else {
+        hipEvent_t fork = h->class_events.back();
+        if ((e = hipEventRecord(fork, s)) != hipSuccess) return e;
+        for (size_t i = 0; i < groups.size(); ++i) {
+            hipStream_t cs = h->class_streams[i];
+            if ((e = hipStreamWaitEvent(cs, fork, 0)) != hipSuccess) return e;
+            if ((e = enqueue_group(h, *groups[i], cs, states, actions, T, counts, history, drop)) != hipSuccess)
+                return e;
+            if ((e = hipEventRecord(h->class_events[i], cs)) != hipSuccess) return e;
+            if ((e = hipStreamWaitEvent(s, h->class_events[i], 0)) != hipSuccess) return e;
+        }
     }
     return hipSuccess;
 }
@@ -879,6 +898,10 @@ void drop_classes(sim_handle* h)
 {
     for (PlanGroup& g : h->classes) free_group(g);
     h->classes.clear();
+    for (hipStream_t cs : h->class_streams) (void)hipStreamDestroy(cs);
+    for (hipEvent_t ev : h->class_events) (void)hipEventDestroy(ev);
+    h->class_streams.clear();
+    h->class_events.clear();
     h->graph.valid = false;
 }
 
@@ -902,6 +925,19 @@ int make_classes(sim_handle* h)
         }
         h->classes.push_back(g);  // owns d_list from here
         HIP_OR_FAIL(h, hipMemcpy(h->classes.back().d_list, g.envs.data(), bytes, hipMemcpyHostToDevice));
+    }
+    if (h->classes.size() > 1) {
+        // default-priority streams (no priority is ever set on them)
+        for (size_t i = 0; i < h->classes.size(); ++i) {
+            hipStream_t cs = nullptr;
+            HIP_OR_FAIL(h, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+            h->class_streams.push_back(cs);
+        }
+        for (size_t i = 0; i <= h->classes.size(); ++i) {
+            hipEvent_t ev = nullptr;
+            HIP_OR_FAIL(h, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+            h->class_events.push_back(ev);
+        }
     }
     return SIM_OK;
 }

@@ -18,13 +18,14 @@
 // gamma(v) = alpha_gamma g(v), g = (1 + veg[class]) (1 + den), to the 17
 // parameters.
 //
-// The forward works on 32 x 16 tiles with a one-cell halo in LDS.  The
-// adjoint's transpose stencil (Bbar(u) gathers the terms of the targets
-// around u, and those need B two cells away) runs in one launch per step on
-// 64 x 16 tiles, one wave each: lanes own columns, walk the rows, and pass
-// neighbouring values and terms by DPP lane shifts; terms that cross into
-// another tile go through an exchange record that the owning tile adds in the
-// next step.  Every sum runs in a fixed order (no atomics), so the gradient
+// Both directions work on 64 x 32 tiles (kAdjW x kAdjR) whose lanes own
+// columns and walk the rows, passing neighbouring values and terms by DPP
+// lane shifts, so each cell is loaded once per step.  The forward cuts a tile
+// into four 8-row bands, one wave each.  The adjoint's transpose stencil
+// (Bbar(u) gathers the terms of the targets around u, and those need B two
+// cells away) runs one wave per tile, one launch per step; terms that cross
+// into another tile go through an exchange record that the owning tile adds
+// in the next step.  Every sum runs in a fixed order (no atomics), so the gradient
 // is the same bits on every run.  Parameter gradients are summed per lane,
 // reduced per wave and added to the tile's own row of partial sums; a last
 // kernel sums the rows.
