@@ -573,6 +573,16 @@ def relaxed_case(args, torch, fs, firegen, batch, params, T, k, label, roofline)
             _, gU, _ = sim.relaxed_loss(U, Y, scale=1.0 / batch.n_env)
             t_b, _ = timed(lambda: sim.relaxed_bwd(theta, gU, None, T_, 1, ws1))
             launches[name] = (t_f, t_b)
+        # store-all: every state kept (checkpoint every step), so nothing is
+        # recomputed; the method's count is then 56 B per cell-step (fwd 24 + adj 32)
+        ms_sa, (_, _, grad_sa) = timed(lambda: fwd_bwd(T, 1, ws1))
+        cs_sa = float(batch.n_cells) * T / (ms_sa / 1e3)
+        out["store_all"] = {"ms_per_fwd_bwd": round(ms_sa, 3), "value": cs_sa,
+                            "workspace_GB": round(ws1.numel() / 1e9, 1),
+                            "hbm_frac_at_56B": round(cs_sa * 56 / 1e9 / HBM_PEAK_GBS, 4),
+                            "grad_max_abs_diff_vs_recompute": float((grad_sa - grad).abs().max())}
+        log("[bench] relaxed %s store-all (checkpoint every step): %.2f ms per fwd+bwd, %.3e cell-steps/s"
+            % (label.split(":")[0], ms_sa, cs_sa))
         del ws1
         kern = {}
         w = RELAXED_WIND_BYTES if wind else 0
