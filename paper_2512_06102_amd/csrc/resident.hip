@@ -96,7 +96,9 @@ __global__ __launch_bounds__(NT) void stoch_resident_kernel(
     uint32_t* nxt = cur + frame_cap;                        // F_{t+1}, framed
     float* sG = reinterpret_cast<float*>(nxt + frame_cap);  // fuel term g(v)
     float* sE = sG + cell_cap;                              // elevation
-    // front list: (cell | nbk << 16, the cell's Philox word >> 8)
+    // front list: (cell | its 3x3 burning window << 16, the cell's Philox
+    // word >> 8); the window holds bits c..c+2 of the up, middle and down row
+    // windows of the cell's dword (c = cell & 3)
     uint2* sL = reinterpret_cast<uint2*>(sE + cell_cap);
 
     // this wave's dwords [d_lo, d_hi) and front-list segment (4 d_lo onwards)
@@ -215,9 +217,10 @@ __global__ __launch_bounds__(NT) void stoch_resident_kernel(
             if (front) {
 #pragma unroll
                 for (int c = 0; c < 4; ++c)
-                    if ((front >> c) & 1u)
-                        sL[slot++] = make_uint2((uint32_t)(4 * i + c) | (direction_mask(up6, md6, dn6, c) << 16),
-                                                compu(w, c) >> 8);
+                    if ((front >> c) & 1u) {
+                        const uint32_t win = ((up6 >> c) & 7u) | (((md6 >> c) & 7u) << 3) | (((dn6 >> c) & 7u) << 6);
+                        sL[slot++] = make_uint2((uint32_t)(4 * i + c) | (win << 16), compu(w, c) >> 8);
+                    }
             }
             n_front += tot;
         }
@@ -228,7 +231,8 @@ __global__ __launch_bounds__(NT) void stoch_resident_kernel(
             for (uint32_t q = lane; q < n_front; q += 64) {
                 const uint2 entry = sL[4 * d_lo + q];
                 const int v = entry.x & 0xFFFF;
-                const uint32_t nbk = entry.x >> 16;
+                const uint32_t win = entry.x >> 16;
+                const uint32_t nbk = direction_mask(win & 7u, (win >> 3) & 7u, (win >> 6) & 7u, 0);
                 float g_u[8], E_u[8], V_u[8], Vx_u[8], Vy_u[8];
 #pragma unroll
                 for (int d = 0; d < 8; ++d) {
