@@ -2,13 +2,14 @@
 workloads to tests/golden/*.json (the GPU tests compare the whole 17-entry
 gradient with them).  Calls only the oracle and the input generators.
 
-    python tests/golden/make_relaxed_goldens.py [relaxed128] [relaxed2048_T100] [relaxed2048_T500]
+    python tests/golden/make_relaxed_goldens.py [relaxed128] [relaxed2048_T<T> ...]
 
 Setups (the benchmark's):
   relaxed128        256 envs of 128 x 128, T = 100, checkpoints every 10.
   relaxed2048_T100  1 env of 2048 x 2048 with per-cell wind, T = 100.
-  relaxed2048_T500  the same env, T = 500 (the large workload's horizon);
-                    the fp64 forward keeps every state: about 37 GB of RAM.
+  relaxed2048_T<T>  the same env at T = 200, 300, 400 or 500 (the large
+                    workload's horizon); the fp64 forward keeps every state:
+                    about 7.4 GB of RAM per 100 steps.
 Target scar Y: BURNING or BURNT after a stochastic oracle run of T steps with
 the workload's parameters and Philox seed 0.  The gradient is taken at
 p_base, alpha_w1, alpha_w2, alpha_s times 1.2 (the others unchanged), on the

@@ -256,7 +256,7 @@ def test_full_size_relaxed128():
         assert np.max(np.abs(batch.env_view(U, e) - Us[-1])) <= 1e-5, e
 
 
-@pytest.mark.parametrize("T", [100, 500])
+@pytest.mark.parametrize("T", [100, 200, 300, 400, 500])
 def test_relaxed2048_whole_gradient(T):
     """The large relaxed workload (1 env of 2048x2048, per-cell wind,
     checkpoints every 10) in the benchmark's setup at T = 100 and at its
