@@ -162,3 +162,31 @@ def test_uneven_workload_per_class_plans_sampled_envs():
     for k, e in enumerate(sample):
         assert np.array_equal(batch.env_view(got, e), sub.env_view(ref.states, k)), e
         assert np.array_equal(cnt[:, e], rc[:, k]), e
+
+
+@pytest.mark.parametrize("per_cell", [False, True])
+def test_class_plans_with_wind_series_and_slope_angle(per_cell):
+    """Class plans under a per-env or per-cell wind series and the slope-angle
+    variant, with drops, over two calls (the series indexed by the absolute
+    step across them)."""
+    sizes = [(20, 20)] * 12 + [(64, 64)] * 4 + [(100, 120)] * 2 + [(256, 200)]
+    batch = firegen.landscape_batch(72, sizes, per_cell_wind=per_cell)
+    params = firegen.Params(p_base=0.85, veg=_veg(72), slope_mode=1)
+    T = 33
+    ser = firegen.wind_series(9, batch, T, per_cell=per_cell, speed_step=1.0, turn_step=0.3)
+    kw = {"wind_cell_series" if per_cell else "wind_env_series": ser}
+    act = firegen.random_actions(33, batch, T, p_none=0.4)
+    ref = oracle.Sim(batch, params, seed=24)
+    want = ref.step(T, actions=act, counts=True, threads=8, **kw)
+    sim = fs.FireSim.from_batch(batch, params, seed=24)
+    sim.set_plan(graph=1)
+    dev = torch.from_numpy(ser).cuda()
+    sim.set_wind_series(cell_series=dev) if per_cell else sim.set_wind_series(env_series=dev)
+    for c, plan in {0: dict(resident=256), 1: dict(resident=512), 2: dict(tile_width=64, temporal=8, skip_static=1),
+                    3: dict(tile_rows=1, tile_width=256, skip_static=1, sparse=1)}.items():
+        sim.set_class_plan(c, **plan)
+    got = [sim.step(n, actions=torch.from_numpy(np.ascontiguousarray(a)), counts=True).cpu().numpy()
+           for n, a in ((13, act[:13]), (T - 13, act[13:]))]
+    torch.cuda.synchronize()
+    assert np.array_equal(sim.states.cpu().numpy(), ref.states)
+    assert np.array_equal(np.concatenate(got), want)

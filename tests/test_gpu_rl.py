@@ -20,7 +20,8 @@ def _agents_np(env):
 # Batches: 20 x 20 envs (one launch per step holds 2 dwords per lane); envs
 # with W % 4 != 0 (the separate launches, whatever single_launch says); up to
 # 64 x 64 (16 dwords per lane); 32 x 32 (4 dwords per lane); per-cell wind;
-# per-env and per-cell wind series.
+# per-env and per-cell wind series; per-size-class plans (resident for the
+# 20 x 20 envs) in a graph.
 @pytest.mark.parametrize("single_launch", [True, False])
 @pytest.mark.parametrize("sizes,plan,wind", [
     ([(20, 20)] * 96, dict(graph=0), None),
@@ -30,6 +31,9 @@ def _agents_np(env):
     ([(32, 32)] * 12 + [(20, 20)] * 12, dict(graph=0), "cell"),
     ([(20, 20)] * 24 + [(28, 16)], dict(graph=0), "env_series"),
     ([(20, 20)] * 24 + [(12, 36)], dict(graph=0), "cell_series"),
+    ([(20, 20)] * 30 + [(64, 64), (32, 48)],
+     dict(graph=1, classes={0: dict(resident=64), 1: dict(tile_rows=2, tile_width=64, skip_static=1, sparse=1)}),
+     "env_series"),
 ])
 def test_rl_episodes_match_oracle(sizes, plan, wind, single_launch):
     batch = firegen.landscape_batch(31, sizes, per_cell_wind=wind in ("cell", "cell_series"))
@@ -42,7 +46,11 @@ def test_rl_episodes_match_oracle(sizes, plan, wind, single_launch):
     ref = rl.RLEnvs(batch, params, 77, cfg, wind_env_series=ser if wind == "env_series" else None,
                     wind_cell_series=ser if wind == "cell_series" else None)
     sim = fs.FireSim.from_batch(batch, params, seed=77)
+    plan = dict(plan)
+    classes = plan.pop("classes", {})
     sim.set_plan(**plan)
+    for c, cp in classes.items():  # per-size-class plans (the multi-launch path runs them)
+        sim.set_class_plan(c, **cp)
     if ser is not None:
         dev = torch.from_numpy(ser).cuda()
         sim.set_wind_series(cell_series=dev) if wind == "cell_series" else sim.set_wind_series(env_series=dev)
