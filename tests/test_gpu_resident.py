@@ -176,3 +176,26 @@ def test_autotune_tries_resident_plans():
     big = fs.FireSim.from_batch(firegen.landscape_batch(70, [(128, 128)]), firegen.Params(), seed=0)
     res = big.autotune(T_probe=5, allow_skip=True, allow_sparse=True)
     assert all(p["resident"] == 0 for p, _ in res)
+
+
+@pytest.mark.parametrize("per_cell", [False, True])
+def test_long_wind_series_across_staging_chunks(per_cell):
+    """Drops and wind exponents are staged 64 steps at a time: a 150-step
+    per-env (or per-cell) wind series with drops, split 70 + 80 so that both
+    calls cross a chunk boundary at a step that is not a multiple of 64 of
+    the run."""
+    batch = firegen.landscape_batch(73, [(64, 64)] * 6 + [(20, 20)] * 10, per_cell_wind=per_cell)
+    params = firegen.Params(p_base=0.7, veg=_veg(73))
+    T = 150
+    ser = firegen.wind_series(10, batch, T, per_cell=per_cell, speed_step=1.5, turn_step=0.4)
+    kw = {"wind_cell_series" if per_cell else "wind_env_series": ser}
+    act = firegen.random_actions(25, batch, T, p_none=0.6)
+    ref = oracle.Sim(batch, params, seed=14)
+    want = ref.step(T, actions=act, counts=True, threads=8, **kw)
+    sim = fs.FireSim.from_batch(batch, params, seed=14)
+    sim.set_plan(resident=512, graph=1)
+    dev = torch.from_numpy(ser).cuda()
+    sim.set_wind_series(cell_series=dev) if per_cell else sim.set_wind_series(env_series=dev)
+    got = [sim.step(n, actions=torch.from_numpy(np.ascontiguousarray(a)), counts=True).cpu().numpy()
+           for n, a in ((70, act[:70]), (T - 70, act[70:]))]
+    _check(sim, ref, np.concatenate(got), want, per_cell)
