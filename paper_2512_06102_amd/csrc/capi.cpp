@@ -484,7 +484,8 @@ hipError_t enqueue_steps(sim_handle* h, hipStream_t s, uint8_t* states, const in
     hipError_t e;
     if (counts && (e = launch_fill_i32(s, counts, (int64_t)T * h->n_env, 0)) != hipSuccess) return e;
     const std::vector<PlanGroup*> groups = active_groups(h);
-    if (groups.size() == 1 || h->class_streams.size() != groups.size())
+    if (groups.size() == 1 || h->class_streams.size() != groups.size() ||
+        h->class_events.size() != groups.size() + 1)
         for (PlanGroup* g : groups) {
             if ((e = enqueue_group(h, *g, s, states, actions, T, counts, history, drop)) != hipSuccess) return e;
         }
@@ -905,8 +906,21 @@ void drop_classes(sim_handle* h)
     h->graph.valid = false;
 }
 
-// Split the batch into its size classes, each under the handle-wide plan.
+// Split the batch into its size classes, each under the handle-wide plan;
+// all or nothing (on an error the handle keeps one plan for all envs).
+int make_classes_or_partial(sim_handle* h);
 int make_classes(sim_handle* h)
+{
+    const int rc = make_classes_or_partial(h);
+    if (rc != SIM_OK) {
+        const std::string err = h->err;
+        drop_classes(h);
+        h->err = err;
+    }
+    return rc;
+}
+
+int make_classes_or_partial(sim_handle* h)
 {
     std::vector<PlanGroup> cls(SIM_N_SIZE_CLASSES);
     for (int32_t e = 0; e < h->n_env; ++e) cls[size_class_of(h->envs[e].H, h->envs[e].W)].envs.push_back(e);
@@ -918,11 +932,7 @@ int make_classes(sim_handle* h)
         g.plan = h->plan;
         describe_group(h, g);
         const size_t bytes = g.envs.size() * sizeof(int32_t);
-        if (hipMalloc(&g.d_list, bytes) != hipSuccess) {
-            for (PlanGroup& x : h->classes) free_group(x);
-            h->classes.clear();
-            return fail(h, SIM_ENOMEM, "size-class env list allocation failed");
-        }
+        if (hipMalloc(&g.d_list, bytes) != hipSuccess) return fail(h, SIM_ENOMEM, "size-class env list allocation failed");
         h->classes.push_back(g);  // owns d_list from here
         HIP_OR_FAIL(h, hipMemcpy(h->classes.back().d_list, g.envs.data(), bytes, hipMemcpyHostToDevice));
     }
