@@ -372,6 +372,22 @@ def bench_paper_config(args, torch, fs, firegen):
     out["unit"] = "env-steps/s"
     out["note"] = ("context only: the paper quotes its peak on an NVIDIA A100 in a garbled form; "
                    "its literal reading is 2.5^16 = 2.3e6 env-steps/s")
+    # the paper's throughput-versus-batch curve: 200 steps of n envs of 64 x 64, autotuned each
+    sweep = []
+    for n in (1, 4, 16, 64, 256, 1024, 4096):
+        b = firegen.landscape_batch(7, [(64, 64)] * n)
+        s2 = fs.FireSim.from_batch(b, params, seed=0)
+        i2 = s2.states.clone()
+        s2.autotune(T_probe=T, allow_skip=True, allow_sparse=True)
+        p2 = s2.plan()
+        s2.set_plan(**{k: p2[k] for k in keys}, graph=1)
+        ms2, _ = timed_runs(torch, stream, s2, i2, T, max(2, args.steps), 1)
+        sweep.append({"n_env": n, "plan": {k: p2[k] for k in keys}, "ms_per_200_steps": round(ms2, 4),
+                      "env_steps_per_s": n * T / (ms2 / 1e3)})
+        log("[bench] paper sweep %4d envs of 64x64: %s %.3f ms per 200 steps, %.3e env-steps/s"
+            % (n, {k: p2[k] for k in keys if p2[k]}, ms2, n * T / (ms2 / 1e3)))
+        del s2, i2, b
+    out["sweep"] = sweep
     log("[bench] paper setting 64 x 64^2: dense %.3f ms, autotuned %s %.3f ms per 200 steps"
         % (out["dense"]["ms_per_200_steps"], out["autotuned"]["plan"], ms))
     return out
