@@ -425,7 +425,10 @@ def bench_uneven(args, torch, fs, firegen):
                     "hbm_frac_at_10B": round(STOCH_BYTES_PER_CELL * rate / 1e9 / HBM_PEAK_GBS, 4)}
     sim.states.copy_(init)
     sim.t = 0
-    sim.autotune(T_probe=50, allow_skip=True, allow_sparse=True)
+    # both tuners probe 150 steps: long enough for the fires to reach the sizes
+    # that decide between plans (a 50-step probe picks 256-wide tiles for the
+    # 512^2 envs, which lose later in the run)
+    sim.autotune(T_probe=150, allow_skip=True, allow_sparse=True)
     best = sim.plan()
     keys = ("tile_rows", "tile_width", "temporal", "skip_static", "sparse", "resident")
     sim.set_plan(**{k: best[k] for k in keys}, graph=1)
@@ -439,7 +442,7 @@ def bench_uneven(args, torch, fs, firegen):
     # one plan per size class (sides 64 / 128 / 256 / 512), each class tuned alone
     sim.states.copy_(init)
     sim.t = 0
-    cls = sim.autotune_classes(T_probe=50, allow_skip=True, allow_sparse=True)
+    cls = sim.autotune_classes(T_probe=150, allow_skip=True, allow_sparse=True)
     run(1)
     torch.cuda.synchronize()
     with StepTimer(torch, stream) as tm:
@@ -520,7 +523,10 @@ def bench_large(args, torch, fs, firegen):
                     "hbm_frac_at_22B": round(bpc * rate / 1e9 / HBM_PEAK_GBS, 4)}
     sim.states.copy_(init)
     sim.t = 0
-    sim.autotune(T_probe=50, allow_skip=True, allow_sparse=True)
+    # both tuners probe 150 steps: long enough for the fires to reach the sizes
+    # that decide between plans (a 50-step probe picks 256-wide tiles for the
+    # 512^2 envs, which lose later in the run)
+    sim.autotune(T_probe=150, allow_skip=True, allow_sparse=True)
     best = sim.plan()
     keys = ("tile_rows", "tile_width", "temporal", "skip_static", "sparse", "resident")
     sim.set_plan(**{k: best[k] for k in keys}, graph=1)
