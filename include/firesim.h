@@ -309,7 +309,10 @@ int sim_get_plan(const sim_handle* h, sim_plan* plan);
  * 64/256/512/1024)
  * for T_probe steps of this batch starting from `states` (device, read only)
  * at the handle's step counter, and makes the fastest the handle's plan
- * (graph flag kept).
+ * (graph flag kept).  Plans are ranked on those steps alone, and which plan
+ * wins depends on how much of each env is burning: probe a representative
+ * stretch of the run (on the 4096-env uneven batch, 50 steps from the
+ * initial fires pick a plan 13% slower over 300 steps than a 150-step probe).
  * Neither `states` nor the step counter change; the handle allocates and
  * frees one scratch state buffer.  Synchronises `stream`.
  *  results      host array of max_results entries or NULL: the plans tried,

@@ -354,7 +354,9 @@ class FireSim:
 
     def autotune(self, T_probe: int = 10, allow_skip: bool = True, allow_sparse: bool = False) -> list:
         """Time every candidate plan on this batch (states and step counter
-        unchanged) and adopt the fastest; returns [(plan dict, ms/step)]."""
+        unchanged) and adopt the fastest; returns [(plan dict, ms/step)].
+        Plans are ranked on the T_probe steps alone: probe a representative
+        stretch of the run (the fire sizes decide between plans)."""
         res = (SimTuneResult * 32)()
         n = ctypes.c_int32(0)
         _check(lib().sim_autotune(self.handle, _ptr(self.states), int(T_probe), int(allow_skip),
