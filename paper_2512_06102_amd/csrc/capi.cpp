@@ -320,6 +320,25 @@ int ensure_tiles(sim_handle* h)
     return SIM_OK;
 }
 
+// The resident kernel's dynamic-LDS limit is an attribute of the kernel
+// functions, shared by every handle in the process: it is raised once per
+// device to everything the device allows beside the kernel's static LDS, so
+// that no batch lowers it under another's.  Returns whether that worked.
+constexpr size_t kResidentStaticLds = 2560;
+bool resident_lds_allowed(int device, int max_lds)
+{
+    static std::mutex mu;
+    static int state[kMaxDevices] = {};  // 0 not tried, 1 set, 2 refused
+    if (device < 0 || device >= kMaxDevices) return false;
+    std::lock_guard<std::mutex> lock(mu);
+    if (state[device] == 0) {
+        const bool ok = resident_set_lds_limit(max_lds - (int)kResidentStaticLds) == hipSuccess;
+        if (!ok) (void)hipGetLastError();  // not sticky: the batches just do not take the plan
+        state[device] = ok ? 1 : 2;
+    }
+    return state[device] == 1;
+}
+
 // Size class of an env (see SIM_N_SIZE_CLASSES).
 int size_class_of(int H, int W)
 {
@@ -355,11 +374,8 @@ void describe_group(sim_handle* h, PlanGroup& g)
         g.res.cell_cap = (int32_t)max_cells;
         // the kernel's own static LDS (under 2.5 KiB) comes on top of the dynamic part
         const size_t need = resident_lds_bytes(g.res);
-        g.res.fits = need + 2560 <= (size_t)max_lds;
-        if (g.res.fits && resident_set_lds_limit((int)need) != hipSuccess) {
-            (void)hipGetLastError();  // not sticky: these envs just do not take the plan
-            g.res.fits = false;
-        }
+        g.res.fits = need + kResidentStaticLds <= (size_t)max_lds && resident_lds_allowed(h->device, max_lds);
+
     }
 }
 

@@ -199,3 +199,25 @@ def test_long_wind_series_across_staging_chunks(per_cell):
     got = [sim.step(n, actions=torch.from_numpy(np.ascontiguousarray(a)), counts=True).cpu().numpy()
            for n, a in ((70, act[:70]), (T - 70, act[70:]))]
     _check(sim, ref, np.concatenate(got), want, per_cell)
+
+
+def test_handles_of_different_sizes_share_the_kernel():
+    """The kernel's LDS limit is shared by all handles: a handle of 64 x 64
+    envs still runs its resident plan after a handle of 20 x 20 envs was
+    created (and stepped) after it."""
+    big = firegen.landscape_batch(74, [(64, 64)] * 8)
+    small = firegen.landscape_batch(75, [(20, 20)] * 8)
+    params = firegen.Params(p_base=0.8, veg=_veg(74))
+    sim_big = fs.FireSim.from_batch(big, params, seed=15)
+    sim_big.set_plan(resident=1024)
+    sim_small = fs.FireSim.from_batch(small, params, seed=15)
+    sim_small.set_plan(resident=64)
+    sim_small.step(20)
+    got = sim_big.step(40, counts=True).cpu().numpy()
+    ref = oracle.Sim(big, params, seed=15)
+    want = ref.step(40, counts=True, threads=8)
+    _check(sim_big, ref, got, want, "big after small")
+    ref_s = oracle.Sim(small, params, seed=15)
+    ref_s.step(20, threads=8)
+    torch.cuda.synchronize()
+    assert np.array_equal(sim_small.states.cpu().numpy(), ref_s.states)
