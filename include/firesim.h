@@ -254,8 +254,12 @@ int sim_set_step(sim_handle* h, uint64_t t);
 /* Launch plan of sim_step, and of sim_step_relaxed_bwd for `sparse` (results
  * never depend on it, up to the summation order of the relaxed gradient).
  * A new handle starts with {tile_rows 4, tile_width 64, temporal 1,
- * skip_static 1, sparse 1, graph 0, resident 0}: fuel and elevation are read only at
- * front cells and tiles with no fire in reach are skipped.  The dense plan
+ * skip_static 1, sparse 1, graph 0, resident r}: fuel and elevation are read only at
+ * front cells and tiles with no fire in reach are skipped.  r is 0 unless
+ * every env fits the resident plan (see below) and the batch needs at most
+ * two rounds of its workgroups across the device; then r follows the largest
+ * env: 1024 when it has at least 4096 cells and there are no more envs than
+ * CUs, else 512 from 2048 cells, 256 from 512 cells and 64 below.  The dense plan
  * {4, 256, 1, 0, 0, 0, 0} streams every cell's state, fuel and elevation each
  * step (the HBM roofline reference).
  *  tile_rows    rows of 4-cell groups each lane owns in its tile (1, 2, 4 or 8),

@@ -221,3 +221,19 @@ def test_handles_of_different_sizes_share_the_kernel():
     ref_s.step(20, threads=8)
     torch.cuda.synchronize()
     assert np.array_equal(sim_small.states.cpu().numpy(), ref_s.states)
+
+
+def test_default_plan_takes_resident_for_small_envs():
+    """A new handle starts with the resident plan when every env fits it and
+    the batch needs at most two rounds of workgroups (the measured choices:
+    1024 lanes for 64 envs of 64 x 64, 512 for 1024 of them, none for 4096,
+    64 lanes for 20 x 20 envs), and with the tiled plan otherwise."""
+    params = firegen.Params()
+    cases = [([(64, 64)] * 64, 1024), ([(64, 64)] * 1024, 512), ([(64, 64)] * 4096, 0),
+             ([(20, 20)] * 512, 64), ([(40, 40)] * 64, 256), ([(128, 128)] * 4, 0), ([(64, 64), (40, 42)], 0)]
+    for sizes, want in cases:
+        sim = fs.FireSim.from_batch(firegen.landscape_batch(76, sizes), params, seed=0)
+        plan = sim.plan()
+        assert plan["resident"] == want, (sizes[0], len(sizes), plan)
+        assert (plan["tile_rows"], plan["tile_width"], plan["skip_static"], plan["sparse"]) == (4, 64, 1, 1)
+        del sim
