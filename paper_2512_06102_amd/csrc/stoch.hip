@@ -245,6 +245,36 @@ __global__ __launch_bounds__(kWave) void stoch_step_kernel(
         }
     }
 
+    // -- 2b. no burning cell in the tile or its one-cell halo: no cell of the
+    //        tile can change (a drop only removes fire); store the state and stop
+    {
+        uint32_t any_burn = 0;
+#pragma unroll
+        for (int j = 0; j < RT + 2; ++j) any_burn |= burning_flags(s[j]) | burning_flags(hl[j]) | burning_flags(hr[j]);
+        if (!__any(any_burn != 0u)) {
+#pragma unroll
+            for (int m = 0; m < RT; ++m) {
+                const int gi = row0 + m;
+                if (!(gi < H && gj0 < W)) continue;
+                uint8_t* o = (dst + base) + (uint32_t)(gi * W + gj0);
+                if constexpr (ALIGNED && !SKIP) {
+                    __builtin_nontemporal_store(s[m + 1], reinterpret_cast<uint32_t*>(o));
+                } else if constexpr (ALIGNED) {
+                    *reinterpret_cast<uint32_t*>(o) = s[m + 1];
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 4; ++c)
+                        if (gj0 + c < W) o[c] = (uint8_t)(s[m + 1] >> (8 * c));
+                }
+            }
+            if (SP.burn_next && lane == 0) {
+                SP.burn_next[tile] = 0;
+                SP.eq[tile] = 0;
+            }
+            return;
+        }
+    }
+
     // -- 3. neighbour dwords across the row segment, then flags of own cells:
     //       burning (bits 0-3), front (bits 4-7) and the burning-neighbour
     //       masks of the four cells (8 bits each)
