@@ -526,7 +526,9 @@ def bench_large(args, torch, fs, firegen):
     # both tuners probe 150 steps: long enough for the fires to reach the sizes
     # that decide between plans (a 50-step probe picks 256-wide tiles for the
     # 512^2 envs, which lose later in the run)
-    sim.autotune(T_probe=150, allow_skip=True, allow_sparse=True)
+    # the whole run: the fires grow for most of the 1000 steps, and a short probe
+    # from the initial fires ranks the plans by their cost on small fronts
+    sim.autotune(T_probe=T, allow_skip=True, allow_sparse=True)
     best = sim.plan()
     keys = ("tile_rows", "tile_width", "temporal", "skip_static", "sparse", "resident")
     sim.set_plan(**{k: best[k] for k in keys}, graph=1)
