@@ -79,7 +79,7 @@ __global__ __launch_bounds__(kWave) void stoch_step_kernel(
     uint8_t* __restrict__ dst, const uint32_t* __restrict__ t_base, uint32_t step,
     const int32_t* __restrict__ actions_row, int32_t* __restrict__ counts_row, SparseArgs SP)
 {
-    __shared__ uint32_t lds_cell[kCellCap];   // lane | m << 6 | c << 9 | nbk << 11 | group << 19
+    __shared__ uint32_t lds_cell[kCellCap];   // lane | m << 6 | c << 9 | 3x3 window << 11 | group << 20
     __shared__ uint16_t lds_group[kGroupCap]; // lane | m << 6
     __shared__ float lds_u[kGroupCap * 4];    // uniforms of each listed group's cells
     __shared__ uint8_t lds_dec[kCellCap];     // ignition decision of each listed cell
@@ -276,8 +276,7 @@ __global__ __launch_bounds__(kWave) void stoch_step_kernel(
     }
 
     // -- 3. neighbour dwords across the row segment, then flags of own cells:
-    //       burning (bits 0-3), front (bits 4-7) and the burning-neighbour
-    //       masks of the four cells (8 bits each)
+    //       burning (bits 0-3) and front (bits 4-7)
     uint32_t win[RT + 2];  // burning bits of the 6-cell window of each loaded row
 #pragma unroll
     for (int j = 0; j < RT + 2; ++j) {
@@ -286,27 +285,34 @@ __global__ __launch_bounds__(kWave) void stoch_step_kernel(
         if (tx == GX - 1) right = hr[j];
         win[j] = row_window(left, s[j], right);
     }
-    uint32_t flags[RT], nbks[RT];
+    uint32_t flags[RT];
     uint32_t my_cells = 0, my_groups = 0;
 #pragma unroll
     for (int m = 0; m < RT; ++m) {
         flags[m] = 0;
-        nbks[m] = 0;
         if (!(row0 + m < H && gj0 < W)) continue;
         const uint32_t up6 = win[m], md6 = win[m + 1], dn6 = win[m + 2];
         const uint32_t ud = up6 | dn6;
         const uint32_t near = (ud | (ud >> 1) | (ud >> 2) | md6 | (md6 >> 2)) & 0xFu;
         const uint32_t burn = pack4(burning_flags(s[m + 1]));
         const uint32_t front = pack4(flammable_flags(s[m + 1])) & near;
-        uint32_t nb = 0;
-#pragma unroll
-        for (int c = 0; c < 4; ++c)
-            if ((front >> c) & 1u) nb |= direction_mask(up6, md6, dn6, c) << (8 * c);
         flags[m] = burn | (front << 4);
-        nbks[m] = nb;
         my_cells += __popc(front);
         my_groups += (burn | front) != 0u;
     }
+    // the row windows, 6 bits each, packed five to a register for the list
+    // and the overflow path after the scan (the empty asm keeps the compiler
+    // from reading the unpacked copies instead, which would hold one
+    // register per row until the end of the kernel)
+    constexpr int kWinRegs = (RT + 2 + 4) / 5;
+    uint32_t wpk[kWinRegs];
+#pragma unroll
+    for (int i = 0; i < kWinRegs; ++i) wpk[i] = 0;
+#pragma unroll
+    for (int j = 0; j < RT + 2; ++j) wpk[j / 5] |= win[j] << (6 * (j % 5));
+#pragma unroll
+    for (int i = 0; i < kWinRegs; ++i) asm volatile("" : "+v"(wpk[i]));
+    auto row_win = [&](int j) { return (wpk[j / 5] >> (6 * (j % 5))) & 0x3Fu; };
     __syncthreads();  // lds_ew visible (one wave: no waiting on other waves)
 
     // -- 4. list front cells and draw groups across the wave
@@ -325,11 +331,17 @@ __global__ __launch_bounds__(kWave) void stoch_step_kernel(
             if (!(burn | front)) continue;
             slot[m] = gidx | (ci << 16);
             lds_group[gidx] = (uint16_t)(lane | (m << 6));
+            // each front cell is listed with its 3x3 burning window (bits
+            // c..c+2 of the up, middle and down row windows); its direction
+            // mask is derived where the list is evaluated, on every lane
 #pragma unroll
             for (int c = 0; c < 4; ++c)
-                if ((front >> c) & 1u)
-                    lds_cell[ci++] = (uint32_t)lane | ((uint32_t)m << 6) | ((uint32_t)c << 9) |
-                                     (((nbks[m] >> (8 * c)) & 0xFFu) << 11) | (gidx << 19);
+                if ((front >> c) & 1u) {
+                    const uint32_t w9 = ((row_win(m) >> c) & 7u) | (((row_win(m + 1) >> c) & 7u) << 3) |
+                                        (((row_win(m + 2) >> c) & 7u) << 6);
+                    lds_cell[ci++] = (uint32_t)lane | ((uint32_t)m << 6) | ((uint32_t)c << 9) | (w9 << 11) |
+                                     (gidx << 20);
+                }
             ++gidx;
         }
         __syncthreads();
@@ -350,7 +362,8 @@ __global__ __launch_bounds__(kWave) void stoch_step_kernel(
         for (uint32_t cq = lane; cq < n_cells; cq += kWave) {
             const uint32_t e = lds_cell[cq];
             const int olane = e & 63, m = (e >> 6) & 7, c = (e >> 9) & 3;
-            const uint32_t nbk = (e >> 11) & 0xFF, gq = e >> 19;
+            const uint32_t w9 = (e >> 11) & 0x1FFu, gq = e >> 20;
+            const uint32_t nbk = direction_mask(w9 & 7u, (w9 >> 3) & 7u, (w9 >> 6) & 7u, 0);
             const int gi = td.r0 + (olane >> gx_log) * RT + m;
             const int gj = td.c0 + 4 * (olane & (GX - 1)) + c;
             const float p = ignite_prob<WIND_CELL>(nbk, base + (int64_t)gi * W + gj, W, F, A, lds_ew);
@@ -394,7 +407,7 @@ __global__ __launch_bounds__(kWave) void stoch_step_kernel(
                     if ((burn >> c) & 1u)
                         next = u < A.p_continue ? kBurning : kBurnt;
                     else if ((front >> c) & 1u)
-                        next = u < ignite_prob<WIND_CELL>((nbks[m] >> (8 * c)) & 0xFFu,
+                        next = u < ignite_prob<WIND_CELL>(direction_mask(row_win(m), row_win(m + 1), row_win(m + 2), c),
                                                           base + n0 + c, W, F, A, lds_ew)
                                    ? kBurning
                                    : kFlammable;
