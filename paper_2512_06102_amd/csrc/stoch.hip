@@ -54,6 +54,45 @@ __device__ __forceinline__ void keep_loaded(const float4& v)
     asm volatile("" ::"v"(v.x), "v"(v.y), "v"(v.z), "v"(v.w));
 }
 
+// x of lane - 1 / lane + 1 of the wave by a DPP wave shift (0 where that
+// lane does not exist); every lane must be active
+__device__ __forceinline__ uint32_t from_lane_below(uint32_t x)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x138 /* wave_shr:1 */, 0xF, 0xF, false);
+}
+__device__ __forceinline__ uint32_t from_lane_above(uint32_t x)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x130 /* wave_shl:1 */, 0xF, 0xF, false);
+}
+
+constexpr int bit_width(int v) { return v == 0 ? 0 : 1 + bit_width(v >> 1); }
+
+// Exclusive prefix sum across the wave of a per-lane value below 2^NB, and
+// the wave total: one ballot per bit plane (no LDS round trips)
+template <int NB>
+__device__ __forceinline__ uint32_t ballot_exclusive_scan(uint32_t x, uint32_t& total)
+{
+    uint32_t off = 0, tot = 0;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const uint64_t m = __ballot((x >> b) & 1u);
+        off += __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u)) << b;
+        tot += (uint32_t)__popcll(m) << b;
+    }
+    total = tot;
+    return off;
+}
+
+// Wave total of a per-lane value below 2^NB
+template <int NB>
+__device__ __forceinline__ uint32_t ballot_sum(uint32_t x)
+{
+    uint32_t tot = 0;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) tot += (uint32_t)__popcll(__ballot((x >> b) & 1u)) << b;
+    return tot;
+}
+
 // State dword of the 4-cell group at (gi, gj); 0 (not burning) off the grid.
 template <bool ALIGNED>
 __device__ __forceinline__ uint32_t load_group(const uint8_t* __restrict__ env_src, int gi, int gj, int H,
@@ -280,7 +319,8 @@ __global__ __launch_bounds__(kWave) void stoch_step_kernel(
     uint32_t win[RT + 2];  // burning bits of the 6-cell window of each loaded row
 #pragma unroll
     for (int j = 0; j < RT + 2; ++j) {
-        uint32_t left = __shfl_up(s[j], 1, GX), right = __shfl_down(s[j], 1, GX);
+        // the segment's end lanes take the halo bytes instead
+        uint32_t left = from_lane_below(s[j]), right = from_lane_above(s[j]);
         if (tx == 0) left = hl[j] << 24;
         if (tx == GX - 1) right = hr[j];
         win[j] = row_window(left, s[j], right);
@@ -316,8 +356,15 @@ __global__ __launch_bounds__(kWave) void stoch_step_kernel(
     __syncthreads();  // lds_ew visible (one wave: no waiting on other waves)
 
     // -- 4. list front cells and draw groups across the wave
+    constexpr int kCellBits = bit_width(4 * RT), kGroupBits = bit_width(RT);
     uint32_t totals = 0, off = 0;
-    if (__any(my_groups != 0u)) off = wave_exclusive_scan(my_cells | (my_groups << 16), totals);
+    if (__any(my_groups != 0u)) {
+        uint32_t tc, tg;
+        const uint32_t oc = ballot_exclusive_scan<kCellBits>(my_cells, tc);
+        const uint32_t og = ballot_exclusive_scan<kGroupBits>(my_groups, tg);
+        off = oc | (og << 16);
+        totals = tc | (tg << 16);
+    }
     const uint32_t n_cells = totals & 0xFFFFu, n_groups = totals >> 16;
     const bool listed = n_cells <= (uint32_t)kCellCap && n_groups <= (uint32_t)kGroupCap;
     uint32_t slot[RT];  // per row: group index | first cell index << 16
@@ -437,12 +484,11 @@ __global__ __launch_bounds__(kWave) void stoch_step_kernel(
 
     // -- BURNING count of the env (and of the tile) after the step --
     if (counts_row || SP.burn_next) {
-#pragma unroll
-        for (int o2 = 32; o2 > 0; o2 >>= 1) cnt += __shfl_xor(cnt, o2);
+        const int tile_cnt = (int)ballot_sum<bit_width(4 * RT)>((uint32_t)cnt);
         if (lane == 0) {
-            if (counts_row && cnt) atomicAdd(counts_row + td.env, cnt);
+            if (counts_row && tile_cnt) atomicAdd(counts_row + td.env, tile_cnt);
             if (SP.burn_next) {
-                SP.burn_next[tile] = cnt;
+                SP.burn_next[tile] = tile_cnt;
                 SP.eq[tile] = 0;
             }
         }
