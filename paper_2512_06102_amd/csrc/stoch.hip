@@ -111,8 +111,21 @@ __device__ __forceinline__ uint32_t load_group(const uint8_t* __restrict__ env_s
     }
 }
 
+// Waves per SIMD the front-skipping kernels with up to 4 rows per lane are
+// compiled for: with per-env wind they fit 64 VGPRs without spilling, so 8
+// waves share each SIMD (7 at the compiler's own choice of 65), and with
+// per-cell wind 80 (6 waves instead of 5).  These plans wait on chains of
+// dependent loads, and the extra wave hides latency (6.6% faster on 1024
+// envs of 256x256).  The dense plan streams instead and runs slower when
+// capped, and 8 rows per lane would spill: both keep the compiler's choice.
+constexpr int step_waves_per_eu(bool wind_cell, int rt, bool skip)
+{
+    return (skip && rt <= 4) ? (wind_cell ? 6 : 8) : 1;
+}
+
 template <bool ALIGNED, bool WIND_CELL, int RT, bool SKIP>
-__global__ __launch_bounds__(kWave) void stoch_step_kernel(
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(step_waves_per_eu(WIND_CELL, RT, SKIP))))
+void stoch_step_kernel(
     const TileDesc* __restrict__ tiles, int32_t n_tiles, int32_t tiles_per_xcd,
     const EnvDev* __restrict__ envs, StaticFields F0, StepArgs A, const uint8_t* __restrict__ src,
     uint8_t* __restrict__ dst, const uint32_t* __restrict__ t_base, uint32_t step,
