@@ -224,12 +224,21 @@ __global__ __launch_bounds__(64) void rl_step_kernel(const EnvDev* __restrict__ 
         __syncthreads();
     }
 
+    // -- 2b. no BURNING cell after the drop: no cell can change (no front, no
+    //        draw; the fire model only spreads from burning cells)
+    uint32_t my_burn = 0;
+    for (int i = lane; i < n_dw; i += 64) {
+        const int r = small_div(i, WD, inv_wd);
+        my_burn |= burning_flags(sS[i + 2 * r + SW + 1]);
+    }
+    const bool quiet = !__any(my_burn != 0u);
+
     // -- 3. draws of the groups that need one; front cells listed across the
     //       wave and evaluated by all lanes together, so that their fuel and
     //       elevation loads overlap instead of queueing on their owners
     const uint2 key = make_uint2(A.key0, A.key1);
     uint32_t my_front = 0;
-    for (int i = lane; i < n_dw; i += 64) {
+    for (int i = lane; i < n_dw && !quiet; i += 64) {
         const int r = small_div(i, WD, inv_wd);
         const uint32_t* m = sS + i + 2 * r + SW + 1;
         const uint32_t burn = pack4(burning_flags(m[0]));
@@ -281,7 +290,7 @@ __global__ __launch_bounds__(64) void rl_step_kernel(const EnvDev* __restrict__ 
         uint32_t out = own;
         const uint32_t burn = pack4(burning_flags(own));
         const uint32_t flam = pack4(flammable_flags(own));
-        if (burn | flam) {
+        if (!quiet && (burn | flam)) {
             const uint32_t front = flam & near_burning(m, SW);
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
@@ -319,9 +328,11 @@ __global__ __launch_bounds__(64) void rl_step_kernel(const EnvDev* __restrict__ 
     }
     __syncthreads();  // the new state and the agent's position
 
-    // -- 6. the new state to HBM, the observation window from LDS
+    // -- 6. the new state to HBM (a quiet env without a drop is unchanged
+    //       there), the observation window from LDS
     uint32_t* dst = reinterpret_cast<uint32_t*>(states + base);
-    for (int i = lane; i < n_dw; i += 64) dst[i] = sN[i];
+    if (!quiet || drop >= 0)
+        for (int i = lane; i < n_dw; i += 64) dst[i] = sN[i];
     const int R = cfg.obs_radius, side = 2 * R + 1, n_obs = side * side;
     const float inv_side = 1.0f / (float)side;
     uint8_t* o = obs + (int64_t)e * n_obs;
