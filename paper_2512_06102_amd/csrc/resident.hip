@@ -84,7 +84,7 @@ __global__ __launch_bounds__(NT) void stoch_resident_kernel(
     extern __shared__ uint4 lds_dyn[];
     __shared__ float s_ew[kChunk][8];  // per-env wind exponents of the chunk's steps
     __shared__ int32_t s_act[kChunk];  // the chunk's drops
-    __shared__ uint32_t s_count[2];
+    __shared__ uint32_t s_count[3];    // BURNING cells after step k, in slot k % 3
     const int e = env_list ? env_list[blockIdx.x] : (int)blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const EnvDev ed = envs[e];
@@ -128,7 +128,7 @@ __global__ __launch_bounds__(NT) void stoch_resident_kernel(
             cur[f] = 0u;
             nxt[f] = 0u;
         }
-        if (tid < 2) s_count[tid] = 0u;
+        if (tid < 3) s_count[tid] = 0u;
         // a static per-env wind gives every step the same exponents
         if (!WIND_CELL && !F0.env_wind && tid < 8)
             s_ew[0][tid] = wind_exponent(tid, A.alpha_w1, A.alpha_w2, ed.V, ed.Vx, ed.Vy);
@@ -136,9 +136,10 @@ __global__ __launch_bounds__(NT) void stoch_resident_kernel(
     const uint2 key = make_uint2(A.key0, A.key1);
     const bool ew_series = !WIND_CELL && F0.env_wind != nullptr;
 
+    bool stopped = false;  // left the step loop early: every remaining step is a no-op
     for (int32_t k = 0; k < T; ++k) {
         const uint32_t t = t0 + (uint32_t)k;
-        const int par = k & 1, kc = k % kChunk;
+        const int slot = k % 3, kc = k % kChunk;
         StaticFields F = F0;
         if (F0.wind_stride != 0) F.wind = F0.wind + (int64_t)t * F0.wind_stride;
         if (kc == 0 && (actions || ew_series)) {
@@ -155,9 +156,21 @@ __global__ __launch_bounds__(NT) void stoch_resident_kernel(
                 }
         }
         __syncthreads();  // F_t complete, the chunk staged, the last step's count summed
-        if (tid == 0 && k > 0) {
-            if (counts) counts[(int64_t)(k - 1) * n_env + e] = (int32_t)s_count[par ^ 1];
-            s_count[par ^ 1] = 0u;  // next added to in step k + 1, after its barrier
+        // the last step's count: read by every thread in this barrier phase;
+        // the slot step k + 1 adds to (step k - 2's, read in the last phase)
+        // is cleared meanwhile
+        const uint32_t prev = s_count[(slot + 2) % 3];
+        if (tid == 0) {
+            if (counts && k > 0) counts[(int64_t)(k - 1) * n_env + e] = (int32_t)prev;
+            s_count[(slot + 1) % 3] = 0u;
+        }
+        // F_t holds no BURNING cell: no cell can ignite or burn out any more,
+        // only the drops can still change it (the counts of the remaining
+        // steps stay 0 as cleared before the launch)
+        const bool quiet = k > 0 && prev == 0u;
+        if (quiet && !actions) {
+            stopped = true;
+            break;
         }
         const float* ew = s_ew[ew_series ? kc : 0];
 
@@ -178,6 +191,7 @@ __global__ __launch_bounds__(NT) void stoch_resident_kernel(
                 __syncthreads();
             }
         }
+        if (quiet) continue;  // F_{t+1} is F_t after the drop: cur keeps it
 
         // -- this wave's dwords: draws, the burning cells' transitions into
         //    F_{t+1} (front cells left FLAMMABLE there), the front list
@@ -257,13 +271,13 @@ __global__ __launch_bounds__(NT) void stoch_resident_kernel(
             }
         }
         cnt = ballot_sum(cnt);
-        if (lane == 0 && cnt) atomicAdd(&s_count[par], cnt);
+        if (lane == 0 && cnt) atomicAdd(&s_count[slot], cnt);
         uint32_t* tmp = cur;
         cur = nxt;
         nxt = tmp;
     }
     __syncthreads();
-    if (tid == 0 && counts) counts[(int64_t)(T - 1) * n_env + e] = (int32_t)s_count[(T - 1) & 1];
+    if (tid == 0 && counts && !stopped) counts[(int64_t)(T - 1) * n_env + e] = (int32_t)s_count[(T - 1) % 3];
     uint32_t* dst = reinterpret_cast<uint32_t*>(dst_states + base);
     for (int i = tid; i < n_dw; i += NT) {
         const int r = small_div(i, WD, inv_wd);

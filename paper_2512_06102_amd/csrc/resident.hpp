@@ -33,6 +33,8 @@ hipError_t resident_set_lds_limit(int bytes);
 // launch serves any starting step), by workgroups of `threads` lanes (64,
 // 256, 512 or 1024); actions and counts point at the rows of the first step
 // (n_env entries per step, indexed by the global env index) or are NULL.
+// The count rows must hold 0 on entry: an env whose fire is out stops
+// stepping (applying only the remaining drops) and leaves its later rows.
 hipError_t launch_stoch_resident(hipStream_t s, const EnvDev* envs, int32_t n_env, const int32_t* env_list,
                                  int32_t n_list, const StaticFields& F, const StepArgs& A, const ResidentShape& shape,
                                  int threads, const uint8_t* src, uint8_t* dst, const uint32_t* t_base,

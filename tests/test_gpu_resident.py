@@ -51,6 +51,27 @@ def test_paper_setting_64x64_with_drops(threads, mode, radius):
 
 
 @pytest.mark.parametrize("threads", THREADS)
+def test_fires_burn_out_without_drops(threads):
+    """The paper setting's batch with no drops: every fire is out well before
+    step 200, after which an env stops stepping and leaves its count rows at
+    0; 200 steps in one call and as 120 + 80 (the second call starts after
+    every fire is out), counts after every step and the final states equal
+    the oracle's."""
+    batch = firegen.landscape_batch(7, [(64, 64)] * 64)
+    params = firegen.Params(veg=_veg(7))
+    T = 200
+    ref = oracle.Sim(batch, params, seed=0)
+    want = ref.step(T, counts=True, threads=8)
+    last = max(int(np.flatnonzero(want[:, e]).max(initial=-1)) for e in range(batch.n_env))
+    assert 0 < last < 120, last  # every fire is out before the split
+    for split in ((T,), (120, 80)):
+        sim = fs.FireSim.from_batch(batch, params, seed=0)
+        sim.set_plan(resident=threads, graph=1)
+        got = np.concatenate([sim.step(n, counts=True).cpu().numpy() for n in split])
+        _check(sim, ref, got, want, (threads, split))
+
+
+@pytest.mark.parametrize("threads", THREADS)
 def test_many_20x20_envs_with_drops(threads):
     """1024 envs of 20 x 20 (the RL layer's size), water drops, 60 steps."""
     batch = firegen.landscape_batch(62, [(20, 20)] * 1024)
