@@ -374,7 +374,7 @@ def bench_paper_config(args, torch, fs, firegen):
                    "its literal reading is 2.5^16 = 2.3e6 env-steps/s")
     # the paper's throughput-versus-batch curve: 200 steps of n envs of 64 x 64, autotuned each
     sweep = []
-    for n in (1, 4, 16, 64, 256, 1024, 4096):
+    for n in (1, 4, 16, 64, 256, 1024, 4096) if args.paper_sweep else ():
         b = firegen.landscape_batch(7, [(64, 64)] * n)
         s2 = fs.FireSim.from_batch(b, params, seed=0)
         i2 = s2.states.clone()
@@ -387,7 +387,8 @@ def bench_paper_config(args, torch, fs, firegen):
         log("[bench] paper sweep %4d envs of 64x64: %s %.3f ms per 200 steps, %.3e env-steps/s"
             % (n, {k: p2[k] for k in keys if p2[k]}, ms2, n * T / (ms2 / 1e3)))
         del s2, i2, b
-    out["sweep"] = sweep
+    if sweep:
+        out["sweep"] = sweep
     log("[bench] paper setting 64 x 64^2: dense %.3f ms, autotuned %s %.3f ms per 200 steps"
         % (out["dense"]["ms_per_200_steps"], out["autotuned"]["plan"], ms))
     return out
@@ -681,6 +682,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the paper-setting, RL, uneven and large objects")
     ap.add_argument("--extras", default="paper,rl,uneven,large",
                     help="comma-separated subset of the extra objects to run")
+    ap.add_argument("--paper-sweep", type=int, default=1,
+                    help="0: time the paper setting without the 1-4096-env sweep (shorter profiles)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (HBM counter calibration)")
