@@ -80,13 +80,17 @@ struct StepLaunch {
 
 // Sparse scheduling of the step: a tile whose cells and neighbouring tiles
 // held no burning cell after the previous step (and that no drop touches) is
-// left as it is.  burn_prev / burn_next: burning cells per tile before and
-// after the step; eq[tile] != 0 when both state buffers hold the same content
-// on the tile; nbr: the 8 neighbouring tiles (-1 off the env).  burn_next ==
-// nullptr disables it; all_active forces every tile to run (first step of a
-// call, when nothing is known about the caller's states).
+// left as it is.  burn_prev / burn_next: per-tile marks (nonzero: run the
+// step) set by the tiles that held a burning cell after the previous step /
+// this step, on themselves and their neighbours; each tile clears its mark in
+// burn_prev once read, so the two arrays alternate.  A stale mark only makes
+// a tile run, which is always exact.  eq[tile] != 0 when both state buffers
+// hold the same content on the tile; nbr: the 8 neighbouring tiles (-1 off
+// the env).  burn_next == nullptr disables it; all_active forces every tile
+// to run (first step of a call, when nothing is known about the caller's
+// states).
 struct SparseArgs {
-    const int32_t* burn_prev;
+    int32_t* burn_prev;
     int32_t* burn_next;
     int32_t* eq;
     const int32_t* nbr;

@@ -140,61 +140,62 @@ void stoch_step_kernel(
     const int b = blockIdx.x;
     const int tile = (b & 7) * tiles_per_xcd + (b >> 3);
     if (tile >= n_tiles) return;
+    const int lane = threadIdx.x;
     const TileDesc td = tiles[tile];
-    const EnvDev ed = envs[td.env];
-    const int H = ed.H, W = ed.W;
+    const EnvDev ed = envs[td.env];  // issued early; an inactive tile does not wait for it
     const int gx_log = td.width == 256 ? 6 : (td.width == 128 ? 5 : (td.width == 64 ? 4 : (td.width == 32 ? 3 : 2)));
     const int GX = 1 << gx_log;  // lanes per row segment
-    const int lane = threadIdx.x;
     const int tx = lane & (GX - 1), ty = lane >> gx_log;
     const int row0 = td.r0 + ty * RT;  // first own row
     const int gj0 = td.c0 + 4 * tx;    // first own column
+
+    // -- 0. sparse scheduling: a tile runs when it or one of its 8 neighbours
+    //       held a burning cell after the previous step (those tiles marked
+    //       it), when a drop may reach it, or on the first step of a call;
+    //       an inactive tile keeps its cells.  Each tile clears its own mark
+    //       once read, so the array takes the marks of the step after next.
+    if (SP.burn_next) {
+        bool active = SP.all_active != 0 || SP.burn_prev[tile] != 0;
+        if (lane == 0) SP.burn_prev[tile] = 0;
+        const int32_t a0 = (!active && actions_row) ? actions_row[td.env] : -1;
+        if (a0 >= 0) {
+            // the drop square reaches the tile or its one-cell ring (a drop
+            // off the grid changes nothing: running the tile is still exact)
+            const int ar = (a0 >> 16) & 0x7FFF, ac = a0 & 0xFFFF;
+            const int R = A.drop_radius, TH = (kWave >> gx_log) * RT;
+            active = ar + R >= td.r0 - 1 && ar - R <= td.r0 + TH && ac + R >= td.c0 - 1 &&
+                     ac - R <= td.c0 + td.width;
+        }
+        if (!active) {
+            if (SP.eq[tile] == 0) {  // the other buffer is stale on this tile: copy it over
+                const EnvDev& ed0 = ed;
+                const int H0 = ed0.H, W0 = ed0.W;
+#pragma unroll
+                for (int m = 0; m < RT; ++m) {
+                    const int gi = row0 + m;
+                    if (!(gi < H0 && gj0 < W0)) continue;
+                    const int64_t c0 = ed0.offset + (int64_t)gi * W0 + gj0;
+                    if constexpr (ALIGNED) {
+                        *reinterpret_cast<uint32_t*>(dst + c0) = *reinterpret_cast<const uint32_t*>(src + c0);
+                    } else {
+#pragma unroll
+                        for (int c = 0; c < 4; ++c)
+                            if (gj0 + c < W0) dst[c0 + c] = src[c0 + c];
+                    }
+                }
+            }
+            if (lane == 0) SP.eq[tile] = 1;
+            return;
+        }
+    }
+
+    const int H = ed.H, W = ed.W;
     const uint32_t t = *t_base + step;
     StaticFields F = F0;
     if (F0.wind_stride != 0) F.wind = F0.wind + (int64_t)t * F0.wind_stride;
     const int64_t base = ed.offset;
     const uint8_t* env_src = src + base;
     const uint2 key = make_uint2(A.key0, A.key1);
-
-    // -- 0. sparse scheduling: an inactive tile keeps its cells
-    if (SP.burn_next) {
-        const int TH = (kWave >> gx_log) * RT;
-        bool active = SP.all_active != 0 || SP.burn_prev[tile] > 0;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int nb = SP.nbr[8 * tile + i];
-            active = active || (nb >= 0 && SP.burn_prev[nb] > 0);
-        }
-        const int32_t a0 = actions_row ? actions_row[td.env] : -1;
-        if (!active && a0 >= 0) {
-            const int ar = (a0 >> 16) & 0x7FFF, ac = a0 & 0xFFFF;
-            const int R = A.drop_radius;
-            active = ar < H && ac < W && ar + R >= td.r0 - 1 && ar - R <= td.r0 + TH &&
-                     ac + R >= td.c0 - 1 && ac - R <= td.c0 + td.width;
-        }
-        if (!active) {
-            if (SP.eq[tile] == 0) {  // the other buffer is stale on this tile: copy it over
-#pragma unroll
-                for (int m = 0; m < RT; ++m) {
-                    const int gi = row0 + m;
-                    if (!(gi < H && gj0 < W)) continue;
-                    const int64_t c0 = base + (int64_t)gi * W + gj0;
-                    if constexpr (ALIGNED) {
-                        *reinterpret_cast<uint32_t*>(dst + c0) = *reinterpret_cast<const uint32_t*>(src + c0);
-                    } else {
-#pragma unroll
-                        for (int c = 0; c < 4; ++c)
-                            if (gj0 + c < W) dst[c0 + c] = src[c0 + c];
-                    }
-                }
-            }
-            if (lane == 0) {
-                SP.eq[tile] = 1;
-                SP.burn_next[tile] = 0;
-            }
-            return;
-        }
-    }
 
     // -- 1. loads: RT own dwords plus the one above and below; halo bytes at
     //       the segment ends; fuel and elevation of own cells (dense plan)
@@ -319,10 +320,7 @@ void stoch_step_kernel(
                         if (gj0 + c < W) o[c] = (uint8_t)(s[m + 1] >> (8 * c));
                 }
             }
-            if (SP.burn_next && lane == 0) {
-                SP.burn_next[tile] = 0;
-                SP.eq[tile] = 0;
-            }
+            if (SP.burn_next && lane == 0) SP.eq[tile] = 0;
             return;
         }
     }
@@ -500,10 +498,13 @@ void stoch_step_kernel(
         const int tile_cnt = (int)ballot_sum<bit_width(4 * RT)>((uint32_t)cnt);
         if (lane == 0) {
             if (counts_row && tile_cnt) atomicAdd(counts_row + td.env, tile_cnt);
-            if (SP.burn_next) {
-                SP.burn_next[tile] = tile_cnt;
-                SP.eq[tile] = 0;
-            }
+            if (SP.burn_next) SP.eq[tile] = 0;
+        }
+        // a tile that still burns marks itself and its 8 neighbours to run
+        // the next step
+        if (SP.burn_next && tile_cnt && lane < 9) {
+            const int nb = lane == 0 ? tile : SP.nbr[8 * tile + lane - 1];
+            if (nb >= 0) SP.burn_next[nb] = 1;
         }
     }
 }
