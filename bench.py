@@ -429,31 +429,37 @@ def bench_uneven(args, torch, fs, firegen):
     # both tuners probe 150 steps: long enough for the fires to reach the sizes
     # that decide between plans (a 50-step probe picks 256-wide tiles for the
     # 512^2 envs, which lose later in the run)
-    sim.autotune(T_probe=150, allow_skip=True, allow_sparse=True)
-    best = sim.plan()
     keys = ("tile_rows", "tile_width", "temporal", "skip_static", "sparse", "resident")
+    if args.tune:
+        sim.autotune(T_probe=150, allow_skip=True, allow_sparse=True)
+        best = sim.plan()
+    else:  # the library's default tiled plan, which the tuner picks here (short profiles)
+        best = dict(tile_rows=4, tile_width=64, temporal=1, skip_static=1, sparse=1, resident=0)
     sim.set_plan(**{k: best[k] for k in keys}, graph=1)
     run(1)
     torch.cuda.synchronize()
     with StepTimer(torch, stream) as tm:
         run(2)
     ms2 = tm.ms() / 2
-    out["autotuned"] = {"plan": {k: best[k] for k in keys}, "ms_per_pass": round(ms2, 3),
-                        "value": cells * T / (ms2 / 1e3)}
-    # one plan per size class (sides 64 / 128 / 256 / 512), each class tuned alone
-    sim.states.copy_(init)
-    sim.t = 0
-    cls = sim.autotune_classes(T_probe=150, allow_skip=True, allow_sparse=True)
-    run(1)
-    torch.cuda.synchronize()
-    with StepTimer(torch, stream) as tm:
-        run(2)
-    ms3 = tm.ms() / 2
-    out["per_class"] = {"classes": [{"size_class": c["size_class"], "n_env": c["n_env"], "plan": c["plan"],
-                                     "tuned_ms_per_step": round(c["ms_per_step"], 4)} for c in cls],
-                        "ms_per_pass": round(ms3, 3), "value": cells * T / (ms3 / 1e3)}
-    log("[bench] uneven: dense %.2f ms (%.3e cell-updates/s, %.0f GB/s at 10 B), autotuned %s %.2f ms, "
-        "per-class %.2f ms" % (ms, rate, STOCH_BYTES_PER_CELL * rate / 1e9, out["autotuned"]["plan"], ms2, ms3))
+    tag = "autotuned" if args.tune else "default_plan"
+    out[tag] = {"plan": {k: best[k] for k in keys}, "ms_per_pass": round(ms2, 3),
+                "value": cells * T / (ms2 / 1e3)}
+    ms3 = float("nan")
+    if args.tune:
+        # one plan per size class (sides 64 / 128 / 256 / 512), each class tuned alone
+        sim.states.copy_(init)
+        sim.t = 0
+        cls = sim.autotune_classes(T_probe=150, allow_skip=True, allow_sparse=True)
+        run(1)
+        torch.cuda.synchronize()
+        with StepTimer(torch, stream) as tm:
+            run(2)
+        ms3 = tm.ms() / 2
+        out["per_class"] = {"classes": [{"size_class": c["size_class"], "n_env": c["n_env"], "plan": c["plan"],
+                                         "tuned_ms_per_step": round(c["ms_per_step"], 4)} for c in cls],
+                            "ms_per_pass": round(ms3, 3), "value": cells * T / (ms3 / 1e3)}
+    log("[bench] uneven: dense %.2f ms (%.3e cell-updates/s, %.0f GB/s at 10 B), %s %s %.2f ms, "
+        "per-class %.2f ms" % (ms, rate, STOCH_BYTES_PER_CELL * rate / 1e9, tag, out[tag]["plan"], ms2, ms3))
     return out
 
 
@@ -524,24 +530,25 @@ def bench_large(args, torch, fs, firegen):
                     "hbm_frac_at_22B": round(bpc * rate / 1e9 / HBM_PEAK_GBS, 4)}
     sim.states.copy_(init)
     sim.t = 0
-    # both tuners probe 150 steps: long enough for the fires to reach the sizes
-    # that decide between plans (a 50-step probe picks 256-wide tiles for the
-    # 512^2 envs, which lose later in the run)
-    # the whole run: the fires grow for most of the 1000 steps, and a short probe
-    # from the initial fires ranks the plans by their cost on small fronts
-    sim.autotune(T_probe=T, allow_skip=True, allow_sparse=True)
-    best = sim.plan()
     keys = ("tile_rows", "tile_width", "temporal", "skip_static", "sparse", "resident")
+    if args.tune:
+        # the whole run: the fires grow for most of the 1000 steps, and a short probe
+        # from the initial fires ranks the plans by their cost on small fronts
+        sim.autotune(T_probe=T, allow_skip=True, allow_sparse=True)
+        best = sim.plan()
+    else:  # the library's default tiled plan, which the tuner picks here (short profiles)
+        best = dict(tile_rows=4, tile_width=64, temporal=1, skip_static=1, sparse=1, resident=0)
     sim.set_plan(**{k: best[k] for k in keys}, graph=1)
     run()
     torch.cuda.synchronize()
     with StepTimer(torch, stream) as tm:
         run()
     ms2 = tm.ms()
-    out["autotuned"] = {"plan": {k: best[k] for k in keys}, "ms_per_pass": round(ms2, 3),
-                        "value": cells * T / (ms2 / 1e3)}
-    log("[bench] large: dense %.2f ms (%.3e cell-updates/s, %.0f GB/s at 22 B), autotuned %s %.2f ms"
-        % (ms, rate, bpc * rate / 1e9, out["autotuned"]["plan"], ms2))
+    tag = "autotuned" if args.tune else "default_plan"
+    out[tag] = {"plan": {k: best[k] for k in keys}, "ms_per_pass": round(ms2, 3),
+                "value": cells * T / (ms2 / 1e3)}
+    log("[bench] large: dense %.2f ms (%.3e cell-updates/s, %.0f GB/s at 22 B), %s %s %.2f ms"
+        % (ms, rate, bpc * rate / 1e9, tag, out[tag]["plan"], ms2))
     return out
 
 
@@ -682,6 +689,9 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the paper-setting, RL, uneven and large objects")
     ap.add_argument("--extras", default="paper,rl,uneven,large",
                     help="comma-separated subset of the extra objects to run")
+    ap.add_argument("--tune", type=int, default=1,
+                    help="0: time the uneven and large workloads under the default tiled plan instead of "
+                         "autotuning them (short profiles)")
     ap.add_argument("--paper-sweep", type=int, default=1,
                     help="0: time the paper setting without the 1-4096-env sweep (shorter profiles)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
