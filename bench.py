@@ -699,7 +699,7 @@ def main():
                     help="also run a 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(envs shard across GPUs with no communication; see the design notes)",
               file=sys.stderr)
         sys.exit(2)

@@ -357,7 +357,7 @@ typedef struct {
 /* Set the plan of one size class.  The first call splits the batch into its
  * classes, each starting from the handle-wide plan.  SIM_EINVAL if the batch
  * has no env in the class or the plan does not suit its envs (as
- * sim_set_plan, judged on the class's envs alone: a class of small envs can
+ * sim_set_plan, checked against the class's envs alone: a class of small envs can
  * take a resident plan that the whole batch cannot). */
 int sim_set_class_plan(sim_handle* h, int32_t size_class, const sim_plan* plan);
 
